@@ -1,0 +1,244 @@
+"""Seeded synthetic inputs shaped like the paper's models (input generation only).
+
+This module draws media, sources and frequencies; it holds none of the LS
+method's arithmetic (no Green's tensor, strain stencil, contrast product or
+background folding), so both the HIP path and the CPU oracle take its arrays
+as plain inputs.  All randomness comes from ``numpy.random.default_rng(seed)``.
+
+Recipes (sizes, value ranges and structure mirror the paper's experiments):
+
+* ``config1`` - 16^3, h = 10 m, isotropic background vp 3000, vs 1730, rho
+  2400; sphere of radius 40 m at the grid centre with +10 % on the isotropic
+  stiffness and +5 % density; 15 Hz; explosion M = diag(1,1,1) at cell (4,8,8).
+* ``config2`` - 64^3, h = 10 m, VTI background from Thomsen parameters
+  (vp0 3000, vs0 1700, eps 0.1, delta 0.05, gamma 0.08, rho 2400), three
+  horizontal layers with uniform +-15 % on C11, C33, C44, C66, C13 (seed 1),
+  20 Hz, double couple 30/60/90 at the centre (the layered VTI structure of the
+  paper's Model 2).
+* ``config3`` - 128^3, h = 8 m: config 2's VTI tilted 30 deg about y and
+  rotated 45 deg about z (TTI), times (1 + 0.08 g_IJ(x)) on all 21 stiffnesses
+  and rho = 2400 (1 + 0.04 g_rho(x)), g Gaussian random fields with covariance
+  exp(-r^2/L^2), L = 40 m (seed 2), over an isotropic background (3000, 1700,
+  2400); 6 elementary moment tensors x 8 frequencies 5-40 Hz at the centre.
+  It stands in for the paper's Hess/SEG model, which is not available here.
+* ``config4`` - 96^3 ellipsoid anomaly in config 2's VTI background.
+
+Every function also takes ``n`` so the same recipe can be drawn at small sizes
+for parity tests.
+"""
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+UPPER21 = tuple((I, J) for I in range(6) for J in range(I, 6))
+VOIGT_PAIRS = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
+
+
+@dataclass
+class Model:
+    shape: tuple            # (N1, N2, N3) = (x, y, z)
+    h: float
+    C0: np.ndarray          # 6x6 background stiffness (Pa)
+    rho0: float
+    dc21: np.ndarray        # [21, N3, N2, N1] contrast relative to C0 (Pa)
+    drho: np.ndarray        # [N3, N2, N1] density contrast (kg/m^3)
+    freqs: list             # Hz
+    sources: list = field(default_factory=list)   # [(M Voigt 11,22,33,23,13,12, (i, j, k))]
+    tol: float = 1e-6
+    name: str = ""
+
+    @property
+    def omegas(self):
+        return [2.0 * np.pi * f for f in self.freqs]
+
+
+def iso_C(vp, vs, rho):
+    c11, c44 = rho * vp * vp, rho * vs * vs
+    C = np.zeros((6, 6))
+    C[:3, :3] = c11 - 2.0 * c44
+    for I in range(3):
+        C[I, I] = c11
+        C[I + 3, I + 3] = c44
+    return C
+
+
+def vti_from_thomsen(vp0, vs0, eps, delta, gamma, rho):
+    """Thomsen (1986) parameters -> VTI Voigt stiffness (symmetry axis z)."""
+    c33 = rho * vp0 * vp0
+    c44 = rho * vs0 * vs0
+    c11 = c33 * (1.0 + 2.0 * eps)
+    c66 = c44 * (1.0 + 2.0 * gamma)
+    c13 = np.sqrt(2.0 * delta * c33 * (c33 - c44) + (c33 - c44) ** 2) - c44
+    return vti_C(c11, c33, c44, c66, c13)
+
+
+def vti_C(c11, c33, c44, c66, c13):
+    C = np.zeros((6, 6))
+    C[0, 0] = C[1, 1] = c11
+    C[2, 2] = c33
+    C[3, 3] = C[4, 4] = c44
+    C[5, 5] = c66
+    C[0, 1] = C[1, 0] = c11 - 2.0 * c66
+    C[0, 2] = C[2, 0] = C[1, 2] = C[2, 1] = c13
+    return C
+
+
+def pack21(C66):
+    C66 = np.asarray(C66)
+    return np.stack([C66[I, J] for (I, J) in UPPER21])
+
+
+def rotate_voigt(C, R):
+    """Rotate a Voigt stiffness by the 3x3 rotation R: c'_ijkl = R_ip R_jq R_kr R_ls c_pqrs."""
+    c = np.zeros((3, 3, 3, 3))
+    for I, (i, j) in enumerate(VOIGT_PAIRS):
+        for J, (k, l) in enumerate(VOIGT_PAIRS):
+            for (a, b) in {(i, j), (j, i)}:
+                for (p, q) in {(k, l), (l, k)}:
+                    c[a, b, p, q] = C[I, J]
+    cr = np.einsum('ip,jq,kr,ls,pqrs->ijkl', R, R, R, R, c)
+    out = np.zeros((6, 6))
+    for I, (i, j) in enumerate(VOIGT_PAIRS):
+        for J, (k, l) in enumerate(VOIGT_PAIRS):
+            out[I, J] = cr[i, j, k, l]
+    return out
+
+
+def rot_y(deg):
+    t = np.deg2rad(deg)
+    return np.array([[np.cos(t), 0, np.sin(t)], [0, 1, 0], [-np.sin(t), 0, np.cos(t)]])
+
+
+def rot_z(deg):
+    t = np.deg2rad(deg)
+    return np.array([[np.cos(t), -np.sin(t), 0], [np.sin(t), np.cos(t), 0], [0, 0, 1]])
+
+
+def double_couple(strike, dip, rake, m0=1.0):
+    """Aki-Richards double couple (x north, y east, z down) -> Voigt (11,22,33,23,13,12)."""
+    f, d, l = np.deg2rad([strike, dip, rake])
+    m11 = -(np.sin(d) * np.cos(l) * np.sin(2 * f) + np.sin(2 * d) * np.sin(l) * np.sin(f) ** 2)
+    m22 = np.sin(d) * np.cos(l) * np.sin(2 * f) - np.sin(2 * d) * np.sin(l) * np.cos(f) ** 2
+    m33 = np.sin(2 * d) * np.sin(l)
+    m12 = np.sin(d) * np.cos(l) * np.cos(2 * f) + 0.5 * np.sin(2 * d) * np.sin(l) * np.sin(2 * f)
+    m13 = -(np.cos(d) * np.cos(l) * np.cos(f) + np.cos(2 * d) * np.sin(l) * np.sin(f))
+    m23 = -(np.cos(d) * np.cos(l) * np.sin(f) - np.cos(2 * d) * np.sin(l) * np.cos(f))
+    return m0 * np.array([m11, m22, m33, m23, m13, m12])
+
+
+EXPLOSION = np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0])
+
+
+def gaussian_random_fields(rng, count, n, h, corr_len):
+    """count fields on an n^3 grid, covariance exp(-r^2/L^2), zero mean and unit std each."""
+    k = 2.0 * np.pi * np.fft.fftfreq(n, d=h)
+    kz, ky, kx = np.meshgrid(k, k, k, indexing='ij')
+    amp = np.exp(-(kx**2 + ky**2 + kz**2) * corr_len**2 / 8.0)   # sqrt of the spectrum exp(-k^2 L^2/4)
+    out = np.empty((count, n, n, n))
+    for c in range(count):
+        w = rng.standard_normal((n, n, n))
+        g = np.fft.ifftn(np.fft.fftn(w) * amp).real
+        g -= g.mean()
+        out[c] = g / g.std()
+    return out
+
+
+def _centre(n):
+    return 0.5 * (n - 1)
+
+
+def config1(n=16):
+    h = 10.0
+    rho0 = 2400.0
+    C0 = iso_C(3000.0, 1730.0, rho0)
+    z, y, x = np.meshgrid(*(np.arange(n),) * 3, indexing='ij')
+    c = _centre(n)
+    inside = ((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2) * h * h <= 40.0 ** 2
+    dc = np.zeros((21, n, n, n))
+    d21 = pack21(0.1 * C0)
+    dc[:, inside] = d21[:, None]
+    drho = np.where(inside, 0.05 * rho0, 0.0)
+    src = (4 * n // 16, 8 * n // 16, 8 * n // 16)
+    return Model((n, n, n), h, C0, rho0, dc, drho, [15.0], [(EXPLOSION.copy(), src)], 1e-8, "config1")
+
+
+VTI_CFG2 = dict(vp0=3000.0, vs0=1700.0, eps=0.1, delta=0.05, gamma=0.08, rho=2400.0)
+
+
+def config2(n=64, seed=1):
+    h = 10.0
+    rho0 = 2400.0
+    C0 = vti_from_thomsen(**VTI_CFG2)
+    rng = np.random.default_rng(seed)
+    base = np.array([C0[0, 0], C0[2, 2], C0[3, 3], C0[5, 5], C0[0, 2]])
+    bounds = [0, n // 3, 2 * n // 3, n]
+    dc = np.zeros((21, n, n, n))
+    for layer in range(3):
+        p = base * (1.0 + rng.uniform(-0.15, 0.15, size=5))
+        dC = vti_C(*p) - C0
+        dc[:, bounds[layer]:bounds[layer + 1]] = pack21(dC)[:, None, None, None]
+    drho = np.zeros((n, n, n))
+    m = n // 2
+    return Model((n, n, n), h, C0, rho0, dc, drho, [20.0], [(double_couple(30, 60, 90), (m, m, m))],
+                 1e-6, "config2")
+
+
+def tti_cfg3():
+    C = vti_from_thomsen(**VTI_CFG2)
+    return rotate_voigt(C, rot_z(45.0) @ rot_y(30.0))
+
+
+def config3(n=128, seed=2, h=8.0, freqs=(5, 10, 15, 20, 25, 30, 35, 40)):
+    rho0 = 2400.0
+    C0 = iso_C(3000.0, 1700.0, rho0)
+    Ct = tti_cfg3()
+    rng = np.random.default_rng(seed)
+    g = gaussian_random_fields(rng, 22, n, h, 40.0)
+    ct21 = pack21(Ct)
+    dc = ct21[:, None, None, None] * (1.0 + 0.08 * g[:21]) - pack21(C0)[:, None, None, None]
+    drho = rho0 * 0.04 * g[21]
+    m = n // 2
+    sources = [(np.eye(6)[J], (m, m, m)) for J in range(6)]
+    return Model((n, n, n), h, C0, rho0, dc, drho, list(map(float, freqs)), sources, 1e-6, "config3")
+
+
+def config4(n=96):
+    h = 10.0
+    rho0 = 2400.0
+    C0 = vti_from_thomsen(**VTI_CFG2)
+    z, y, x = np.meshgrid(*(np.arange(n),) * 3, indexing='ij')
+    c = _centre(n)
+    inside = (((x - c) * h / 120.0) ** 2 + ((y - c) * h / 80.0) ** 2 + ((z - c) * h / 60.0) ** 2) <= 1.0
+    dc = np.zeros((21, n, n, n))
+    dC = np.zeros((6, 6))
+    dC[2, 2] = 0.12 * C0[2, 2]
+    dc[:, inside] = pack21(dC)[:, None]
+    drho = np.where(inside, -0.08 * rho0, 0.0)
+    zs = 60 * n // 96
+    srcs = [(EXPLOSION.copy(), (32 * n // 96, 48 * n // 96, zs)),
+            (double_couple(30, 60, 90), (48 * n // 96, 48 * n // 96, zs)),
+            (double_couple(0, 90, 0), (64 * n // 96, 48 * n // 96, zs))]
+    return Model((n, n, n), h, C0, rho0, dc, drho, [8.0, 16.0, 24.0, 32.0], srcs, 1e-6, "config4")
+
+
+def random_field(shape, seed, complex_=True):
+    """Seeded standard-normal test field [3, N3, N2, N1] (complex by default)."""
+    rng = np.random.default_rng(seed)
+    n1, n2, n3 = shape
+    re = rng.standard_normal((3, n3, n2, n1))
+    if not complex_:
+        return re
+    return re + 1j * rng.standard_normal((3, n3, n2, n1))
+
+
+def random_medium(shape, seed, rel=0.1, h=10.0, aniso_background=False):
+    """Small general-anisotropic test medium: every one of the 21 contrast values per cell drawn at random."""
+    rng = np.random.default_rng(seed)
+    n1, n2, n3 = shape
+    rho0 = 2400.0
+    C0 = vti_from_thomsen(**VTI_CFG2) if aniso_background else iso_C(3000.0, 1730.0, rho0)
+    scale = np.abs(pack21(C0)).max()
+    dc = rel * scale * rng.uniform(-1.0, 1.0, size=(21, n3, n2, n1))
+    drho = rel * rho0 * rng.uniform(-1.0, 1.0, size=(n3, n2, n1))
+    return Model(tuple(shape), h, C0, rho0, dc, drho, [15.0], [], 1e-8, "random")
