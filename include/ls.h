@@ -1,0 +1,161 @@
+/*
+ * ls.h - C ABI of the MI355X (gfx950) Lippmann-Schwinger (LS) displacement solver.
+ *
+ * The library evaluates and solves the frequency-domain volume integral equation of
+ * Shekhar, Jakobsen, Iversen, Berre and Radu (arXiv 2301.12836) for the particle
+ * displacement u in a heterogeneous anisotropic elastic medium:
+ *
+ *     A u = u0,   A = I - Gconv B,   B = -E^T dC E + w^2 drho            (Eq 19-21)
+ *
+ * with E the finite-difference Voigt strain of Eq 17-18 (central inside, one-sided
+ * first-order on the model boundary), dC the per-cell 6x6 stiffness contrast and drho
+ * the density contrast (Eq 2-3, 11-12), Gconv the linear convolution with h^3 times the
+ * isotropic background Green's tensor of Eq 7 / Appendix A (the r = 0 cell takes the
+ * average over the sphere of volume h^3), evaluated with zero-padded 3-D FFTs, and u0
+ * the incident field of a moment tensor source (Eq 13-16): u0 = e^{i w t0} Gconv E^T (M delta_s)/h^3.
+ * The system is solved with BiCGSTAB to the relative residual e = ||u0 - A u|| / ||u0||
+ * of Eq 22.
+ *
+ * Conventions shared by every call
+ *   - Grid: n[0] = N1 (x), n[1] = N2 (y), n[2] = N3 (z) cells, spacing h (m); cell
+ *     (i, j, k) sits at (i h, j h, k h).  Each n[a] must be in [2, 256].
+ *   - Field arrays are component-major, x fastest: u[c][N3][N2][N1] for c = x, y, z,
+ *     complex interleaved (re, im): "c128" = two doubles, "c64" = two floats.  A batch
+ *     of R fields is R such arrays back to back.
+ *   - Contrast: dC[21][N3][N2][N1] doubles, the Voigt upper triangle of each cell's 6x6
+ *     in row order 11,12,13,14,15,16,22,...,26,33,...,66 (Voigt 1..6 = 11,22,33,23,13,12);
+ *     drho[N3][N2][N1] doubles.  Units Pa and kg/m^3.
+ *   - Moment tensor: M[6] in Voigt order (M11, M22, M33, M23, M13, M12), N m.
+ *   - Every device pointer is caller-owned HIP device memory; the library reads or writes
+ *     it on the context's stream and never frees it.  Calls are stream-ordered and return
+ *     without synchronising unless stated.  A context is not thread-safe; use one context
+ *     per host thread / stream.
+ *   - Return codes: LS_OK (0) or a negative LS_ERR_*; ls_last_error() gives a message
+ *     (thread-local).  No C++ exception crosses this interface.
+ */
+#ifndef LS_H
+#define LS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LS_OK = 0,
+    LS_ERR_ARG = -1,            /* invalid argument (null pointer, bad size or index)      */
+    LS_ERR_OOM = -2,            /* device allocation failed                                */
+    LS_ERR_HIP = -3,            /* a HIP runtime call failed                               */
+    LS_ERR_BREAKDOWN = -4,      /* BiCGSTAB breakdown (rho, r^H v or t^H t vanished)       */
+    LS_ERR_NOT_CONVERGED = -5,  /* maxit reached; the output holds the last iterate        */
+    LS_ERR_NONFINITE = -6,      /* NaN or Inf met in the residual                          */
+    LS_ERR_STATE = -7           /* the context was not built for the requested precision   */
+};
+
+enum { LS_PREC_C128 = 0, LS_PREC_MIXED = 1 };
+enum { LS_GREEN_EXACT = 0, LS_GREEN_PAPER_SUM = 1 };
+
+typedef struct {
+    int n[3];       /* N1, N2, N3 */
+    double h;       /* grid spacing (m) */
+} ls_grid;
+
+typedef struct {
+    int precision;  /* LS_PREC_C128: FP64 operator only; LS_PREC_MIXED: also the FP32 operator */
+    int green_mode; /* LS_GREEN_EXACT (default): the closed-form solution of Eq 7;
+                       LS_GREEN_PAPER_SUM: the near-field A.4 plus far-field A.5 tensors   */
+    int max_rhs;    /* largest batch of right-hand sides one call may carry (>= 1)         */
+    int reserved[5];
+} ls_options;
+
+typedef struct {
+    int iters;           /* BiCGSTAB iterations (inner iterations summed for mixed solves)  */
+    int matvecs;         /* operator applications, the final true-residual check included  */
+    int refinements;     /* outer FP64 refinement steps (mixed precision), else 0          */
+    int status;          /* LS_OK or the LS_ERR_* code of this right-hand side              */
+    double rel_res;      /* last recursively updated relative residual                     */
+    double rel_res_true; /* ||u0 - A u|| / ||u0|| recomputed with the FP64 operator (Eq 22) */
+} ls_info;
+
+typedef struct ls_ctx ls_ctx;
+
+/* Build a context for one grid and medium at n_omega angular frequencies (Eq 1-3, 7, 21).
+ *   C0[36]  host, row-major 6x6 background stiffness (must be symmetric).  If it is not
+ *           isotropic, the isotropic reference c11 = C33, c44 = (C44 + C55)/2 is used (the
+ *           rule of the paper's Model 1) and C0 minus that reference is added to every
+ *           cell's contrast.
+ *   rho0    background density.
+ *   dC      device, [21][N3][N2][N1] doubles (see conventions); drho device, [N3][N2][N1].
+ *           Both are copied; the caller may free them after the call returns.
+ *   omega   host, n_omega angular frequencies (rad/s, > 0).
+ *   opt     may be NULL (c128, exact Green's tensor, max_rhs 1).
+ *   stream  a hipStream_t (NULL = the null stream); all work of this context runs on it.
+ * Allocates all device memory the context will use (tables, contrast, workspaces).
+ * Synchronises the stream before returning.  On error *out is NULL. */
+int ls_setup(const ls_grid* grid, const double C0[36], double rho0,
+             const double* dC, const double* drho,
+             const double* omega, int n_omega, const ls_options* opt,
+             void* stream, ls_ctx** out);
+
+/* Release every device allocation of the context (synchronises its stream). NULL is a no-op. */
+void ls_destroy(ls_ctx* ctx);
+
+/* One LS matvec Au = u - Gconv B u at frequency omega[i_omega] (Eq 19-21), for n_rhs fields
+ * (1 <= n_rhs <= max_rhs).  u, Au: device c128 arrays [n_rhs][3][N3][N2][N1]; they must not
+ * overlap.  Asynchronous. */
+int ls_apply(ls_ctx* ctx, int i_omega, const void* u, void* Au, int n_rhs);
+
+/* The same matvec with the operator, its FFTs and Green's multiply in FP32 (c64 fields).
+ * Needs a context built with LS_PREC_MIXED, else LS_ERR_STATE.  Asynchronous. */
+int ls_apply_c64(ls_ctx* ctx, int i_omega, const void* u, void* Au, int n_rhs);
+
+/* Incident field of a moment tensor M at source cell src[3] = (i, j, k) with rupture time t0
+ * (Eq 13-16): b = e^{i w t0} Gconv E^T (M delta_src) / h^3, evaluated cell by cell from the
+ * closed-form Green's tensor.  b: device c128 [3][N3][N2][N1].  Asynchronous. */
+int ls_rhs_moment(ls_ctx* ctx, int i_omega, const double M[6], const int src[3], double t0, void* b);
+
+/* Incident field of a point force F (N) at cell[3] (Eq 6): b = Gconv (F delta_cell) / h^3.
+ * b: device c128 [3][N3][N2][N1].  Asynchronous. */
+int ls_rhs_force(ls_ctx* ctx, int i_omega, const double F[3], const int cell[3], void* b);
+
+/* Solve A u = b for n_rhs right-hand sides b (device c128 [n_rhs][3][N3][N2][N1]) with
+ * BiCGSTAB (x0 = 0 or the given guess), stopping when the recursive residual reaches tol
+ * (Eq 22), then recomputing the true FP64 residual.  With precision LS_PREC_MIXED the
+ * context's FP32 operator runs the inner BiCGSTAB inside an FP64 iterative-refinement loop
+ * whose residual b - A u uses the FP64 operator; the stopping test is always the FP64 true
+ * residual.  All n_rhs systems advance together through batched operator applications.
+ *   x0     device c128 like b, or NULL for zero.   u_out device c128 like b.
+ *   info   host array of n_rhs entries (may be NULL).
+ *   precision  LS_PREC_C128 or LS_PREC_MIXED (the latter needs a mixed context).
+ * Returns LS_OK when every system met tol; LS_ERR_NOT_CONVERGED, LS_ERR_BREAKDOWN or
+ * LS_ERR_NONFINITE otherwise (per-system codes in info[].status, u_out holds the best
+ * iterate).  Synchronises the stream. */
+int ls_solve(ls_ctx* ctx, int i_omega, const void* b, int n_rhs, double tol, int maxit,
+             int precision, const void* x0, void* u_out, ls_info* info);
+
+/* Convenience form for one moment-tensor source: builds b with ls_rhs_moment, then ls_solve. */
+int ls_solve_moment(ls_ctx* ctx, int i_omega, const double M[6], const int src[3], double t0,
+                    double tol, int maxit, int precision, void* u_out, ls_info* info);
+
+/* Voigt engineering strain of n_rhs fields (Eq 17-18): eps device c128 [n_rhs][6][N3][N2][N1]. */
+int ls_strain(ls_ctx* ctx, const void* u, void* eps, int n_rhs);
+
+/* Per-kernel timing of the library's own launches.  ls_profile(ctx, 1) starts recording a
+ * HIP event pair around every kernel launch on the context's stream (at most a fixed number
+ * of launches; later ones are not recorded); ls_profile(ctx, 0) stops.  ls_profile_read
+ * synchronises, then for each kernel family k < n_max writes its name (NUL-terminated, at
+ * most 63 chars) into names + 64 k, its launch count into counts[k] and the summed event time
+ * in milliseconds into ms[k]; returns the number of families, and clears the record. */
+int ls_profile(ls_ctx* ctx, int enable);
+int ls_profile_read(ls_ctx* ctx, char* names, int* counts, double* ms, int n_max);
+
+/* Bytes of device memory the context holds. */
+long long ls_device_bytes(const ls_ctx* ctx);
+
+/* Message of the last error on this host thread ("" if none). */
+const char* ls_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LS_H */

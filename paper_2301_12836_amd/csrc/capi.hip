@@ -1,0 +1,451 @@
+// C ABI of the LS solver library: context set-up, the matvec pipeline, incident fields, solves,
+// profiling.  See include/ls.h for the contract of every entry point.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "common.h"
+
+struct ls_ctx : public ls::Ctx {};
+
+namespace ls {
+
+// ------------------------------------------------------------------------------------------
+// errors
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return LS_ERR_HIP;
+}
+
+// ------------------------------------------------------------------------------------------
+// profiler
+
+int Profiler::family(const char* name) {
+    for (size_t i = 0; i < names.size(); ++i)
+        if (names[i] == name) return (int)i;
+    names.emplace_back(name);
+    return (int)names.size() - 1;
+}
+
+void Profiler::begin(hipStream_t s, const char* name) {
+    open_family = -1;
+    if (!on || n >= kMax) return;
+    open_family = family(name);
+    (void)hipEventRecord(ev[2 * n], s);
+}
+
+void Profiler::end(hipStream_t s) {
+    if (open_family < 0) return;
+    (void)hipEventRecord(ev[2 * n + 1], s);
+    fam[n] = open_family;
+    ++n;
+    open_family = -1;
+}
+
+Profiler::~Profiler() {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+}
+
+// ------------------------------------------------------------------------------------------
+// context helpers
+
+int dalloc(Ctx* c, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return LS_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(LS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    c->bytes += (long long)bytes;
+    return LS_OK;
+}
+
+const z128* Ctx::twiddle128(int L) const {
+    for (size_t i = 0; i < tw_len.size(); ++i)
+        if (tw_len[i] == L) return tw128[i];
+    return nullptr;
+}
+
+const z64* Ctx::twiddle64(int L) const {
+    for (size_t i = 0; i < tw_len.size(); ++i)
+        if (tw_len[i] == L) return tw64[i];
+    return nullptr;
+}
+
+static void release(Ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
+                    c->xd, c->bd, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
+                    c->state, c->stage, c->red};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    for (auto q : c->ghat) (void)hipFree(q);
+    for (auto q : c->ghat32) (void)hipFree(q);
+    for (auto q : c->tw128) (void)hipFree(q);
+    for (auto q : c->tw64) (void)hipFree(q);
+    if (c->red_host) (void)hipHostFree(c->red_host);
+    delete static_cast<ls_ctx*>(c);
+}
+
+// ------------------------------------------------------------------------------------------
+// the matvec
+
+template <typename T>
+int apply_op(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* Au, int nrhs) {
+    int rc = contrast_to_work<T>(c, i_omega, u, (cpx<T>*)c->work, (cpx<T>*)c->tau, nrhs);
+    if (rc) return rc;
+    return fft_apply_passes<T>(c, i_omega, (cpx<T>*)c->work, u, Au, nrhs, true);
+}
+
+template int apply_op<double>(Ctx*, int, const z128*, z128*, int);
+template int apply_op<float>(Ctx*, int, const z64*, z64*, int);
+
+}  // namespace ls
+
+using namespace ls;
+
+namespace {
+
+int check_ctx(const ls_ctx* c) {
+    if (!c) return fail(LS_ERR_ARG, "null context");
+    return LS_OK;
+}
+
+int check_omega(const ls_ctx* c, int i) {
+    if (i < 0 || i >= (int)c->omega.size()) return fail(LS_ERR_ARG, "frequency index out of range");
+    return LS_OK;
+}
+
+int check_cell(const ls_ctx* c, const int* cell) {
+    if (!cell) return fail(LS_ERR_ARG, "null cell index");
+    const int n[3] = {c->n1, c->n2, c->n3};
+    for (int a = 0; a < 3; ++a)
+        if (cell[a] < 0 || cell[a] >= n[a]) return fail(LS_ERR_ARG, "cell index outside the grid");
+    return LS_OK;
+}
+
+bool is_isotropic(const double* C) {
+    double scale = 0;
+    for (int i = 0; i < 36; ++i) scale = std::max(scale, std::fabs(C[i]));
+    const double c11 = C[0], c44 = C[21], c12 = c11 - 2.0 * c44;
+    for (int I = 0; I < 6; ++I)
+        for (int J = 0; J < 6; ++J) {
+            double ref = 0;
+            if (I < 3 && J < 3) ref = (I == J) ? c11 : c12;
+            if (I >= 3 && I == J) ref = c44;
+            if (std::fabs(C[I * 6 + J] - ref) > 1e-12 * scale) return false;
+        }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ls_last_error(void) { return g_last_error.c_str(); }
+
+int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double* dC, const double* drho,
+             const double* omega, int n_omega, const ls_options* opt, void* stream, ls_ctx** out) {
+    if (!out) return fail(LS_ERR_ARG, "null output pointer");
+    *out = nullptr;
+    if (!grid || !C0 || !dC || !drho || !omega) return fail(LS_ERR_ARG, "null argument");
+    for (int a = 0; a < 3; ++a)
+        if (grid->n[a] < 2 || grid->n[a] > 256) return fail(LS_ERR_ARG, "grid size must be in [2, 256] per axis");
+    if (!(grid->h > 0) || !std::isfinite(grid->h)) return fail(LS_ERR_ARG, "grid spacing must be positive");
+    if (!(rho0 > 0) || !std::isfinite(rho0)) return fail(LS_ERR_ARG, "background density must be positive");
+    if (n_omega < 1) return fail(LS_ERR_ARG, "need at least one frequency");
+    for (int i = 0; i < n_omega; ++i)
+        if (!(omega[i] > 0) || !std::isfinite(omega[i])) return fail(LS_ERR_ARG, "frequencies must be positive");
+    double cmax = 0;
+    for (int i = 0; i < 36; ++i) {
+        if (!std::isfinite(C0[i])) return fail(LS_ERR_ARG, "non-finite background stiffness");
+        cmax = std::max(cmax, std::fabs(C0[i]));
+    }
+    for (int I = 0; I < 6; ++I)
+        for (int J = 0; J < I; ++J)
+            if (std::fabs(C0[I * 6 + J] - C0[J * 6 + I]) > 1e-12 * cmax)
+                return fail(LS_ERR_ARG, "background stiffness must be symmetric");
+    ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, {0, 0, 0, 0, 0}};
+    if (opt) o = *opt;
+    if (o.precision != LS_PREC_C128 && o.precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
+    if (o.green_mode != LS_GREEN_EXACT && o.green_mode != LS_GREEN_PAPER_SUM) return fail(LS_ERR_ARG, "bad green_mode");
+    if (o.max_rhs < 1 || o.max_rhs > 64) return fail(LS_ERR_ARG, "max_rhs must be in [1, 64]");
+
+    // isotropic reference and the anisotropic remainder folded into the contrast
+    double c11, c44;
+    if (is_isotropic(C0)) {
+        c11 = C0[0];
+        c44 = C0[21];
+    } else {
+        c11 = C0[14];
+        c44 = 0.5 * (C0[21] + C0[28]);
+    }
+    if (!(c44 > 0) || !(c11 > c44)) return fail(LS_ERR_ARG, "reference medium needs C11 > C44 > 0");
+    double Ciso[36] = {0};
+    for (int I = 0; I < 3; ++I)
+        for (int J = 0; J < 3; ++J) Ciso[I * 6 + J] = (I == J) ? c11 : c11 - 2.0 * c44;
+    for (int I = 3; I < 6; ++I) Ciso[I * 6 + I] = c44;
+    double fold21[21];
+    for (int I = 0, q = 0; I < 6; ++I)
+        for (int J = I; J < 6; ++J, ++q) fold21[q] = C0[I * 6 + J] - Ciso[I * 6 + J];
+
+    Ctx* c = new (std::nothrow) ls_ctx();
+    if (!c) return fail(LS_ERR_OOM, "host allocation failed");
+    c->n1 = grid->n[0];
+    c->n2 = grid->n[1];
+    c->n3 = grid->n[2];
+    c->L1 = supported_fft_length(c->n1);
+    c->L2 = supported_fft_length(c->n2);
+    c->L3 = supported_fft_length(c->n3);
+    c->ncell = (long long)c->n1 * c->n2 * c->n3;
+    c->h = grid->h;
+    c->mixed = o.precision == LS_PREC_MIXED;
+    c->green_mode = o.green_mode;
+    c->max_rhs = o.max_rhs;
+    c->rho0 = rho0;
+    c->alpha = std::sqrt(c11 / rho0);
+    c->beta = std::sqrt(c44 / rho0);
+    c->omega.assign(omega, omega + n_omega);
+    c->stream = (hipStream_t)stream;
+
+    const size_t n = (size_t)c->ncell;
+    const size_t fe = 3 * n * (size_t)c->max_rhs;  // field elements of a batch
+    const size_t oct = (size_t)(c->L1 / 2 + 1) * (c->L2 / 2 + 1) * (c->L3 / 2 + 1);
+    int rc = LS_OK;
+    auto A = [&](void** p, size_t bytes) {
+        if (rc == LS_OK) rc = dalloc(c, p, bytes);
+    };
+    A((void**)&c->dc, 21 * n * sizeof(double));
+    A((void**)&c->drho, n * sizeof(double));
+    if (c->mixed) {
+        A((void**)&c->dc32, 21 * n * sizeof(float));
+        A((void**)&c->drho32, n * sizeof(float));
+    }
+    c->ghat.assign(n_omega, nullptr);
+    c->ghat32.assign(n_omega, nullptr);
+    for (int i = 0; i < n_omega; ++i) {
+        A((void**)&c->ghat[i], 6 * oct * sizeof(z128));
+        if (c->mixed) A((void**)&c->ghat32[i], 6 * oct * sizeof(z64));
+    }
+    A(&c->work, (size_t)c->max_rhs * 3 * c->n3 * c->L2 * c->L1 * sizeof(z128));
+    A(&c->tau, (size_t)c->max_rhs * 6 * n * sizeof(z128));
+    z128** v128[] = {&c->r, &c->rhat, &c->p, &c->v, &c->s, &c->t};
+    for (auto pp : v128) A((void**)pp, fe * sizeof(z128));
+    A((void**)&c->bd, 3 * n * sizeof(z128));
+    if (c->mixed) {
+        z64** v64[] = {&c->r32, &c->rhat32, &c->p32, &c->v32, &c->s32, &c->t32, &c->x32, &c->b32};
+        for (auto pp : v64) A((void**)pp, fe * sizeof(z64));
+    }
+    A((void**)&c->partials, (size_t)c->max_rhs * kRedSlots * kRedBlocks * sizeof(double));
+    A((void**)&c->state, (size_t)c->max_rhs * kStateLen * sizeof(double));
+    A((void**)&c->red, 4 * kRedBlocks * sizeof(double));
+    A(&c->stage, 4096);
+    if (rc == LS_OK) {
+        const size_t hb = std::max<size_t>(4 * kRedBlocks, (size_t)c->max_rhs * kStateLen) * sizeof(double);
+        if (hipHostMalloc((void**)&c->red_host, hb, hipHostMallocDefault) != hipSuccess) {
+            c->red_host = nullptr;
+            rc = fail(LS_ERR_OOM, "pinned host allocation failed");
+        }
+    }
+    // twiddle tables e^{-2 pi i m / L} computed in FP64 on the host
+    for (int L : {c->L1, c->L2, c->L3}) {
+        if (rc || c->twiddle128(L)) continue;
+        std::vector<z128> h128(L);
+        std::vector<z64> h64(L);
+        for (int m = 0; m < L; ++m) {
+            const double ang = -2.0 * 3.14159265358979323846 * (double)m / (double)L;
+            h128[m] = {std::cos(ang), std::sin(ang)};
+            h64[m] = {(float)h128[m].x, (float)h128[m].y};
+        }
+        z128* d128 = nullptr;
+        z64* d64 = nullptr;
+        A((void**)&d128, L * sizeof(z128));
+        A((void**)&d64, L * sizeof(z64));
+        if (rc) {
+            if (d128) (void)hipFree(d128);
+            if (d64) (void)hipFree(d64);
+            break;
+        }
+        c->tw_len.push_back(L);
+        c->tw128.push_back(d128);
+        c->tw64.push_back(d64);
+        if (hipMemcpy(d128, h128.data(), L * sizeof(z128), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d64, h64.data(), L * sizeof(z64), hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(LS_ERR_HIP, "twiddle upload failed");
+    }
+    if (rc == LS_OK) rc = fold_background(c, dC, drho, fold21);
+    if (rc == LS_OK) rc = build_green_tables(c);
+    if (rc == LS_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LS_ERR_HIP, "setup synchronisation failed");
+    if (rc) {
+        const std::string msg = g_last_error;
+        release(c);
+        g_last_error = msg;
+        return rc;
+    }
+    *out = static_cast<ls_ctx*>(c);
+    return LS_OK;
+}
+
+void ls_destroy(ls_ctx* ctx) { release(ctx); }
+
+int ls_apply(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!u || !Au) return fail(LS_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    return apply_op<double>(c, i_omega, (const z128*)u, (z128*)Au, n_rhs);
+}
+
+int ls_apply_c64(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!c->mixed) return fail(LS_ERR_STATE, "the FP32 operator needs a context built with LS_PREC_MIXED");
+    if (!u || !Au) return fail(LS_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    return apply_op<float>(c, i_omega, (const z64*)u, (z64*)Au, n_rhs);
+}
+
+int ls_rhs_moment(ls_ctx* c, int i_omega, const double M[6], const int src[3], double t0, void* b) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega)) || (rc = check_cell(c, src))) return rc;
+    if (!M || !b) return fail(LS_ERR_ARG, "null argument");
+    for (int J = 0; J < 6; ++J)
+        if (!std::isfinite(M[J])) return fail(LS_ERR_ARG, "non-finite moment tensor");
+    if (!std::isfinite(t0)) return fail(LS_ERR_ARG, "non-finite rupture time");
+    // E^T (M delta_src): for each axis a and component c, row src_a of the 1-D difference matrix
+    // D_a, weighted by the moment component of the Voigt pair (a, c)
+    static const int voigt[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+    const int n[3] = {c->n1, c->n2, c->n3};
+    const double ih = 1.0 / c->h;
+    std::map<std::array<int, 3>, std::array<double, 3>> pts;
+    for (int a = 0; a < 3; ++a) {
+        int cols[2];
+        double coef[2];
+        const int s = src[a];
+        if (s == 0) {
+            cols[0] = 0, coef[0] = -ih, cols[1] = 1, coef[1] = ih;
+        } else if (s == n[a] - 1) {
+            cols[0] = s, coef[0] = ih, cols[1] = s - 1, coef[1] = -ih;
+        } else {
+            cols[0] = s + 1, coef[0] = 0.5 * ih, cols[1] = s - 1, coef[1] = -0.5 * ih;
+        }
+        for (int cc = 0; cc < 3; ++cc) {
+            const double m = M[voigt[a][cc]];
+            if (m == 0.0) continue;
+            for (int q = 0; q < 2; ++q) {
+                std::array<int, 3> cell = {src[0], src[1], src[2]};
+                cell[a] = cols[q];
+                auto& f = pts[cell];
+                f[cc] += m * coef[q];
+            }
+        }
+    }
+    std::vector<int> cells;
+    std::vector<double> F;
+    for (auto& kv : pts) {
+        for (int a = 0; a < 3; ++a) cells.push_back(kv.first[a]);
+        for (int a = 0; a < 3; ++a) F.push_back(kv.second[a]);
+    }
+    if (cells.empty()) {
+        LS_HIP(hipMemsetAsync(b, 0, sizeof(z128) * c->field_elems(), c->stream));
+        return LS_OK;
+    }
+    return rhs_points_launch(c, i_omega, cells.data(), F.data(), (int)pts.size(), t0, (z128*)b);
+}
+
+int ls_rhs_force(ls_ctx* c, int i_omega, const double F[3], const int cell[3], void* b) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega)) || (rc = check_cell(c, cell))) return rc;
+    if (!F || !b) return fail(LS_ERR_ARG, "null argument");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(F[a])) return fail(LS_ERR_ARG, "non-finite force");
+    return rhs_points_launch(c, i_omega, cell, F, 1, 0.0, (z128*)b);
+}
+
+int ls_solve(ls_ctx* c, int i_omega, const void* b, int n_rhs, double tol, int maxit, int precision, const void* x0,
+             void* u_out, ls_info* info) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!b || !u_out) return fail(LS_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    if (!(tol > 0) || !(tol < 1)) return fail(LS_ERR_ARG, "tol must be in (0, 1)");
+    if (maxit < 1) return fail(LS_ERR_ARG, "maxit must be >= 1");
+    if (precision != LS_PREC_C128 && precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
+    if (precision == LS_PREC_MIXED && !c->mixed)
+        return fail(LS_ERR_STATE, "mixed precision needs a context built with LS_PREC_MIXED");
+    return solve_systems(c, i_omega, (const z128*)b, n_rhs, tol, maxit, precision, (const z128*)x0, (z128*)u_out, info);
+}
+
+int ls_solve_moment(ls_ctx* c, int i_omega, const double M[6], const int src[3], double t0, double tol, int maxit,
+                    int precision, void* u_out, ls_info* info) {
+    int rc = ls_rhs_moment(c, i_omega, M, src, t0, c ? (void*)c->bd : nullptr);
+    if (rc) return rc;
+    return ls_solve(c, i_omega, c->bd, 1, tol, maxit, precision, nullptr, u_out, info);
+}
+
+int ls_strain(ls_ctx* c, const void* u, void* eps, int n_rhs) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if (!u || !eps) return fail(LS_ERR_ARG, "null field pointer");
+    if (n_rhs < 1) return fail(LS_ERR_ARG, "n_rhs must be >= 1");
+    return strain_launch(c, (const z128*)u, (z128*)eps, n_rhs);
+}
+
+int ls_profile(ls_ctx* c, int enable) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    Profiler& P = c->prof;
+    if (enable && P.ev.empty()) {
+        P.ev.resize(2 * Profiler::kMax);
+        P.fam.resize(Profiler::kMax);
+        for (auto& e : P.ev) LS_HIP(hipEventCreate(&e));
+    }
+    P.on = enable != 0;
+    return LS_OK;
+}
+
+int ls_profile_read(ls_ctx* c, char* names, int* counts, double* ms, int n_max) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    Profiler& P = c->prof;
+    LS_HIP(hipStreamSynchronize(c->stream));
+    std::vector<double> sum(P.names.size(), 0.0);
+    std::vector<int> cnt(P.names.size(), 0);
+    for (int i = 0; i < P.n; ++i) {
+        float t = 0;
+        LS_HIP(hipEventElapsedTime(&t, P.ev[2 * i], P.ev[2 * i + 1]));
+        sum[P.fam[i]] += t;
+        cnt[P.fam[i]] += 1;
+    }
+    const int nf = (int)P.names.size();
+    for (int k = 0; k < nf && k < n_max; ++k) {
+        if (names) {
+            std::strncpy(names + 64 * k, P.names[k].c_str(), 63);
+            names[64 * k + 63] = 0;
+        }
+        if (counts) counts[k] = cnt[k];
+        if (ms) ms[k] = sum[k];
+    }
+    P.n = 0;
+    return nf;
+}
+
+long long ls_device_bytes(const ls_ctx* c) { return c ? c->bytes : 0; }
+
+}  // extern "C"

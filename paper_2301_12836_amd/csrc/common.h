@@ -1,0 +1,163 @@
+// Internal declarations shared by the library's translation units (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ls.h"
+
+namespace ls {
+
+// ------------------------------------------------------------------------------------------
+// complex arithmetic on interleaved (re, im) pairs, layout-compatible with complex128/complex64
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+    T x, y;
+};
+using z128 = cpx<double>;
+using z64 = cpx<float>;
+
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return {s * a.x, s * a.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.x, -a.y}; }
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+
+// ------------------------------------------------------------------------------------------
+// error reporting
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define LS_HIP(call)                                         \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return ::ls::hip_fail(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------------------------------------------
+// per-kernel event timing (enabled by ls_profile)
+
+struct Profiler {
+    bool on = false;
+    static constexpr int kMax = 8192;
+    std::vector<hipEvent_t> ev;      // 2 per record
+    std::vector<int> fam;            // family index per record
+    std::vector<std::string> names;  // family names
+    int n = 0;
+    int family(const char* name);
+    void begin(hipStream_t s, const char* name);
+    void end(hipStream_t s);
+    int open_family = -1;
+    ~Profiler();
+};
+
+// ------------------------------------------------------------------------------------------
+// context
+
+struct Ctx {
+    int n1 = 0, n2 = 0, n3 = 0;   // cells per axis (x, y, z)
+    int L1 = 0, L2 = 0, L3 = 0;   // FFT lengths per axis (>= 2n - 1, supported sizes)
+    long long ncell = 0;
+    double h = 0;
+    int mixed = 0;
+    int green_mode = LS_GREEN_EXACT;
+    int max_rhs = 1;
+    double rho0 = 0, alpha = 0, beta = 0;
+    std::vector<double> omega;
+    hipStream_t stream = nullptr;
+
+    // medium (folded contrast), FP64 and (mixed) FP32
+    double* dc = nullptr;     // [21][ncell]
+    double* drho = nullptr;   // [ncell]
+    float* dc32 = nullptr;
+    float* drho32 = nullptr;
+
+    // k-space Green's tables per frequency: octant [6][L3/2+1][L2/2+1][L1/2+1], already scaled by
+    // 1/(L1 L2 L3) so the inverse FFT needs no normalisation
+    std::vector<z128*> ghat;
+    std::vector<z64*> ghat32;
+
+    // twiddle tables e^{-2 pi i m / L}, m < L, per distinct length
+    std::vector<int> tw_len;
+    std::vector<z128*> tw128;
+    std::vector<z64*> tw64;
+
+    // workspaces
+    void* work = nullptr;       // padded FFT buffer [max_rhs][3][N3][L2][L1] (c128 size)
+    void* tau = nullptr;        // Voigt stress scratch [max_rhs][6][ncell] (c128 size)
+    // Krylov vectors, c128 [max_rhs][3][ncell] each
+    z128 *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
+    z128 *xd = nullptr, *bd = nullptr;           // FP64 iterate / rhs copies for refinement
+    // c64 Krylov vectors for the inner solve of the mixed path
+    z64 *r32 = nullptr, *rhat32 = nullptr, *p32 = nullptr, *v32 = nullptr, *s32 = nullptr, *t32 = nullptr,
+        *x32 = nullptr, *b32 = nullptr;
+    double* partials = nullptr;  // reduction partials [max_rhs][kRedSlots][kRedBlocks]
+    double* state = nullptr;     // BiCGSTAB scalars per right-hand side [max_rhs][kStateLen]
+    void* stage = nullptr;       // small host-to-device staging area (4 KB)
+    double* red = nullptr;       // reduction results (device)
+    double* red_host = nullptr;  // pinned host mirror
+    long long bytes = 0;
+    Profiler prof;
+
+    const z128* twiddle128(int L) const;
+    const z64* twiddle64(int L) const;
+    size_t field_elems() const { return (size_t)3 * (size_t)ncell; }
+};
+
+// device allocation tracked in ctx->bytes
+int dalloc(Ctx* c, void** p, size_t bytes);
+
+// ------------------------------------------------------------------------------------------
+// host launchers (each returns LS_OK or an error code)
+
+// FFT passes over the padded buffer; see fft.hip
+template <typename T>
+int fft_apply_passes(Ctx* c, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, int nrhs,
+                     bool subtract_from_u);
+template <typename T>
+int fft_full_3d_forward(Ctx* c, cpx<T>* buf);
+int supported_fft_length(int n);
+
+// contrast kernels; see contrast.hip
+template <typename T>
+int contrast_to_work(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* work, cpx<T>* tau, int nrhs);
+int fold_background(Ctx* c, const double* dc_in, const double* drho_in, const double fold21[21]);
+int strain_launch(Ctx* c, const z128* u, z128* eps, int nrhs);
+
+// Green's tables and incident fields; see green.hip
+int build_green_tables(Ctx* c);
+int rhs_points_launch(Ctx* c, int i_omega, const int* cells, const double* forces, int npts, double t0,
+                      z128* b);
+
+// the LS matvec Au = u - Gconv B u (or v = Gconv B u); see capi.hip
+template <typename T>
+int apply_op(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* Au, int nrhs);
+
+// solver (BiCGSTAB, mixed-precision refinement); see solver.hip
+int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int maxit, int precision,
+                  const z128* x0, z128* u_out, ls_info* info);
+
+constexpr int kRedBlocks = 1024;  // fixed partial count: reductions are deterministic
+constexpr int kRedSlots = 4;      // partial sums per right-hand side and pass
+constexpr int kStateLen = 16;
+
+}  // namespace ls

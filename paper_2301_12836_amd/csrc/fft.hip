@@ -1,0 +1,307 @@
+// Zero-padded 3-D FFT passes of the matrix-free LS operator (Eq 21) and the k-space Green's
+// tensor multiply.
+//
+// Work buffer layout (per right-hand side r, component c): W[r][c][z < N3][y < L2][x < L1].
+// The convolution of a force density f (supported on the N1 x N2 x N3 cells) with the Green's
+// table is linear (not periodic) because every FFT length L_a >= 2 N_a - 1.  The passes prune
+// the zeros: the forward x pass reads N1 inputs per line and runs only on the N2 x N3 lines
+// that carry data; the forward y pass reads N2 inputs; the fused z pass reads N3 inputs, runs
+// the forward z FFT, multiplies by the 3x3 symmetric table G^(k), runs the inverse z FFT and
+// keeps N3 outputs; the inverse y pass keeps N2 outputs and the inverse x pass keeps N1 outputs
+// and writes Au = u - v (or v) into the compact caller array.  Every pass except the last is
+// in place, so W holds 3 N3 L2 L1 complex values per right-hand side.
+#include "fft_core.h"
+
+namespace ls {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// Lines per block of the contiguous (x) pass: about 32 KB of LDS.
+template <typename T, int L>
+constexpr int contig_lines() {
+    constexpr int elems = 32768 / (int)sizeof(cpx<T>);
+    return elems / L > 1 ? elems / L : 1;
+}
+// Adjacent columns per block of the strided (y, z) passes: 128-byte row segments.
+template <typename T>
+constexpr int strided_cols() {
+    return 128 / (int)sizeof(cpx<T>);
+}
+// Adjacent columns per block of the fused z pass (three components resident in LDS).
+template <typename T, int L>
+constexpr int zpass_cols() {
+    constexpr int budget = 49152;  // bytes of LDS
+    constexpr int tx = budget / (3 * L * (int)sizeof(cpx<T>));
+    return tx >= 8 ? 8 : (tx >= 4 ? 4 : (tx >= 2 ? 2 : 1));
+}
+
+// MODE 0: in place into data; 1: out = u - v (compact); 2: out = v (compact)
+template <typename T, int L, int TY, int SIGN, int MODE>
+__global__ __launch_bounds__(kThreads) void k_fft_contig(cpx<T>* __restrict__ data, long long nlines, int D2,
+                                                         long long S1, long long S2, int n_in, int n_out,
+                                                         const cpx<T>* __restrict__ tw,
+                                                         const cpx<T>* __restrict__ u, cpx<T>* __restrict__ out) {
+    constexpr int LDP = TY + 1;
+    __shared__ cpx<T> s[L * LDP];
+    const int tid = threadIdx.x;
+    const long long line0 = (long long)blockIdx.x * TY;
+    for (int idx = tid; idx < L * TY; idx += kThreads) {
+        const int e = idx % L, ln = idx / L;
+        const long long line = line0 + ln;
+        cpx<T> val = {T(0), T(0)};
+        if (line < nlines && e < n_in) {
+            const long long o1 = line / D2, o2 = line - o1 * D2;
+            val = data[o1 * S1 + o2 * S2 + e];
+        }
+        s[e * LDP + ln] = val;
+    }
+    __syncthreads();
+    lds_fft<T, L, TY, LDP, kThreads, SIGN>(s, tw, tid);
+    for (int idx = tid; idx < L * TY; idx += kThreads) {
+        const int e = idx % L, ln = idx / L;
+        const long long line = line0 + ln;
+        if (line < nlines && e < n_out) {
+            const cpx<T> v = s[e * LDP + ln];
+            if constexpr (MODE == 0) {
+                const long long o1 = line / D2, o2 = line - o1 * D2;
+                data[o1 * S1 + o2 * S2 + e] = v;
+            } else {
+                const long long q = line * n_out + e;   // compact [.. lines ..][n_out]
+                if constexpr (MODE == 1)
+                    out[q] = u[q] - v;
+                else
+                    out[q] = v;
+            }
+        }
+    }
+}
+
+template <typename T, int L, int TX, int SIGN>
+__global__ __launch_bounds__(kThreads) void k_fft_strided(cpx<T>* __restrict__ data, long long S1, long long S2,
+                                                          long long ES, int n_in, int n_out,
+                                                          const cpx<T>* __restrict__ tw) {
+    __shared__ cpx<T> s[L * TX];
+    const int tid = threadIdx.x;
+    cpx<T>* base = data + (long long)blockIdx.z * S1 + (long long)blockIdx.y * S2 + (long long)blockIdx.x * TX;
+    for (int idx = tid; idx < L * TX; idx += kThreads) {
+        const int t = idx % TX, e = idx / TX;
+        cpx<T> val = {T(0), T(0)};
+        if (e < n_in) val = base[e * ES + t];
+        s[e * TX + t] = val;
+    }
+    __syncthreads();
+    lds_fft<T, L, TX, TX, kThreads, SIGN>(s, tw, tid);
+    for (int idx = tid; idx < L * TX; idx += kThreads) {
+        const int t = idx % TX, e = idx / TX;
+        if (e < n_out) base[e * ES + t] = s[e * TX + t];
+    }
+}
+
+// Visit y and its mirror L2 - y in consecutive blocks so both read the same octant rows of G^.
+__device__ __forceinline__ int paired_row(int by, int L2) {
+    if (by == 0) return 0;
+    if (by == L2 - 1) return L2 / 2;
+    const int m = (by + 1) >> 1;
+    return (by & 1) ? m : L2 - m;
+}
+
+// Fused z pass: forward z FFT of the three components, v^ = G^(k) f^, inverse z FFT.
+// G^ holds the octant [6][L3/2+1][L2/2+1][L1/2+1] (Voigt order 11,22,33,23,13,12); under
+// k_a -> L_a - k_a an off-diagonal component ij changes sign once for each of i, j equal to a.
+template <typename T, int L, int TX>
+__global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1, int L2,
+                                                         long long CS, long long RS, long long ES, int n3,
+                                                         const cpx<T>* __restrict__ ghat,
+                                                         const cpx<T>* __restrict__ tw) {
+    constexpr int NL = 3 * TX;
+    __shared__ cpx<T> s[L * NL];
+    const int tid = threadIdx.x;
+    const int rhs = blockIdx.x % nrhs;
+    const int x0 = (blockIdx.x / nrhs) * TX;
+    const int y = paired_row(blockIdx.y, L2);
+    cpx<T>* base = data + (long long)rhs * RS + (long long)y * L1 + x0;
+    for (int idx = tid; idx < L * NL; idx += kThreads) {
+        const int t = idx % TX, c = (idx / TX) % 3, e = idx / NL;
+        cpx<T> val = {T(0), T(0)};
+        if (e < n3) val = base[c * CS + e * ES + t];
+        s[e * NL + c * TX + t] = val;
+    }
+    __syncthreads();
+    lds_fft<T, L, NL, NL, kThreads, -1>(s, tw, tid);
+
+    const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1, O3 = L / 2 + 1;
+    const long long GS = (long long)O3 * O2 * O1;
+    const bool fy = y > L2 / 2;
+    const int ky = fy ? L2 - y : y;
+    for (int idx = tid; idx < L * TX; idx += kThreads) {
+        const int t = idx % TX, kz0 = idx / TX;
+        const int kx0 = x0 + t;
+        const bool fx = kx0 > L1 / 2, fz = kz0 > L / 2;
+        const int kx = fx ? L1 - kx0 : kx0, kz = fz ? L - kz0 : kz0;
+        const cpx<T>* g = ghat + ((long long)kz * O2 + ky) * O1 + kx;
+        const cpx<T> g11 = g[0], g22 = g[GS], g33 = g[2 * GS];
+        cpx<T> g23 = g[3 * GS], g13 = g[4 * GS], g12 = g[5 * GS];
+        if (fy != fz) g23 = T(-1) * g23;
+        if (fx != fz) g13 = T(-1) * g13;
+        if (fx != fy) g12 = T(-1) * g12;
+        cpx<T>* row = s + kz0 * NL + t;
+        const cpx<T> f1 = row[0], f2 = row[TX], f3 = row[2 * TX];
+        row[0] = g11 * f1 + g12 * f2 + g13 * f3;
+        row[TX] = g12 * f1 + g22 * f2 + g23 * f3;
+        row[2 * TX] = g13 * f1 + g23 * f2 + g33 * f3;
+    }
+    __syncthreads();
+    lds_fft<T, L, NL, NL, kThreads, +1>(s, tw, tid);
+    for (int idx = tid; idx < L * NL; idx += kThreads) {
+        const int t = idx % TX, c = (idx / TX) % 3, e = idx / NL;
+        if (e < n3) base[c * CS + e * ES + t] = s[e * NL + c * TX + t];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// host dispatch over the supported lengths
+
+#define LS_FOR_LENGTHS(X) X(16) X(32) X(64) X(128) X(256) X(512)
+
+template <typename T, int SIGN, int MODE>
+int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long long S1, long long S2, int n_in,
+                  int n_out, const cpx<T>* tw, const cpx<T>* u, cpx<T>* out, const char* name) {
+    c->prof.begin(c->stream, name);
+    switch (L) {
+#define CASE(LL)                                                                                         \
+    case LL: {                                                                                           \
+        constexpr int TY = contig_lines<T, LL>();                                                        \
+        const long long nb = (nlines + TY - 1) / TY;                                                     \
+        hipLaunchKernelGGL((k_fft_contig<T, LL, TY, SIGN, MODE>), dim3((unsigned)nb), dim3(kThreads), 0, \
+                           c->stream, data, nlines, D2, S1, S2, n_in, n_out, tw, u, out);                \
+        break;                                                                                           \
+    }
+        LS_FOR_LENGTHS(CASE)
+#undef CASE
+        default:
+            return fail(LS_ERR_ARG, "unsupported FFT length");
+    }
+    c->prof.end(c->stream);
+    LS_HIP(hipGetLastError());
+    return LS_OK;
+}
+
+template <typename T, int SIGN>
+int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long long S1, long long S2, long long ES,
+                   int n_in, int n_out, const cpx<T>* tw, const char* name) {
+    constexpr int TX = strided_cols<T>();
+    if (NX % TX) return fail(LS_ERR_ARG, "x length not a multiple of the column tile");
+    c->prof.begin(c->stream, name);
+    switch (L) {
+#define CASE(LL)                                                                                             \
+    case LL:                                                                                                 \
+        hipLaunchKernelGGL((k_fft_strided<T, LL, TX, SIGN>), dim3(NX / TX, D2, D1), dim3(kThreads), 0,        \
+                           c->stream, data, S1, S2, ES, n_in, n_out, tw);                                    \
+        break;
+        LS_FOR_LENGTHS(CASE)
+#undef CASE
+        default:
+            return fail(LS_ERR_ARG, "unsupported FFT length");
+    }
+    c->prof.end(c->stream);
+    LS_HIP(hipGetLastError());
+    return LS_OK;
+}
+
+template <typename T>
+int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<T>* tw) {
+    const int L1 = c->L1, L2 = c->L2, L = c->L3;
+    const long long CS = (long long)c->n3 * L2 * L1;
+    const long long RS = 3 * CS;
+    const long long ES = (long long)L2 * L1;
+    c->prof.begin(c->stream, "fft_z_green");
+    switch (L) {
+#define CASE(LL)                                                                                          \
+    case LL: {                                                                                            \
+        constexpr int TX = zpass_cols<T, LL>();                                                           \
+        if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");               \
+        hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), 0,    \
+                           c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw);                   \
+        break;                                                                                            \
+    }
+        LS_FOR_LENGTHS(CASE)
+#undef CASE
+        default:
+            return fail(LS_ERR_ARG, "unsupported FFT length");
+    }
+    c->prof.end(c->stream);
+    LS_HIP(hipGetLastError());
+    return LS_OK;
+}
+
+template <typename T>
+const cpx<T>* twiddles(const Ctx* c, int L);
+template <>
+const z128* twiddles<double>(const Ctx* c, int L) { return c->twiddle128(L); }
+template <>
+const z64* twiddles<float>(const Ctx* c, int L) { return c->twiddle64(L); }
+
+template <typename T>
+const cpx<T>* green_table(const Ctx* c, int i);
+template <>
+const z128* green_table<double>(const Ctx* c, int i) { return c->ghat[i]; }
+template <>
+const z64* green_table<float>(const Ctx* c, int i) { return c->ghat32[i]; }
+
+}  // namespace
+
+int supported_fft_length(int n) {
+    for (int L = 16; L <= 512; L *= 2)
+        if (L >= 2 * n - 1) return L;
+    return 0;
+}
+
+// Au = u - Gconv(f) (subtract_from_u) or Au = Gconv(f), where f already sits in work.
+template <typename T>
+int fft_apply_passes(Ctx* c, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, int nrhs,
+                     bool subtract_from_u) {
+    const int N1 = c->n1, N2 = c->n2, N3 = c->n3, L1 = c->L1, L2 = c->L2, L3 = c->L3;
+    const long long rc = 3LL * nrhs;
+    const long long plane = (long long)L2 * L1;
+    const cpx<T>* tw1 = twiddles<T>(c, L1);
+    const cpx<T>* tw2 = twiddles<T>(c, L2);
+    const cpx<T>* tw3 = twiddles<T>(c, L3);
+    int rc_ = LS_OK;
+    // x forward on the N2 x N3 data lines
+    rc_ = launch_contig<T, -1, 0>(c, L1, work, rc * N3 * N2, N2, plane, L1, N1, L1, tw1, nullptr, nullptr,
+                                  "fft_x_fwd");
+    if (rc_) return rc_;
+    // y forward on all L1 columns of the N3 data planes
+    rc_ = launch_strided<T, -1>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, N2, L2, tw2, "fft_y_fwd");
+    if (rc_) return rc_;
+    rc_ = launch_zgreen<T>(c, work, nrhs, green_table<T>(c, i_omega), tw3);
+    if (rc_) return rc_;
+    rc_ = launch_strided<T, +1>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, L2, N2, tw2, "fft_y_inv");
+    if (rc_) return rc_;
+    if (subtract_from_u)
+        rc_ = launch_contig<T, +1, 1>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, "fft_x_inv_epi");
+    else
+        rc_ = launch_contig<T, +1, 2>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, "fft_x_inv_epi");
+    return rc_;
+}
+
+// In-place unnormalised forward 3-D FFT of one [L3][L2][L1] array (Green's table setup).
+template <typename T>
+int fft_full_3d_forward(Ctx* c, cpx<T>* buf) {
+    const int L1 = c->L1, L2 = c->L2, L3 = c->L3;
+    const long long plane = (long long)L2 * L1;
+    int rc_ = launch_contig<T, -1, 0>(c, L1, buf, (long long)L3 * L2, L2, plane, L1, L1, L1, twiddles<T>(c, L1),
+                                      nullptr, nullptr, "table_fft_x");
+    if (rc_) return rc_;
+    rc_ = launch_strided<T, -1>(c, L2, buf, L1, 1, L3, plane, 0, L1, L2, L2, twiddles<T>(c, L2), "table_fft_y");
+    if (rc_) return rc_;
+    return launch_strided<T, -1>(c, L3, buf, L1, L2, 1, 0, L1, plane, L3, L3, twiddles<T>(c, L3), "table_fft_z");
+}
+
+template int fft_apply_passes<double>(Ctx*, int, z128*, const z128*, z128*, int, bool);
+template int fft_apply_passes<float>(Ctx*, int, z64*, const z64*, z64*, int, bool);
+template int fft_full_3d_forward<double>(Ctx*, z128*);
+
+}  // namespace ls

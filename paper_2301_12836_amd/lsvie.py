@@ -1,0 +1,323 @@
+"""ctypes binding of the HIP LS library (include/ls.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels on the GPU; this module only converts
+torch tensors to device pointers and checks shapes.  If the shared library has not been built,
+loading fails loudly (there is no CPU fallback).
+
+The module-level functions carry the C names (``ls_setup``, ``ls_apply``, ``ls_apply_c64``,
+``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_moment``, ``ls_strain``,
+``ls_profile``, ``ls_profile_read``, ``ls_device_bytes``, ``ls_destroy``); ``Context`` wraps them
+for convenience.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblsvie.so")
+
+LS_OK = 0
+LS_ERR_ARG = -1
+LS_ERR_OOM = -2
+LS_ERR_HIP = -3
+LS_ERR_BREAKDOWN = -4
+LS_ERR_NOT_CONVERGED = -5
+LS_ERR_NONFINITE = -6
+LS_ERR_STATE = -7
+LS_PREC_C128 = 0
+LS_PREC_MIXED = 1
+LS_GREEN_EXACT = 0
+LS_GREEN_PAPER_SUM = 1
+
+ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "LS_ERR_HIP",
+               LS_ERR_BREAKDOWN: "LS_ERR_BREAKDOWN", LS_ERR_NOT_CONVERGED: "LS_ERR_NOT_CONVERGED",
+               LS_ERR_NONFINITE: "LS_ERR_NONFINITE", LS_ERR_STATE: "LS_ERR_STATE"}
+
+EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
+            "ls_solve_moment", "ls_strain", "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_last_error")
+
+
+class LsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("h", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("green_mode", ctypes.c_int), ("max_rhs", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int), ("refinements", ctypes.c_int),
+                ("status", ctypes.c_int), ("rel_res", ctypes.c_double), ("rel_res_true", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def library_path():
+    return LIB_PATH
+
+
+def load():
+    """Load liblsvie.so (raises if it is missing: build it with paper_2301_12836_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run `python -m paper_2301_12836_amd.build`); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "ls_setup": (I, [ctypes.POINTER(Grid), dp, D, P, P, dp, I, ctypes.POINTER(Options), P,
+                         ctypes.POINTER(P)]),
+        "ls_destroy": (None, [P]),
+        "ls_apply": (I, [P, I, P, P, I]),
+        "ls_apply_c64": (I, [P, I, P, P, I]),
+        "ls_rhs_moment": (I, [P, I, dp, ip, D, P]),
+        "ls_rhs_force": (I, [P, I, dp, ip, P]),
+        "ls_solve": (I, [P, I, P, I, D, I, I, P, P, ctypes.POINTER(Info)]),
+        "ls_solve_moment": (I, [P, I, dp, ip, D, D, I, I, P, ctypes.POINTER(Info)]),
+        "ls_strain": (I, [P, P, P, I]),
+        "ls_profile": (I, [P, I]),
+        "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, I]),
+        "ls_device_bytes": (ctypes.c_longlong, [P]),
+        "ls_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != LS_OK:
+        raise LsError(code, load().ls_last_error().decode())
+    return code
+
+
+def _dbl(a, n):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+    if a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _int3(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(3))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# ------------------------------------------------------------------------------------------
+# C-named entry points (torch tensors in, plain pointers to the library)
+
+def ls_setup(shape, h, C0, rho0, dC, drho, omegas, precision=LS_PREC_C128, green_mode=LS_GREEN_EXACT,
+             max_rhs=1, stream=None):
+    """dC, drho: contiguous float64 CUDA tensors [21, N3, N2, N1] and [N3, N2, N1]; returns a handle."""
+    lib = load()
+    g = Grid((ctypes.c_int * 3)(*[int(v) for v in shape]), float(h))
+    opt = Options(int(precision), int(green_mode), int(max_rhs), (ctypes.c_int * 5)())
+    c0, c0p = _dbl(C0, 36)
+    om, omp = _dbl(omegas, len(np.atleast_1d(omegas)))
+    out = ctypes.c_void_p()
+    _check(lib.ls_setup(ctypes.byref(g), c0p, float(rho0), _ptr(dC), _ptr(drho), omp, len(om), ctypes.byref(opt),
+                        ctypes.c_void_p(stream or 0), ctypes.byref(out)))
+    return out
+
+
+def ls_destroy(ctx):
+    load().ls_destroy(ctx)
+
+
+def ls_apply(ctx, i_omega, u, Au, n_rhs):
+    return _check(load().ls_apply(ctx, int(i_omega), _ptr(u), _ptr(Au), int(n_rhs)))
+
+
+def ls_apply_c64(ctx, i_omega, u, Au, n_rhs):
+    return _check(load().ls_apply_c64(ctx, int(i_omega), _ptr(u), _ptr(Au), int(n_rhs)))
+
+
+def ls_rhs_moment(ctx, i_omega, M, src, t0, b):
+    m, mp = _dbl(M, 6)
+    s, sp = _int3(src)
+    return _check(load().ls_rhs_moment(ctx, int(i_omega), mp, sp, float(t0), _ptr(b)))
+
+
+def ls_rhs_force(ctx, i_omega, F, cell, b):
+    f, fp = _dbl(F, 3)
+    s, sp = _int3(cell)
+    return _check(load().ls_rhs_force(ctx, int(i_omega), fp, sp, _ptr(b)))
+
+
+def ls_solve(ctx, i_omega, b, n_rhs, tol, maxit, precision, x0, u_out, raise_on_error=True):
+    infos = (Info * int(n_rhs))()
+    code = load().ls_solve(ctx, int(i_omega), _ptr(b), int(n_rhs), float(tol), int(maxit), int(precision),
+                           _ptr(x0), _ptr(u_out), infos)
+    if raise_on_error:
+        _check(code)
+    return code, [i.as_dict() for i in infos]
+
+
+def ls_solve_moment(ctx, i_omega, M, src, t0, tol, maxit, precision, u_out, raise_on_error=True):
+    m, mp = _dbl(M, 6)
+    s, sp = _int3(src)
+    info = Info()
+    code = load().ls_solve_moment(ctx, int(i_omega), mp, sp, float(t0), float(tol), int(maxit), int(precision),
+                                  _ptr(u_out), ctypes.byref(info))
+    if raise_on_error:
+        _check(code)
+    return code, info.as_dict()
+
+
+def ls_strain(ctx, u, eps, n_rhs):
+    return _check(load().ls_strain(ctx, _ptr(u), _ptr(eps), int(n_rhs)))
+
+
+def ls_profile(ctx, enable):
+    return _check(load().ls_profile(ctx, int(bool(enable))))
+
+
+def ls_profile_read(ctx, n_max=64):
+    names = ctypes.create_string_buffer(64 * n_max)
+    counts = (ctypes.c_int * n_max)()
+    ms = (ctypes.c_double * n_max)()
+    nf = load().ls_profile_read(ctx, names, counts, ms, n_max)
+    if nf < 0:
+        _check(nf)
+    out = {}
+    for k in range(min(nf, n_max)):
+        name = names.raw[64 * k:64 * k + 64].split(b"\0", 1)[0].decode()
+        out[name] = {"count": counts[k], "ms": ms[k]}
+    return out
+
+
+def ls_device_bytes(ctx):
+    return int(load().ls_device_bytes(ctx))
+
+
+# ------------------------------------------------------------------------------------------
+# convenience wrapper
+
+
+class Context:
+    """One grid + medium + frequency set on one GPU (owns the library context)."""
+
+    def __init__(self, shape, h, C0, rho0, dc21, drho, omegas, precision="c128", green_mode="exact", max_rhs=1,
+                 device="cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the LS library runs only on the GPU")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.shape = tuple(int(v) for v in shape)
+        n1, n2, n3 = self.shape
+        self.field_shape = (3, n3, n2, n1)
+        self.max_rhs = int(max_rhs)
+        self.omegas = list(np.atleast_1d(np.asarray(omegas, dtype=np.float64)))
+        self.mixed = precision == "mixed"
+        dc = torch.as_tensor(np.asarray(dc21, dtype=np.float64)).reshape(21, n3, n2, n1).to(self.device).contiguous()
+        dr = torch.as_tensor(np.asarray(drho, dtype=np.float64)).reshape(n3, n2, n1).to(self.device).contiguous()
+        self.stream = torch.cuda.current_stream(self.device)
+        self.handle = ls_setup(self.shape, h, C0, rho0, dc, dr, self.omegas,
+                               LS_PREC_MIXED if self.mixed else LS_PREC_C128,
+                               LS_GREEN_PAPER_SUM if green_mode == "paper_sum" else LS_GREEN_EXACT, max_rhs,
+                               self.stream.cuda_stream)
+        del dc, dr
+
+    def close(self):
+        if self.handle is not None:
+            ls_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # helpers
+    def _field(self, t, dtype=None):
+        torch = self.torch
+        t = torch.as_tensor(t, device=self.device)
+        if dtype is not None:
+            t = t.to(dtype)
+        if t.dtype not in (torch.complex128, torch.complex64):
+            t = t.to(torch.complex128)
+        t = t.contiguous()
+        if t.shape[-4:] != self.field_shape:
+            raise ValueError(f"field shape {tuple(t.shape)} does not end in {self.field_shape}")
+        nrhs = 1 if t.dim() == 4 else int(np.prod(t.shape[:-4]))
+        return t, nrhs
+
+    def empty(self, nrhs=None, dtype=None):
+        torch = self.torch
+        shape = self.field_shape if nrhs is None else (nrhs,) + self.field_shape
+        return torch.empty(shape, dtype=dtype or torch.complex128, device=self.device)
+
+    def apply(self, u, i_omega=0, out=None):
+        u, nrhs = self._field(u)
+        out = self.torch.empty_like(u) if out is None else out
+        if u.dtype == self.torch.complex64:
+            ls_apply_c64(self.handle, i_omega, u, out, nrhs)
+        else:
+            ls_apply(self.handle, i_omega, u, out, nrhs)
+        return out
+
+    def rhs_moment(self, M, src, i_omega=0, t0=0.0, out=None):
+        out = self.empty() if out is None else out
+        ls_rhs_moment(self.handle, i_omega, M, src, t0, out)
+        return out
+
+    def rhs_force(self, F, cell, i_omega=0, out=None):
+        out = self.empty() if out is None else out
+        ls_rhs_force(self.handle, i_omega, F, cell, out)
+        return out
+
+    def solve(self, b, i_omega=0, tol=1e-8, maxit=2000, precision=None, x0=None, out=None, raise_on_error=True):
+        b, nrhs = self._field(b, self.torch.complex128)
+        if x0 is not None:
+            x0, _ = self._field(x0, self.torch.complex128)
+        out = self.torch.empty_like(b) if out is None else out
+        prec = LS_PREC_MIXED if (precision or ("mixed" if self.mixed else "c128")) == "mixed" else LS_PREC_C128
+        code, infos = ls_solve(self.handle, i_omega, b, nrhs, tol, maxit, prec, x0, out, raise_on_error)
+        return out, infos
+
+    def strain(self, u):
+        u, nrhs = self._field(u, self.torch.complex128)
+        eps = self.torch.empty(u.shape[:-4] + (6,) + self.field_shape[1:], dtype=u.dtype, device=self.device)
+        ls_strain(self.handle, u, eps, nrhs)
+        return eps
+
+    def profile(self, enable=True):
+        ls_profile(self.handle, enable)
+
+    def profile_read(self):
+        return ls_profile_read(self.handle)
+
+    @property
+    def device_bytes(self):
+        return ls_device_bytes(self.handle)
+
+
+def context_from_model(model, precision="c128", max_rhs=1, green_mode="exact", device="cuda:0", omegas=None):
+    return Context(model.shape, model.h, model.C0, model.rho0, model.dc21, model.drho,
+                   model.omegas if omegas is None else omegas, precision=precision, green_mode=green_mode,
+                   max_rhs=max_rhs, device=device)

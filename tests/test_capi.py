@@ -1,0 +1,63 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry point, and rejects
+invalid arguments before touching the GPU."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2301_12836_amd import lsvie
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ls.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ls_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ls_setup", "ls_apply", "ls_solve", "ls_destroy", "ls_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lsvie.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(lsvie.EXPORTED)
+
+
+def test_setup_rejects_bad_arguments_without_a_gpu():
+    lib = lsvie.load()
+    g = lsvie.Grid((ctypes.c_int * 3)(1, 8, 8), 10.0)      # an axis with one cell
+    C0 = np.eye(6).ravel() * 1e10
+    om = np.array([1.0])
+    out = ctypes.c_void_p()
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib.ls_setup(ctypes.byref(g), C0.ctypes.data_as(dp), 2400.0, ctypes.c_void_p(1), ctypes.c_void_p(1),
+                      om.ctypes.data_as(dp), 1, None, None, ctypes.byref(out))
+    assert rc == lsvie.LS_ERR_ARG
+    assert b"grid size" in lib.ls_last_error()
+    g = lsvie.Grid((ctypes.c_int * 3)(8, 8, 8), 10.0)
+    rc = lib.ls_setup(ctypes.byref(g), C0.ctypes.data_as(dp), 2400.0, None, None, om.ctypes.data_as(dp), 1, None,
+                      None, ctypes.byref(out))
+    assert rc == lsvie.LS_ERR_ARG
+    bad = C0.copy()
+    bad[1] = 5.0                                          # C0[0][1] != C0[1][0]
+    rc = lib.ls_setup(ctypes.byref(g), bad.ctypes.data_as(dp), 2400.0, ctypes.c_void_p(1), ctypes.c_void_p(1),
+                      om.ctypes.data_as(dp), 1, None, None, ctypes.byref(out))
+    assert rc == lsvie.LS_ERR_ARG and b"symmetric" in lib.ls_last_error()
+    assert not out.value
+
+
+def test_null_context_is_rejected():
+    lib = lsvie.load()
+    assert lib.ls_apply(None, 0, None, None, 1) == lsvie.LS_ERR_ARG
+    assert lib.ls_solve(None, 0, None, 1, 1e-6, 10, 0, None, None, None) == lsvie.LS_ERR_ARG
+    lib.ls_destroy(None)
+    assert lib.ls_device_bytes(None) == 0
