@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the LS displacement solver on one MI355X.
+
+Workload (the metric's configuration): a 128^3 grid, h = 8 m, TTI stiffness (config 2's VTI tilted
+30 deg about y and rotated 45 deg about z) with Gaussian random-field perturbations (8 % on all 21
+stiffnesses, 4 % on density, correlation length 40 m, seed 2) over an isotropic background
+(3000, 1700, 2400); 6 elementary moment tensors x 8 frequencies 5-40 Hz at the centre cell;
+relative residual 1e-6 certified with the FP64 operator.
+
+One step = the whole hot path over that batch: for each frequency, the 6 moment-tensor incident
+fields, then one batched mixed-precision solve of the 6 systems (FP32 operator inside BiCGSTAB with
+FP64 inner products, FP64 iterative refinement with the FP64 operator, final FP64 true residual).
+The Green's tables for the 8 frequencies are built once before the timed region (set-up time is
+reported separately).  ``value`` is LS matvecs per second over the timed steps (every operator
+application of every right-hand side counts once, FP32 and FP64 alike).
+
+Also reported: the operator alone (c128 and c64, 1 and 6 right-hand sides), the roofline of the
+dominant kernel measured with HIP events on the library's stream during the timed steps, and the
+CPU oracle's FFT-based apply timed on the host as a baseline.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "LS matvecs/s + time-to-solve (rel res 1e-6) at 128^3; HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(fam, n1, n2, n3, L1, L2, L3, nrhs):
+    """Algorithmic HBM bytes of one launch of a kernel family (each array read or written once)."""
+    if "." not in fam:
+        return None
+    name, prec = fam.rsplit(".", 1)
+    sc = 16 if prec == "c128" else 8      # complex element
+    sr = sc // 2                          # real element
+    n = n1 * n2 * n3
+    R = nrhs
+    x_lines = 3 * R * n3 * n2             # data lines of the x passes
+    plane_cols = 3 * R * n3 * L1          # columns of the y passes
+    oct_ = (L1 // 2 + 1) * (L2 // 2 + 1) * (L3 // 2 + 1)
+    table = {
+        "contrast_strain_stress": (3 * R * n + 6 * R * n) * sc + 21 * n * sr,
+        "contrast_divergence": (6 * R * n + 3 * R * n + 3 * R * n) * sc + n * sr,
+        "fft_x_fwd": (x_lines * n1 + x_lines * L1) * sc,
+        "fft_y_fwd": (plane_cols * n2 + plane_cols * L2) * sc,
+        "fft_z_green": (2 * 3 * R * n3 * L2 * L1) * sc + 6 * oct_ * sc,
+        "fft_y_inv": (plane_cols * L2 + plane_cols * n2) * sc,
+        "fft_x_inv_epi": (x_lines * L1 + 2 * 3 * R * n) * sc,
+    }
+    return table.get(name)
+
+
+def apply_bytes(n, prec, nrhs):
+    """Algorithmic bytes of one LS matvec for nrhs right-hand sides (L = 2N): the sum over its kernels."""
+    L = 2 * n
+    return sum(kernel_bytes(f + "." + prec, n, n, n, L, L, L, nrhs) for f in
+               ("contrast_strain_stress", "contrast_divergence", "fft_x_fwd", "fft_y_fwd", "fft_z_green",
+                "fft_y_inv", "fft_x_inv_epi"))
+
+
+def time_applies(torch, ctx, u, reps):
+    out = torch.empty_like(u)
+    ctx.apply(u, 0, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.apply(u, 0, out=out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def cpu_baseline(model, reps):
+    """The oracle's FFT apply (FP64, scipy.fft on all host threads) on the same model at 5 Hz."""
+    import numpy as np
+
+    from oracle import operator as op
+    from paper_2301_12836_amd import models
+    P = op.Problem(model.shape, model.h, model.C0, model.rho0, model.dc21, model.drho, model.omegas[0])
+    P.table()   # built once, not timed (like the GPU tables)
+    u = models.random_field(model.shape, 0)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.apply_fft(u)
+    dt = (time.perf_counter() - t0) / reps
+    threads = os.cpu_count()
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    return {"value": 1.0 / dt, "unit": "matvecs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} oracle FFT applies (FP64, scipy.fft workers=-1) of the 128^3 model at 5 Hz, "
+                      f"one right-hand side; {dt:.2f} s each; Green's table built beforehand, untimed"}
+
+
+COPY_BYTES = 1 << 30
+
+
+def apply_profile(args):
+    """A short run for rocprofv3: 3 batched c64 applies, 3 batched c128 applies and 3 copies of a 1 GiB
+    buffer (a plain copy kernel of known size, to calibrate the FETCH_SIZE / WRITE_SIZE counters)."""
+    import numpy as np
+    import torch
+
+    from paper_2301_12836_amd import lsvie, models
+    model = models.config3(n=args.n)
+    nrhs = len(model.sources)
+    ctx = lsvie.context_from_model(model, precision="mixed", max_rhs=nrhs, omegas=model.omegas[-1:])
+    u = torch.from_numpy(np.stack([models.random_field(model.shape, s) for s in range(nrhs)])).to(ctx.device)
+    for dt_ in (torch.complex64, torch.complex128):
+        uu = u.to(dt_)
+        out = torch.empty_like(uu)
+        for _ in range(3):
+            ctx.apply(uu, 0, out=out)
+        torch.cuda.synchronize()
+        log(f"3 applies of {nrhs} right-hand sides in {dt_}")
+        del uu, out
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=ctx.device).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"3 copies of {COPY_BYTES} bytes")
+    ctx.close()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128, help="grid size (128 is the metric's workload)")
+    ap.add_argument("--maxit", type=int, default=3000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--mode", choices=["bench", "apply-profile"], default="bench",
+                    help="apply-profile: only a few batched applies plus a copy of known size, for counter runs")
+    args = ap.parse_args()
+    if args.mode == "apply-profile":
+        return apply_profile(args)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver shards by "
+              "(grid, frequency) jobs across GPUs, which this build does not launch", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2301_12836_amd import lsvie, models
+
+    t0 = time.perf_counter()
+    model = models.config3(n=args.n)
+    log(f"model built in {time.perf_counter() - t0:.1f} s: {model.shape}, h={model.h}, freqs={model.freqs}")
+    n = args.n
+    L = 2 * n
+    nrhs = len(model.sources)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = lsvie.context_from_model(model, precision="mixed", max_rhs=nrhs)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"context set up in {setup_s:.2f} s ({ctx.device_bytes / 2**30:.2f} GiB on the device)")
+
+    out = [ctx.empty(nrhs) for _ in model.omegas]
+    bufs = [ctx.empty(nrhs) for _ in model.omegas]
+
+    def step():
+        mv = 0
+        its = []
+        res = []
+        for iw in range(len(model.omegas)):
+            for J, (M, src) in enumerate(model.sources):
+                ctx.rhs_moment(M, src, i_omega=iw, out=bufs[iw][J])
+            x, infos = ctx.solve(bufs[iw], i_omega=iw, tol=model.tol, maxit=args.maxit, precision="mixed",
+                                 out=out[iw])
+            mv += sum(i["matvecs"] for i in infos)
+            its.append([i["iters"] for i in infos])
+            res.append(max(i["rel_res_true"] for i in infos))
+            log(f"  {model.freqs[iw]:.0f} Hz: iterations {its[-1]}, refinements "
+                f"{[i['refinements'] for i in infos]}, worst residual {res[-1]:.2e}")
+        return mv, its, res
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        mv, its, res = step()
+        torch.cuda.synchronize()
+        log(f"warmup step {w}: {time.perf_counter() - t0:.2f} s, {mv} matvecs, worst residual {max(res):.2e}")
+
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_mv = 0
+    for k in range(args.steps):
+        mv, its, res = step()
+        total_mv += mv
+        log(f"step {k}: {mv} matvecs, iterations per frequency {[max(i) for i in its]}, "
+            f"worst residual {max(res):.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = total_mv / elapsed
+    log(f"timed {args.steps} steps: {ms_per_step:.1f} ms per step, {value:.1f} matvecs/s")
+
+    # roofline of the dominant kernel family during the timed steps
+    fam_rows = []
+    for fam, d in prof.items():
+        b = kernel_bytes(fam, n, n, n, L, L, L, nrhs)
+        if b is None or d["count"] == 0:
+            continue
+        avg_ms = d["ms"] / d["count"]
+        fam_rows.append((d["ms"], fam, d["count"], avg_ms, b))
+    fam_rows.sort(reverse=True)
+    total_prof_ms = sum(d["ms"] for d in prof.values())
+    kernels = {f: {"launches": c, "avg_ms": round(a, 4), "share": round(ms / total_prof_ms, 3),
+                   "GBps": round(b / (a * 1e-3) / 1e9, 1)} for ms, f, c, a, b in fam_rows}
+    _, dom, dom_count, dom_ms, dom_bytes = fam_rows[0]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 4), "launches": dom_count}
+    log(f"dominant kernel {dom}: {dom_ms:.3f} ms avg over {dom_count} launches, {achieved:.0f} GB/s")
+
+    # the operator alone
+    rates = {}
+    for prec, dt_ in (("c128", torch.complex128), ("c64", torch.complex64)):
+        for r in (1, nrhs):
+            u = torch.from_numpy(np.stack([models.random_field(model.shape, s) for s in range(r)])).to(
+                ctx.device).to(dt_)
+            per = time_applies(torch, ctx, u, 10)
+            rates[f"{prec}_x{r}"] = {"matvecs_per_s": round(r / per, 1), "ms_per_apply": round(per * 1e3, 3),
+                                     "GBps_algorithmic": round(apply_bytes(n, prec, r) / per / 1e9, 1)}
+            del u
+    log(f"apply rates: {json.dumps(rates)}")
+    ctx.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
+        cpu = cpu_baseline(model, args.cpu_reps)
+        log(f"cpu baseline: {cpu['value']:.3f} matvecs/s on {cpu['cores']} threads")
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "matvecs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64/f64", "data": "synthetic",
+        "config": {"workload": f"{n}^3 h=8 m TTI + Gaussian random fields, 6 moment tensors x 8 frequencies "
+                               f"5-40 Hz, batched mixed-precision BiCGSTAB to rel res 1e-6",
+                   "grid": n, "rhs": nrhs * len(model.omegas), "tol": model.tol},
+        "time_to_solve_s": round(ms_per_step / 1e3, 3),
+        "setup_s": round(setup_s, 3),
+        "iterations_per_frequency": [max(i) for i in its],
+        "worst_rel_res_true": max(res),
+        "apply": rates,
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -54,7 +54,8 @@ int hip_fail(hipError_t e, const char* what);
     } while (0)
 
 // ------------------------------------------------------------------------------------------
-// per-kernel event timing (enabled by ls_profile)
+// per-kernel event timing (enabled by ls_profile); family names carry the precision
+#define LS_PNAME(T, base) (sizeof(T) == 8 ? base ".c128" : base ".c64")
 
 struct Profiler {
     bool on = false;

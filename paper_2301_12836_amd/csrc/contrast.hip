@@ -174,12 +174,12 @@ int contrast_to_work(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* work, cpx<T>*
     const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
     const T inv_h = T(1.0 / c->h);
     const double w = c->omega[i_omega];
-    c->prof.begin(c->stream, "contrast_strain_stress");
+    c->prof.begin(c->stream, LS_PNAME(T, "contrast_strain_stress"));
     hipLaunchKernelGGL((k_strain_stress<T>), dim3(nb), dim3(kThreads), 0, c->stream, u, tau, contrast_of<T>(c), nrhs,
                        c->n1, c->n2, c->n3, inv_h);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
-    c->prof.begin(c->stream, "contrast_divergence");
+    c->prof.begin(c->stream, LS_PNAME(T, "contrast_divergence"));
     hipLaunchKernelGGL((k_divergence<T>), dim3(nb), dim3(kThreads), 0, c->stream, tau, u, density_of<T>(c), work, nrhs,
                        c->n1, c->n2, c->n3, c->L1, c->L2, inv_h, T(w * w));
     c->prof.end(c->stream);

@@ -10,7 +10,10 @@
 // keeps N3 outputs; the inverse y pass keeps N2 outputs and the inverse x pass keeps N1 outputs
 // and writes Au = u - v (or v) into the compact caller array.  Every pass except the last is
 // in place, so W holds 3 N3 L2 L1 complex values per right-hand side.
-#include "fft_core.h"
+#include <cstdlib>
+#include <cstring>
+
+#include "fft_reg.h"
 
 namespace ls {
 
@@ -161,22 +164,230 @@ __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ da
 }
 
 // ------------------------------------------------------------------------------------------
+// Register four-step passes (fft_reg.h).  Each thread keeps its N2 elements of a line in registers;
+// one LDS transpose per direction replaces the Stockham stages, and a block covers 128 bytes of
+// adjacent columns (strided passes) or lines (contiguous passes).
+
+template <typename T>
+constexpr int seg_cols() {
+    return 128 / (int)sizeof(cpx<T>);
+}
+
+// usable when the transpose buffer stays within 64 KB (all lengths but c128 at 512)
+template <typename T, int L>
+constexpr bool fs_ok() {
+    return L * seg_cols<T>() * (int)sizeof(cpx<T>) <= 65536;
+}
+
+template <typename T, int L>
+constexpr int fs_threads() {
+    return seg_cols<T>() * FourStep<L>::N1;
+}
+
+// Strided pass.  Forward: natural input (n_in values), all L outputs.  Inverse: all L inputs,
+// natural output (n_out values).  In place: a block reads its columns before any write.
+template <typename T, int L, int TX, int SIGN>
+__global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_strided(cpx<T>* __restrict__ data, long long S1,
+                                                                     long long S2, long long ES, int n_in, int n_out,
+                                                                     const cpx<T>* __restrict__ tw) {
+    using F = FourStep<L>;
+    __shared__ cpx<T> lds[L * TX];
+    const int tid = threadIdx.x, t = tid % TX, q = tid / TX;
+    cpx<T>* base = data + (long long)blockIdx.z * S1 + (long long)blockIdx.y * S2 + (long long)blockIdx.x * TX + t;
+    cpx<T> v[F::N2];
+    if constexpr (SIGN < 0) {
+#pragma unroll
+        for (int j = 0; j < F::N2; ++j) {
+            const int e = q + F::N1 * j;
+            v[j] = e < n_in ? base[e * ES] : cpx<T>{T(0), T(0)};
+        }
+        fs_forward<T, L, TX, SIGN>(v, lds, tw, t, q);
+#pragma unroll
+        for (int i = 0; i < F::N2; ++i) {
+            const int k = spectral_index<L>(q, i);
+            if (k < n_out) base[k * ES] = v[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < F::N2; ++i) {
+            const int k = spectral_index<L>(q, i);
+            v[i] = k < n_in ? base[k * ES] : cpx<T>{T(0), T(0)};
+        }
+        fs_backward<T, L, TX, SIGN>(v, lds, tw, t, q);
+#pragma unroll
+        for (int j = 0; j < F::N2; ++j) {
+            const int e = q + F::N1 * j;
+            if (e < n_out) base[e * ES] = v[j];
+        }
+    }
+}
+
+// Contiguous (x) pass over TY lines per block.  MODE 0: forward in place; MODE 1: inverse with
+// out = u - v (compact); MODE 2: inverse with out = v (compact).
+template <typename T, int L, int TY, int SIGN, int MODE>
+__global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __restrict__ data, long long nlines,
+                                                                    int D2, long long S1, long long S2, int n_in,
+                                                                    int n_out, const cpx<T>* __restrict__ tw,
+                                                                    const cpx<T>* __restrict__ u,
+                                                                    cpx<T>* __restrict__ out) {
+    using F = FourStep<L>;
+    constexpr int LDP = TY + 1;
+    __shared__ cpx<T> lds[L * LDP];
+    const int tid = threadIdx.x, q = tid % F::N1, ln = tid / F::N1;
+    const long long line = (long long)blockIdx.x * TY + ln;
+    const bool valid = line < nlines;
+    const long long o1 = line / D2, o2 = line - o1 * D2;
+    cpx<T>* base = data + o1 * S1 + o2 * S2;
+    cpx<T> v[F::N2];
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int j = 0; j < F::N2; ++j) {
+            const int e = q + F::N1 * j;
+            v[j] = (valid && e < n_in) ? base[e] : cpx<T>{T(0), T(0)};
+        }
+        fs_forward<T, L, LDP, SIGN>(v, lds, tw, ln, q);
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < F::N2; ++i) {
+                const int k = spectral_index<L>(q, i);
+                if (k < n_out) base[k] = v[i];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < F::N2; ++i) {
+            const int k = spectral_index<L>(q, i);
+            v[i] = (valid && k < n_in) ? base[k] : cpx<T>{T(0), T(0)};
+        }
+        fs_backward<T, L, LDP, SIGN>(v, lds, tw, ln, q);
+        if (valid) {
+#pragma unroll
+            for (int j = 0; j < F::N2; ++j) {
+                const int e = q + F::N1 * j;
+                if (e < n_out) {
+                    const long long qq = line * n_out + e;
+                    if constexpr (MODE == 1)
+                        out[qq] = u[qq] - v[j];
+                    else
+                        out[qq] = v[j];
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void fold_index(int k, int L, int& kf, bool& flipped) {
+    flipped = k > L / 2;
+    kf = flipped ? L - k : k;
+}
+
+// Fused z pass with the four-step FFT: three components per column held in registers.  Logical
+// block order (XCD-aware): right-hand side fastest, then x tiles and y rows in mirror pairs, so the
+// blocks that read the same octant rows of G^ run together on one XCD.
+template <typename T, int L, int TX>
+__global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
+                                                                    int L2, long long CS, long long RS, long long ES,
+                                                                    int n3, const cpx<T>* __restrict__ ghat,
+                                                                    const cpx<T>* __restrict__ tw, long long nb_real) {
+    using F = FourStep<L>;
+    __shared__ cpx<T> lds[L * TX];
+    const long long lb = xcd_logical_block(blockIdx.x, nb_real);
+    if (lb < 0) return;
+    const int ntx = L1 / TX;
+    const int rhs = (int)(lb % nrhs);
+    const int xt = paired_row((int)((lb / nrhs) % ntx), ntx);
+    const int y = paired_row((int)(lb / ((long long)nrhs * ntx)), L2);
+    const int tid = threadIdx.x, t = tid % TX, q = tid / TX;
+    const int kx0 = xt * TX + t;
+    cpx<T>* base = data + (long long)rhs * RS + (long long)y * L1 + kx0;
+    cpx<T> v[3][F::N2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < F::N2; ++j) {
+            const int e = q + F::N1 * j;
+            v[c][j] = e < n3 ? base[c * CS + e * ES] : cpx<T>{T(0), T(0)};
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fs_forward<T, L, TX, -1>(v[c], lds, tw, t, q);
+
+    const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1, O3 = L / 2 + 1;
+    const long long GS = (long long)O3 * O2 * O1;
+    int kx, ky;
+    bool fx, fy;
+    fold_index(kx0, L1, kx, fx);
+    fold_index(y, L2, ky, fy);
+#pragma unroll
+    for (int i = 0; i < F::N2; ++i) {
+        int kz;
+        bool fz;
+        fold_index(spectral_index<L>(q, i), L, kz, fz);
+        const cpx<T>* g = ghat + ((long long)kz * O2 + ky) * O1 + kx;
+        const cpx<T> g11 = g[0], g22 = g[GS], g33 = g[2 * GS];
+        cpx<T> g23 = g[3 * GS], g13 = g[4 * GS], g12 = g[5 * GS];
+        if (fy != fz) g23 = T(-1) * g23;
+        if (fx != fz) g13 = T(-1) * g13;
+        if (fx != fy) g12 = T(-1) * g12;
+        const cpx<T> f1 = v[0][i], f2 = v[1][i], f3 = v[2][i];
+        v[0][i] = g11 * f1 + g12 * f2 + g13 * f3;
+        v[1][i] = g12 * f1 + g22 * f2 + g23 * f3;
+        v[2][i] = g13 * f1 + g23 * f2 + g33 * f3;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fs_backward<T, L, TX, +1>(v[c], lds, tw, t, q);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < F::N2; ++j) {
+            const int e = q + F::N1 * j;
+            if (e < n3) base[c * CS + e * ES] = v[c][j];
+        }
+}
+
+// z pass in registers where three components of N2 values fit (c64 up to 512, c128 up to 256)
+template <typename T, int L>
+constexpr bool fs_z_ok() {
+    return fs_ok<T, L>() && 3 * FourStep<L>::N2 * (int)sizeof(cpx<T>) <= 3 * 32 * 8;
+}
+
+// ------------------------------------------------------------------------------------------
 // host dispatch over the supported lengths
 
 #define LS_FOR_LENGTHS(X) X(16) X(32) X(64) X(128) X(256) X(512)
+
+// LS_FFT=stockham in the environment selects the LDS Stockham kernels everywhere (both paths are
+// kept under test); otherwise the register four-step kernels run wherever they fit.
+bool use_fourstep() {
+    static const bool fs = [] {
+        const char* e = std::getenv("LS_FFT");
+        return !(e && std::strcmp(e, "stockham") == 0);
+    }();
+    return fs;
+}
 
 template <typename T, int SIGN, int MODE>
 int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long long S1, long long S2, int n_in,
                   int n_out, const cpx<T>* tw, const cpx<T>* u, cpx<T>* out, const char* name) {
     c->prof.begin(c->stream, name);
+    const bool fs = use_fourstep();
     switch (L) {
-#define CASE(LL)                                                                                         \
-    case LL: {                                                                                           \
-        constexpr int TY = contig_lines<T, LL>();                                                        \
-        const long long nb = (nlines + TY - 1) / TY;                                                     \
-        hipLaunchKernelGGL((k_fft_contig<T, LL, TY, SIGN, MODE>), dim3((unsigned)nb), dim3(kThreads), 0, \
-                           c->stream, data, nlines, D2, S1, S2, n_in, n_out, tw, u, out);                \
-        break;                                                                                           \
+#define CASE(LL)                                                                                             \
+    case LL: {                                                                                               \
+        if constexpr (fs_ok<T, LL>()) {                                                                      \
+            if (fs) {                                                                                        \
+                constexpr int TY = seg_cols<T>();                                                            \
+                const long long nb = (nlines + TY - 1) / TY;                                                 \
+                hipLaunchKernelGGL((k_fs_contig<T, LL, TY, SIGN, MODE>), dim3((unsigned)nb),                  \
+                                   dim3(fs_threads<T, LL>()), 0, c->stream, data, nlines, D2, S1, S2, n_in,  \
+                                   n_out, tw, u, out);                                                       \
+                break;                                                                                       \
+            }                                                                                                \
+        }                                                                                                    \
+        constexpr int TY = contig_lines<T, LL>();                                                            \
+        const long long nb = (nlines + TY - 1) / TY;                                                         \
+        hipLaunchKernelGGL((k_fft_contig<T, LL, TY, SIGN, MODE>), dim3((unsigned)nb), dim3(kThreads), 0,     \
+                           c->stream, data, nlines, D2, S1, S2, n_in, n_out, tw, u, out);                    \
+        break;                                                                                               \
     }
         LS_FOR_LENGTHS(CASE)
 #undef CASE
@@ -192,14 +403,25 @@ template <typename T, int SIGN>
 int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long long S1, long long S2, long long ES,
                    int n_in, int n_out, const cpx<T>* tw, const char* name) {
     constexpr int TX = strided_cols<T>();
+    static_assert(TX == seg_cols<T>(), "both strided kernels use 128-byte column tiles");
     if (NX % TX) return fail(LS_ERR_ARG, "x length not a multiple of the column tile");
     c->prof.begin(c->stream, name);
+    const bool fs = use_fourstep();
     switch (L) {
 #define CASE(LL)                                                                                             \
-    case LL:                                                                                                 \
+    case LL: {                                                                                               \
+        if constexpr (fs_ok<T, LL>()) {                                                                      \
+            if (fs) {                                                                                        \
+                hipLaunchKernelGGL((k_fs_strided<T, LL, TX, SIGN>), dim3(NX / TX, D2, D1),                    \
+                                   dim3(fs_threads<T, LL>()), 0, c->stream, data, S1, S2, ES, n_in, n_out,   \
+                                   tw);                                                                      \
+                break;                                                                                       \
+            }                                                                                                \
+        }                                                                                                    \
         hipLaunchKernelGGL((k_fft_strided<T, LL, TX, SIGN>), dim3(NX / TX, D2, D1), dim3(kThreads), 0,        \
                            c->stream, data, S1, S2, ES, n_in, n_out, tw);                                    \
-        break;
+        break;                                                                                               \
+    }
         LS_FOR_LENGTHS(CASE)
 #undef CASE
         default:
@@ -216,15 +438,28 @@ int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<
     const long long CS = (long long)c->n3 * L2 * L1;
     const long long RS = 3 * CS;
     const long long ES = (long long)L2 * L1;
-    c->prof.begin(c->stream, "fft_z_green");
+    c->prof.begin(c->stream, LS_PNAME(T, "fft_z_green"));
+    const bool fs = use_fourstep();
     switch (L) {
-#define CASE(LL)                                                                                          \
-    case LL: {                                                                                            \
-        constexpr int TX = zpass_cols<T, LL>();                                                           \
-        if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");               \
-        hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), 0,    \
-                           c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw);                   \
-        break;                                                                                            \
+#define CASE(LL)                                                                                              \
+    case LL: {                                                                                                \
+        if constexpr (fs_z_ok<T, LL>()) {                                                                     \
+            if (fs) {                                                                                         \
+                constexpr int TX = seg_cols<T>();                                                             \
+                if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");           \
+                const long long nb = (long long)nrhs * (L1 / TX) * L2;                                        \
+                const long long nb_launch = (nb + 7) / 8 * 8;                                                 \
+                hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX>), dim3((unsigned)nb_launch),                       \
+                                   dim3(fs_threads<T, LL>()), 0, c->stream, data, nrhs, L1, L2, CS, RS, ES,   \
+                                   c->n3, ghat, tw, nb);                                                      \
+                break;                                                                                        \
+            }                                                                                                 \
+        }                                                                                                     \
+        constexpr int TX = zpass_cols<T, LL>();                                                               \
+        if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");                   \
+        hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), 0,        \
+                           c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw);                       \
+        break;                                                                                                \
     }
         LS_FOR_LENGTHS(CASE)
 #undef CASE
@@ -271,19 +506,19 @@ int fft_apply_passes(Ctx* c, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>*
     int rc_ = LS_OK;
     // x forward on the N2 x N3 data lines
     rc_ = launch_contig<T, -1, 0>(c, L1, work, rc * N3 * N2, N2, plane, L1, N1, L1, tw1, nullptr, nullptr,
-                                  "fft_x_fwd");
+                                  LS_PNAME(T, "fft_x_fwd"));
     if (rc_) return rc_;
     // y forward on all L1 columns of the N3 data planes
-    rc_ = launch_strided<T, -1>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, N2, L2, tw2, "fft_y_fwd");
+    rc_ = launch_strided<T, -1>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, N2, L2, tw2, LS_PNAME(T, "fft_y_fwd"));
     if (rc_) return rc_;
     rc_ = launch_zgreen<T>(c, work, nrhs, green_table<T>(c, i_omega), tw3);
     if (rc_) return rc_;
-    rc_ = launch_strided<T, +1>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, L2, N2, tw2, "fft_y_inv");
+    rc_ = launch_strided<T, +1>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, L2, N2, tw2, LS_PNAME(T, "fft_y_inv"));
     if (rc_) return rc_;
     if (subtract_from_u)
-        rc_ = launch_contig<T, +1, 1>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, "fft_x_inv_epi");
+        rc_ = launch_contig<T, +1, 1>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, LS_PNAME(T, "fft_x_inv_epi"));
     else
-        rc_ = launch_contig<T, +1, 2>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, "fft_x_inv_epi");
+        rc_ = launch_contig<T, +1, 2>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, LS_PNAME(T, "fft_x_inv_epi"));
     return rc_;
 }
 

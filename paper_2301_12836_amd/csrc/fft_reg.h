@@ -1,0 +1,153 @@
+// Register-resident four-step FFT of one line of length L = N1 * N2 spread over N1 threads.
+//
+// With n = n1 + N1 n2 and k = k2 + N2 k1 (n1, k1 < N1; n2, k2 < N2):
+//   X[k2 + N2 k1] = sum_{n1} W_N1^{n1 k1} W_L^{n1 k2} sum_{n2} W_N2^{n2 k2} x[n1 + N1 n2],
+// so each thread q = n1 runs a length-N2 DFT on the elements it holds, applies the twiddles
+// W_L^{q k2}, and one transpose through LDS hands every thread the N1 values of M = N2/N1 fixed k2
+// for the length-N1 DFTs.  The inverse walks the same steps backwards, so
+//   natural layout:  thread q holds x[q + N1 j],              j  < N2
+//   spectral layout: thread q holds X[(q + N1 s) + N2 k1]     at v[s N1 + k1], s < M, k1 < N1.
+// Columns: TX independent lines side by side (thread index t = tid % TX is the column), so
+// global accesses for a fixed element are TX consecutive values.
+#pragma once
+
+#include "fft_core.h"
+
+namespace ls {
+
+// cos(2 pi m / 32) for m = 0..8 (first quadrant); the rest by symmetry
+constexpr double kCos32[9] = {1.0,
+                                                  0.98078528040323044912618223613424,
+                                                  0.92387953251128675612818318939679,
+                                                  0.83146961230254523707878837761791,
+                                                  0.70710678118654752440084436210485,
+                                                  0.55557023301960222474283081394853,
+                                                  0.38268343236508977172845998403040,
+                                                  0.19509032201612826784828486847702,
+                                                  0.0};
+
+// e^{SIGN 2 pi i m / N} for N dividing 32, as a compile-time constant
+template <int SIGN, int N, typename T>
+__device__ __forceinline__ constexpr cpx<T> unit_root(int m) {
+    const int q = ((m % N) + N) % N * (32 / N);   // index on the 32-point circle
+    double c = 0.0, s = 0.0;
+    if (q <= 8) {
+        c = kCos32[q];
+        s = kCos32[8 - q];
+    } else if (q <= 16) {
+        c = -kCos32[16 - q];
+        s = kCos32[q - 8];
+    } else if (q <= 24) {
+        c = -kCos32[q - 16];
+        s = -kCos32[24 - q];
+    } else {
+        c = kCos32[32 - q];
+        s = -kCos32[q - 24];
+    }
+    return {T(c), T(SIGN * s)};
+}
+
+// In-register DFT of length N (2, 4, 8, 16, 32) with sign SIGN, natural order in and out.
+template <int SIGN, int N, typename T>
+__device__ __forceinline__ void reg_dft(cpx<T>* v) {
+    if constexpr (N <= 8) {
+        SmallDft<SIGN, N, T>::run(v);
+    } else {
+        constexpr int A = 4, B = N / A;   // n = a + A b, k = k2 + B k1
+        cpx<T> tmp[N];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            cpx<T> w[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) w[b] = v[a + A * b];
+            reg_dft<SIGN, B, T>(w);
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) tmp[a * B + k2] = (a * k2 == 0) ? w[k2] : w[k2] * unit_root<SIGN, N, T>(a * k2);
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) {
+            cpx<T> w[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) w[a] = tmp[a * B + k2];
+            SmallDft<SIGN, A, T>::run(w);
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) v[k2 + B * k1] = w[k1];
+        }
+    }
+}
+
+template <int L>
+struct FourStep {
+    static constexpr int N1 = (L == 16) ? 4 : (L == 32) ? 4 : (L == 64) ? 8 : (L == 128) ? 8 : 16;
+    static constexpr int N2 = L / N1;
+    static constexpr int M = N2 / N1;
+    static_assert(N1 * N2 == L && M * N1 == N2 && (M == 1 || M == 2), "unsupported length");
+};
+
+// twiddle W_L^{SIGN m} from the table e^{-2 pi i m / L}
+template <int SIGN, typename T>
+__device__ __forceinline__ cpx<T> tw_at(const cpx<T>* __restrict__ tw, int m) {
+    cpx<T> w = tw[m];
+    if constexpr (SIGN > 0) w.y = -w.y;
+    return w;
+}
+
+// natural -> spectral, one line per column.  lds: L * TX values, free on entry; free on exit.
+template <typename T, int L, int TX, int SIGN>
+__device__ __forceinline__ void fs_forward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int q) {
+    using F = FourStep<L>;
+    reg_dft<SIGN, F::N2, T>(v);
+#pragma unroll
+    for (int k2 = 1; k2 < F::N2; ++k2) v[k2] = v[k2] * tw_at<SIGN>(tw, q * k2);
+#pragma unroll
+    for (int k2 = 0; k2 < F::N2; ++k2) lds[(k2 * F::N1 + q) * TX + t] = v[k2];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < F::M; ++s)
+#pragma unroll
+        for (int n1 = 0; n1 < F::N1; ++n1) v[s * F::N1 + n1] = lds[((q + F::N1 * s) * F::N1 + n1) * TX + t];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < F::M; ++s) reg_dft<SIGN, F::N1, T>(v + s * F::N1);
+}
+
+// spectral -> natural (the reverse steps), same LDS contract.
+template <typename T, int L, int TX, int SIGN>
+__device__ __forceinline__ void fs_backward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int q) {
+    using F = FourStep<L>;
+#pragma unroll
+    for (int s = 0; s < F::M; ++s) reg_dft<SIGN, F::N1, T>(v + s * F::N1);
+#pragma unroll
+    for (int s = 0; s < F::M; ++s)
+#pragma unroll
+        for (int n1 = 1; n1 < F::N1; ++n1)
+            v[s * F::N1 + n1] = v[s * F::N1 + n1] * tw_at<SIGN>(tw, n1 * (q + F::N1 * s));
+#pragma unroll
+    for (int s = 0; s < F::M; ++s)
+#pragma unroll
+        for (int n1 = 0; n1 < F::N1; ++n1) lds[(n1 * F::N2 + q + F::N1 * s) * TX + t] = v[s * F::N1 + n1];
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < F::N2; ++k2) v[k2] = lds[(q * F::N2 + k2) * TX + t];
+    __syncthreads();
+    reg_dft<SIGN, F::N2, T>(v);
+}
+
+// index of the value held in slot i of thread q in the spectral layout
+template <int L>
+__device__ __forceinline__ int spectral_index(int q, int i) {
+    using F = FourStep<L>;
+    const int s = i / F::N1, k1 = i % F::N1;
+    return (q + F::N1 * s) + F::N2 * k1;
+}
+
+// XCD-aware block order: hardware hands out workgroups round-robin over the 8 XCDs, so logical
+// block b' = (b mod 8) * ceil(nb / 8) + b / 8 gives every XCD one contiguous range of logical
+// blocks (neighbours in logical order then share that XCD's L2).  Returns -1 for padding blocks.
+__device__ __forceinline__ long long xcd_logical_block(long long b, long long nb_real) {
+    const long long per = (nb_real + 7) / 8;
+    const long long lb = (b % 8) * per + b / 8;
+    return lb < nb_real ? lb : -1;
+}
+
+}  // namespace ls

@@ -414,26 +414,26 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
     if (rc) return rc;
     std::vector<double> st((size_t)nrhs * kStateLen);
     for (int it = 0; it < maxit; ++it) {
-        c->prof.begin(c->stream, "blas1");
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_update_p<T>), g, dim3(kThreads), 0, c->stream, r, p, v, m, c->state);
         c->prof.end(c->stream);
         if ((rc = apply(p, v))) return rc;
-        c->prof.begin(c->stream, "blas1");
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_dot<T>), g, dim3(kThreads), 0, c->stream, rhat, v, m, c->state, c->partials);
         c->prof.end(c->stream);
         if ((rc = finalize(c, PH_ALPHA, 2, nrhs))) return rc;
-        c->prof.begin(c->stream, "blas1");
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_update_s<T>), g, dim3(kThreads), 0, c->stream, r, v, s, m, c->state, c->partials);
         c->prof.end(c->stream);
         if ((rc = finalize(c, PH_S, 1, nrhs))) return rc;
         hipLaunchKernelGGL((k_update_x_half<T, X>), g, dim3(kThreads), 0, c->stream, x, p, m, c->state);
         hipLaunchKernelGGL(k_clear_half, dim3(1), dim3(64), 0, c->stream, c->state, nrhs);
         if ((rc = apply(s, t))) return rc;
-        c->prof.begin(c->stream, "blas1");
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_dot_ts<T>), g, dim3(kThreads), 0, c->stream, t, s, m, c->state, c->partials);
         c->prof.end(c->stream);
         if ((rc = finalize(c, PH_OMEGA, 3, nrhs))) return rc;
-        c->prof.begin(c->stream, "blas1");
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_update_xr<T, X>), g, dim3(kThreads), 0, c->stream, x, p, s, t, r, rhat, m, c->state,
                            c->partials);
         c->prof.end(c->stream);

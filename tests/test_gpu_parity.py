@@ -223,3 +223,39 @@ def test_error_paths_on_gpu():
     x, infos = ctx.solve(torch.zeros_like(b), tol=1e-8)
     assert float(torch.abs(x).max()) == 0.0 and infos[0]["iters"] == 0
     ctx.close()
+
+
+def test_apply_config2_full_field_c128_and_c64():
+    """64^3 layered VTI (FFT length 128): full-field parity of both operator precisions."""
+    m = models.config2()
+    ctx, (P,) = ctx_and_problem(m, precision="mixed")
+    u = models.random_field(m.shape, seed=11)
+    want = P.apply_fft(u)
+    got = to_np(ctx.apply(torch.from_numpy(u)))
+    got32 = to_np(ctx.apply(torch.from_numpy(u).to(torch.complex64)))
+    print("config2 c128", rel(got, want), "c64", rel(got32, want), flush=True)
+    assert rel(got, want) < 1e-10
+    assert rel(got32, want) < 1e-5
+    ctx.close()
+
+
+def test_apply_config3_sampled_cells_batched():
+    """128^3 TTI random medium, 6 right-hand sides in one launch (the benchmark's configuration):
+    sampled output cells against the oracle's direct per-cell sums."""
+    m = models.config3()
+    omega = m.omegas[-1]
+    ctx = lsvie.context_from_model(m, precision="mixed", max_rhs=6, omegas=[omega])
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, omega)
+    rng = np.random.default_rng(5)
+    cells = np.concatenate([rng.integers(0, 128, size=(4, 3)), [[0, 0, 0], [127, 127, 127], [64, 64, 64]]])
+    u = np.stack([models.random_field(m.shape, seed=s) for s in range(6)])
+    got = to_np(ctx.apply(torch.from_numpy(u)))
+    got32 = to_np(ctx.apply(torch.from_numpy(u).to(torch.complex64)))
+    for r in (0, 5):
+        want = P.apply_bruteforce(u[r], cells)
+        g = got[r][:, cells[:, 2], cells[:, 1], cells[:, 0]].T
+        g32 = got32[r][:, cells[:, 2], cells[:, 1], cells[:, 0]].T
+        print("config3 rhs", r, "c128", rel(g, want), "c64", rel(g32, want), flush=True)
+        assert rel(g, want) < 1e-10
+        assert rel(g32, want) < 1e-5
+    ctx.close()
