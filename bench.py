@@ -69,6 +69,34 @@ def apply_bytes(n, prec, nrhs):
                 "fft_y_inv", "fft_x_inv_epi"))
 
 
+def source_hash():
+    """sha256 (first 16 hex digits) of the HIP sources, to match counter summaries to the built kernels."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2301_12836_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h")):
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family):
+    """HBM bytes per launch of a kernel family from the committed rocprofv3 counter summary, or None when
+    the summary was taken from different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_config3_apply.txt")
+    if not os.path.exists(path):
+        return None
+    lines = open(path).read().splitlines()
+    tag = [ln.split()[1] for ln in lines if ln.startswith("source_sha256 ")]
+    if not tag or tag[0] != source_hash():
+        return None
+    for ln in lines:
+        parts = ln.split()
+        if len(parts) == 3 and parts[0] == "traffic" and parts[1] == family:
+            return float(parts[2])
+    return None
+
+
 def time_applies(torch, ctx, u, reps):
     out = torch.empty_like(u)
     ctx.apply(u, 0, out=out)
@@ -227,8 +255,9 @@ def main():
                    "GBps": round(b / (a * 1e-3) / 1e9, 1)} for ms, f, c, a, b in fam_rows}
     _, dom, dom_count, dom_ms, dom_bytes = fam_rows[0]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 4), "launches": dom_count}
     log(f"dominant kernel {dom}: {dom_ms:.3f} ms avg over {dom_count} launches, {achieved:.0f} GB/s")
 

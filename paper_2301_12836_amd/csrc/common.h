@@ -92,7 +92,7 @@ struct Ctx {
     float* dc32 = nullptr;
     float* drho32 = nullptr;
 
-    // k-space Green's tables per frequency: octant [6][L3/2+1][L2/2+1][L1/2+1], already scaled by
+    // k-space Green's tables per frequency: octant [L3/2+1][L2/2+1][L1/2+1][6], already scaled by
     // 1/(L1 L2 L3) so the inverse FFT needs no normalisation
     std::vector<z128*> ghat;
     std::vector<z64*> ghat32;

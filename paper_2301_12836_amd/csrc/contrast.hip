@@ -5,7 +5,7 @@
 // divergence of the contrast stress is -E^T tau.  Per cell, tau = dC eps with dC the symmetric
 // 6x6 of the cell (21 packed values).  The first kernel writes tau for every cell, the second
 // forms f and writes it straight into the zero-padded FFT work buffer.
-#include "common.h"
+#include "fft_reg.h"
 
 namespace ls {
 
@@ -66,8 +66,9 @@ __global__ __launch_bounds__(kThreads) void k_strain_stress(const cpx<T>* __rest
                                                             const T* __restrict__ dc, int nrhs, int N1, int N2,
                                                             int N3, T inv_h) {
     const long long n = (long long)N1 * N2 * N3;
-    const long long p = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (p >= n) return;
+    const long long lb = xcd_logical_block(blockIdx.x, (n + kThreads - 1) / kThreads);
+    const long long p = lb * kThreads + threadIdx.x;
+    if (lb < 0 || p >= n) return;
     const int i = (int)(p % N1);
     const int j = (int)((p / N1) % N2);
     const int k = (int)(p / ((long long)N1 * N2));
@@ -96,8 +97,9 @@ __global__ __launch_bounds__(kThreads) void k_divergence(const cpx<T>* __restric
                                                          int nrhs, int N1, int N2, int N3, int L1, int L2, T inv_h,
                                                          T w2) {
     const long long n = (long long)N1 * N2 * N3;
-    const long long p = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (p >= n) return;
+    const long long lb = xcd_logical_block(blockIdx.x, (n + kThreads - 1) / kThreads);
+    const long long p = lb * kThreads + threadIdx.x;
+    if (lb < 0 || p >= n) return;
     const int i = (int)(p % N1);
     const int j = (int)((p / N1) % N2);
     const int k = (int)(p / ((long long)N1 * N2));
@@ -171,7 +173,8 @@ const float* density_of<float>(const Ctx* c) { return c->drho32; }
 template <typename T>
 int contrast_to_work(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* work, cpx<T>* tau, int nrhs) {
     const long long n = c->ncell;
-    const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
+    // XCD-aware order: grid padded to a multiple of 8, neighbouring cells share an L2
+    const unsigned nb = (unsigned)(((n + kThreads - 1) / kThreads + 7) / 8 * 8);
     const T inv_h = T(1.0 / c->h);
     const double w = c->omega[i_omega];
     c->prof.begin(c->stream, LS_PNAME(T, "contrast_strain_stress"));

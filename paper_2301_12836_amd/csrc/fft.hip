@@ -110,8 +110,27 @@ __device__ __forceinline__ int paired_row(int by, int L2) {
     return (by & 1) ? m : L2 - m;
 }
 
+// the six table entries of one k-point: 48 (c64) or 96 (c128) contiguous bytes, read as 16-byte vectors
+__device__ __forceinline__ void load_g6(const z64* __restrict__ ghat, long long idx, z64 g[6]) {
+    const float4* p = reinterpret_cast<const float4*>(ghat + idx * 6);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float4 a = p[k];
+        g[2 * k] = {a.x, a.y};
+        g[2 * k + 1] = {a.z, a.w};
+    }
+}
+__device__ __forceinline__ void load_g6(const z128* __restrict__ ghat, long long idx, z128 g[6]) {
+    const double2* p = reinterpret_cast<const double2*>(ghat + idx * 6);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double2 a = p[k];
+        g[k] = {a.x, a.y};
+    }
+}
+
 // Fused z pass: forward z FFT of the three components, v^ = G^(k) f^, inverse z FFT.
-// G^ holds the octant [6][L3/2+1][L2/2+1][L1/2+1] (Voigt order 11,22,33,23,13,12); under
+// G^ holds the octant [L3/2+1][L2/2+1][L1/2+1][6] (Voigt order 11,22,33,23,13,12); under
 // k_a -> L_a - k_a an off-diagonal component ij changes sign once for each of i, j equal to a.
 template <typename T, int L, int TX>
 __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1, int L2,
@@ -135,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ da
     lds_fft<T, L, NL, NL, kThreads, -1>(s, tw, tid);
 
     const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1, O3 = L / 2 + 1;
-    const long long GS = (long long)O3 * O2 * O1;
+    (void)O3;
     const bool fy = y > L2 / 2;
     const int ky = fy ? L2 - y : y;
     for (int idx = tid; idx < L * TX; idx += kThreads) {
@@ -143,9 +162,10 @@ __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ da
         const int kx0 = x0 + t;
         const bool fx = kx0 > L1 / 2, fz = kz0 > L / 2;
         const int kx = fx ? L1 - kx0 : kx0, kz = fz ? L - kz0 : kz0;
-        const cpx<T>* g = ghat + ((long long)kz * O2 + ky) * O1 + kx;
-        const cpx<T> g11 = g[0], g22 = g[GS], g33 = g[2 * GS];
-        cpx<T> g23 = g[3 * GS], g13 = g[4 * GS], g12 = g[5 * GS];
+        cpx<T> g[6];
+        load_g6(ghat, ((long long)kz * O2 + ky) * O1 + kx, g);
+        const cpx<T> g11 = g[0], g22 = g[1], g33 = g[2];
+        cpx<T> g23 = g[3], g13 = g[4], g12 = g[5];
         if (fy != fz) g23 = T(-1) * g23;
         if (fx != fz) g13 = T(-1) * g13;
         if (fx != fy) g12 = T(-1) * g12;
@@ -184,24 +204,40 @@ constexpr int fs_threads() {
     return seg_cols<T>() * FourStep<L>::N1;
 }
 
+// Twiddles e^{-2 pi i m / L} copied to LDS once per block (cheaper than per-use global loads).
+template <typename T, int L>
+__device__ __forceinline__ void stage_twiddles(cpx<T>* tws, const cpx<T>* __restrict__ tw, int tid, int nthreads) {
+    for (int m = tid; m < L; m += nthreads) tws[m] = tw[m];
+}
+
+// Natural-layout element j of a line is zero by construction (PRUNE: the data occupy the first
+// half, n < L/2, which always holds for the zero-padded convolution) or beyond n_in.
+template <int L, bool PRUNE>
+__device__ __forceinline__ constexpr bool half_slot(int j) {
+    return PRUNE && j >= FourStep<L>::N2 / 2;
+}
+
 // Strided pass.  Forward: natural input (n_in values), all L outputs.  Inverse: all L inputs,
 // natural output (n_out values).  In place: a block reads its columns before any write.
-template <typename T, int L, int TX, int SIGN>
+template <typename T, int L, int TX, int SIGN, bool PRUNE>
 __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_strided(cpx<T>* __restrict__ data, long long S1,
                                                                      long long S2, long long ES, int n_in, int n_out,
                                                                      const cpx<T>* __restrict__ tw) {
     using F = FourStep<L>;
     __shared__ cpx<T> lds[L * TX];
+    __shared__ cpx<T> tws[L];
     const int tid = threadIdx.x, t = tid % TX, q = tid / TX;
+    stage_twiddles<T, L>(tws, tw, tid, TX * F::N1);
     cpx<T>* base = data + (long long)blockIdx.z * S1 + (long long)blockIdx.y * S2 + (long long)blockIdx.x * TX + t;
     cpx<T> v[F::N2];
     if constexpr (SIGN < 0) {
 #pragma unroll
         for (int j = 0; j < F::N2; ++j) {
             const int e = q + F::N1 * j;
-            v[j] = e < n_in ? base[e * ES] : cpx<T>{T(0), T(0)};
+            v[j] = (!half_slot<L, PRUNE>(j) && e < n_in) ? base[e * ES] : cpx<T>{T(0), T(0)};
         }
-        fs_forward<T, L, TX, SIGN>(v, lds, tw, t, q);
+        __syncthreads();
+        fs_forward<T, L, TX, SIGN>(v, lds, tws, t, q);
 #pragma unroll
         for (int i = 0; i < F::N2; ++i) {
             const int k = spectral_index<L>(q, i);
@@ -213,18 +249,19 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_strided(cpx<T>* __r
             const int k = spectral_index<L>(q, i);
             v[i] = k < n_in ? base[k * ES] : cpx<T>{T(0), T(0)};
         }
-        fs_backward<T, L, TX, SIGN>(v, lds, tw, t, q);
+        __syncthreads();
+        fs_backward<T, L, TX, SIGN>(v, lds, tws, t, q);
 #pragma unroll
         for (int j = 0; j < F::N2; ++j) {
             const int e = q + F::N1 * j;
-            if (e < n_out) base[e * ES] = v[j];
+            if (!half_slot<L, PRUNE>(j) && e < n_out) base[e * ES] = v[j];
         }
     }
 }
 
 // Contiguous (x) pass over TY lines per block.  MODE 0: forward in place; MODE 1: inverse with
 // out = u - v (compact); MODE 2: inverse with out = v (compact).
-template <typename T, int L, int TY, int SIGN, int MODE>
+template <typename T, int L, int TY, int SIGN, int MODE, bool PRUNE>
 __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __restrict__ data, long long nlines,
                                                                     int D2, long long S1, long long S2, int n_in,
                                                                     int n_out, const cpx<T>* __restrict__ tw,
@@ -233,7 +270,9 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
     using F = FourStep<L>;
     constexpr int LDP = TY + 1;
     __shared__ cpx<T> lds[L * LDP];
+    __shared__ cpx<T> tws[L];
     const int tid = threadIdx.x, q = tid % F::N1, ln = tid / F::N1;
+    stage_twiddles<T, L>(tws, tw, tid, TY * F::N1);
     const long long line = (long long)blockIdx.x * TY + ln;
     const bool valid = line < nlines;
     const long long o1 = line / D2, o2 = line - o1 * D2;
@@ -243,9 +282,10 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
 #pragma unroll
         for (int j = 0; j < F::N2; ++j) {
             const int e = q + F::N1 * j;
-            v[j] = (valid && e < n_in) ? base[e] : cpx<T>{T(0), T(0)};
+            v[j] = (!half_slot<L, PRUNE>(j) && valid && e < n_in) ? base[e] : cpx<T>{T(0), T(0)};
         }
-        fs_forward<T, L, LDP, SIGN>(v, lds, tw, ln, q);
+        __syncthreads();
+        fs_forward<T, L, LDP, SIGN>(v, lds, tws, ln, q);
         if (valid) {
 #pragma unroll
             for (int i = 0; i < F::N2; ++i) {
@@ -259,12 +299,13 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
             const int k = spectral_index<L>(q, i);
             v[i] = (valid && k < n_in) ? base[k] : cpx<T>{T(0), T(0)};
         }
-        fs_backward<T, L, LDP, SIGN>(v, lds, tw, ln, q);
+        __syncthreads();
+        fs_backward<T, L, LDP, SIGN>(v, lds, tws, ln, q);
         if (valid) {
 #pragma unroll
             for (int j = 0; j < F::N2; ++j) {
                 const int e = q + F::N1 * j;
-                if (e < n_out) {
+                if (!half_slot<L, PRUNE>(j) && e < n_out) {
                     const long long qq = line * n_out + e;
                     if constexpr (MODE == 1)
                         out[qq] = u[qq] - v[j];
@@ -283,7 +324,7 @@ __device__ __forceinline__ void fold_index(int k, int L, int& kf, bool& flipped)
 
 // Fused z pass with the four-step FFT: three components per column held in registers.  Logical
 // block order (XCD-aware): right-hand side fastest, then x tiles and y rows in mirror pairs, so the
-// blocks that read the same octant rows of G^ run together on one XCD.
+// blocks that read the same octant rows of G^ run together on one XCD.  The data occupy z < n3 <= L/2.
 template <typename T, int L, int TX>
 __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
@@ -291,13 +332,15 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_zgreen(cpx<T>* __re
                                                                     const cpx<T>* __restrict__ tw, long long nb_real) {
     using F = FourStep<L>;
     __shared__ cpx<T> lds[L * TX];
+    __shared__ cpx<T> tws[L];
     const long long lb = xcd_logical_block(blockIdx.x, nb_real);
     if (lb < 0) return;
+    const int tid = threadIdx.x, t = tid % TX, q = tid / TX;
+    stage_twiddles<T, L>(tws, tw, tid, TX * F::N1);
     const int ntx = L1 / TX;
     const int rhs = (int)(lb % nrhs);
     const int xt = paired_row((int)((lb / nrhs) % ntx), ntx);
     const int y = paired_row((int)(lb / ((long long)nrhs * ntx)), L2);
-    const int tid = threadIdx.x, t = tid % TX, q = tid / TX;
     const int kx0 = xt * TX + t;
     cpx<T>* base = data + (long long)rhs * RS + (long long)y * L1 + kx0;
     cpx<T> v[3][F::N2];
@@ -306,13 +349,14 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_zgreen(cpx<T>* __re
 #pragma unroll
         for (int j = 0; j < F::N2; ++j) {
             const int e = q + F::N1 * j;
-            v[c][j] = e < n3 ? base[c * CS + e * ES] : cpx<T>{T(0), T(0)};
+            v[c][j] = (!half_slot<L, true>(j) && e < n3) ? base[c * CS + e * ES] : cpx<T>{T(0), T(0)};
         }
+    __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fs_forward<T, L, TX, -1>(v[c], lds, tw, t, q);
+    for (int c = 0; c < 3; ++c) fs_forward<T, L, TX, -1>(v[c], lds, tws, t, q);
 
     const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1, O3 = L / 2 + 1;
-    const long long GS = (long long)O3 * O2 * O1;
+    (void)O3;
     int kx, ky;
     bool fx, fy;
     fold_index(kx0, L1, kx, fx);
@@ -322,9 +366,10 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_zgreen(cpx<T>* __re
         int kz;
         bool fz;
         fold_index(spectral_index<L>(q, i), L, kz, fz);
-        const cpx<T>* g = ghat + ((long long)kz * O2 + ky) * O1 + kx;
-        const cpx<T> g11 = g[0], g22 = g[GS], g33 = g[2 * GS];
-        cpx<T> g23 = g[3 * GS], g13 = g[4 * GS], g12 = g[5 * GS];
+        cpx<T> g[6];
+        load_g6(ghat, ((long long)kz * O2 + ky) * O1 + kx, g);
+        const cpx<T> g11 = g[0], g22 = g[1], g33 = g[2];
+        cpx<T> g23 = g[3], g13 = g[4], g12 = g[5];
         if (fy != fz) g23 = T(-1) * g23;
         if (fx != fz) g13 = T(-1) * g13;
         if (fx != fy) g12 = T(-1) * g12;
@@ -334,13 +379,13 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_zgreen(cpx<T>* __re
         v[2][i] = g13 * f1 + g23 * f2 + g33 * f3;
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fs_backward<T, L, TX, +1>(v[c], lds, tw, t, q);
+    for (int c = 0; c < 3; ++c) fs_backward<T, L, TX, +1>(v[c], lds, tws, t, q);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int j = 0; j < F::N2; ++j) {
             const int e = q + F::N1 * j;
-            if (e < n3) base[c * CS + e * ES] = v[c][j];
+            if (!half_slot<L, true>(j) && e < n3) base[c * CS + e * ES] = v[c][j];
         }
 }
 
@@ -365,7 +410,7 @@ bool use_fourstep() {
     return fs;
 }
 
-template <typename T, int SIGN, int MODE>
+template <typename T, int SIGN, int MODE, bool PRUNE>
 int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long long S1, long long S2, int n_in,
                   int n_out, const cpx<T>* tw, const cpx<T>* u, cpx<T>* out, const char* name) {
     c->prof.begin(c->stream, name);
@@ -377,7 +422,7 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
             if (fs) {                                                                                        \
                 constexpr int TY = seg_cols<T>();                                                            \
                 const long long nb = (nlines + TY - 1) / TY;                                                 \
-                hipLaunchKernelGGL((k_fs_contig<T, LL, TY, SIGN, MODE>), dim3((unsigned)nb),                  \
+                hipLaunchKernelGGL((k_fs_contig<T, LL, TY, SIGN, MODE, PRUNE>), dim3((unsigned)nb),                  \
                                    dim3(fs_threads<T, LL>()), 0, c->stream, data, nlines, D2, S1, S2, n_in,  \
                                    n_out, tw, u, out);                                                       \
                 break;                                                                                       \
@@ -399,7 +444,7 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
     return LS_OK;
 }
 
-template <typename T, int SIGN>
+template <typename T, int SIGN, bool PRUNE>
 int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long long S1, long long S2, long long ES,
                    int n_in, int n_out, const cpx<T>* tw, const char* name) {
     constexpr int TX = strided_cols<T>();
@@ -412,7 +457,7 @@ int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long lon
     case LL: {                                                                                               \
         if constexpr (fs_ok<T, LL>()) {                                                                      \
             if (fs) {                                                                                        \
-                hipLaunchKernelGGL((k_fs_strided<T, LL, TX, SIGN>), dim3(NX / TX, D2, D1),                    \
+                hipLaunchKernelGGL((k_fs_strided<T, LL, TX, SIGN, PRUNE>), dim3(NX / TX, D2, D1),                    \
                                    dim3(fs_threads<T, LL>()), 0, c->stream, data, S1, S2, ES, n_in, n_out,   \
                                    tw);                                                                      \
                 break;                                                                                       \
@@ -505,20 +550,20 @@ int fft_apply_passes(Ctx* c, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>*
     const cpx<T>* tw3 = twiddles<T>(c, L3);
     int rc_ = LS_OK;
     // x forward on the N2 x N3 data lines
-    rc_ = launch_contig<T, -1, 0>(c, L1, work, rc * N3 * N2, N2, plane, L1, N1, L1, tw1, nullptr, nullptr,
+    rc_ = launch_contig<T, -1, 0, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, N1, L1, tw1, nullptr, nullptr,
                                   LS_PNAME(T, "fft_x_fwd"));
     if (rc_) return rc_;
     // y forward on all L1 columns of the N3 data planes
-    rc_ = launch_strided<T, -1>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, N2, L2, tw2, LS_PNAME(T, "fft_y_fwd"));
+    rc_ = launch_strided<T, -1, true>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, N2, L2, tw2, LS_PNAME(T, "fft_y_fwd"));
     if (rc_) return rc_;
     rc_ = launch_zgreen<T>(c, work, nrhs, green_table<T>(c, i_omega), tw3);
     if (rc_) return rc_;
-    rc_ = launch_strided<T, +1>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, L2, N2, tw2, LS_PNAME(T, "fft_y_inv"));
+    rc_ = launch_strided<T, +1, true>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, L2, N2, tw2, LS_PNAME(T, "fft_y_inv"));
     if (rc_) return rc_;
     if (subtract_from_u)
-        rc_ = launch_contig<T, +1, 1>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, LS_PNAME(T, "fft_x_inv_epi"));
+        rc_ = launch_contig<T, +1, 1, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, LS_PNAME(T, "fft_x_inv_epi"));
     else
-        rc_ = launch_contig<T, +1, 2>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, LS_PNAME(T, "fft_x_inv_epi"));
+        rc_ = launch_contig<T, +1, 2, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, LS_PNAME(T, "fft_x_inv_epi"));
     return rc_;
 }
 
@@ -527,12 +572,12 @@ template <typename T>
 int fft_full_3d_forward(Ctx* c, cpx<T>* buf) {
     const int L1 = c->L1, L2 = c->L2, L3 = c->L3;
     const long long plane = (long long)L2 * L1;
-    int rc_ = launch_contig<T, -1, 0>(c, L1, buf, (long long)L3 * L2, L2, plane, L1, L1, L1, twiddles<T>(c, L1),
+    int rc_ = launch_contig<T, -1, 0, false>(c, L1, buf, (long long)L3 * L2, L2, plane, L1, L1, L1, twiddles<T>(c, L1),
                                       nullptr, nullptr, "table_fft_x");
     if (rc_) return rc_;
-    rc_ = launch_strided<T, -1>(c, L2, buf, L1, 1, L3, plane, 0, L1, L2, L2, twiddles<T>(c, L2), "table_fft_y");
+    rc_ = launch_strided<T, -1, false>(c, L2, buf, L1, 1, L3, plane, 0, L1, L2, L2, twiddles<T>(c, L2), "table_fft_y");
     if (rc_) return rc_;
-    return launch_strided<T, -1>(c, L3, buf, L1, L2, 1, 0, L1, plane, L3, L3, twiddles<T>(c, L3), "table_fft_z");
+    return launch_strided<T, -1, false>(c, L3, buf, L1, L2, 1, 0, L1, plane, L3, L3, twiddles<T>(c, L3), "table_fft_z");
 }
 
 template int fft_apply_passes<double>(Ctx*, int, z128*, const z128*, z128*, int, bool);

@@ -139,9 +139,10 @@ __global__ void k_sample_table(z128* __restrict__ buf, int comp, int L1, int L2,
     buf[q] = v;
 }
 
-// copy the octant k_a <= L_a/2 of one transformed component, scaled by 1/(L1 L2 L3)
-__global__ void k_extract_octant(const z128* __restrict__ buf, z128* __restrict__ g, z64* __restrict__ g32, int L1,
-                                 int L2, int L3, double scale) {
+// copy the octant k_a <= L_a/2 of one transformed component, scaled by 1/(L1 L2 L3), into the
+// component-interleaved table [L3/2+1][L2/2+1][L1/2+1][6]
+__global__ void k_extract_octant(const z128* __restrict__ buf, z128* __restrict__ g, z64* __restrict__ g32, int comp,
+                                 int L1, int L2, int L3, double scale) {
     const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1, O3 = L3 / 2 + 1;
     const long long total = (long long)O1 * O2 * O3;
     const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -149,8 +150,8 @@ __global__ void k_extract_octant(const z128* __restrict__ buf, z128* __restrict_
     const int x = (int)(q % O1), y = (int)((q / O1) % O2), z = (int)(q / ((long long)O1 * O2));
     const z128 v = buf[((long long)z * L2 + y) * L1 + x];
     const z128 s = {v.x * scale, v.y * scale};
-    g[q] = s;
-    if (g32) g32[q] = {(float)s.x, (float)s.y};
+    g[q * 6 + comp] = s;
+    if (g32) g32[q * 6 + comp] = {(float)s.x, (float)s.y};
 }
 
 // b_i(x) = phase * sum_q [ G_ij(x - q) F_j(q)  (x != q);  self/h^3 F_i(q)  (x == q) ]
@@ -206,7 +207,7 @@ int build_green_tables(Ctx* c) {
             rc = fft_full_3d_forward<double>(c, buf);
             if (rc) break;
             hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((oct + 255) / 256)), dim3(256), 0, c->stream, buf,
-                               c->ghat[i] + comp * oct, c->mixed ? c->ghat32[i] + comp * oct : nullptr, L1, L2, L3,
+                               c->ghat[i], c->mixed ? c->ghat32[i] : nullptr, comp, L1, L2, L3,
                                1.0 / (double)total);
             if (hipGetLastError() != hipSuccess) rc = fail(LS_ERR_HIP, "octant extraction launch failed");
         }
