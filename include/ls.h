@@ -99,6 +99,11 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0,
 /* Release every device allocation of the context (synchronises its stream). NULL is a no-op. */
 void ls_destroy(ls_ctx* ctx);
 
+/* Replace the medium's contrast (same layout and background fold as ls_setup) without rebuilding the
+ * Green's tables, which depend only on the background and the frequencies.  dC, drho: device, copied.
+ * Synchronises the stream. */
+int ls_set_contrast(ls_ctx* ctx, const double* dC, const double* drho);
+
 /* One LS matvec Au = u - Gconv B u at frequency omega[i_omega] (Eq 19-21), for n_rhs fields
  * (1 <= n_rhs <= max_rhs).  u, Au: device c128 arrays [n_rhs][3][N3][N2][N1]; they must not
  * overlap.  Asynchronous. */
@@ -138,6 +143,30 @@ int ls_solve_moment(ls_ctx* ctx, int i_omega, const double M[6], const int src[3
 
 /* Voigt engineering strain of n_rhs fields (Eq 17-18): eps device c128 [n_rhs][6][N3][N2][N1]. */
 int ls_strain(ls_ctx* ctx, const void* u, void* eps, int n_rhs);
+
+/* Adjoint side of the operator (for gradients of misfits through the solution of Eq 21).
+ * Both Gconv (the Green's tensor is symmetric and even) and B are symmetric, so the transpose is
+ * A^T = I - B Gconv: the Green's convolution first, then the contrast.  The conjugate transpose is
+ * A^H y = conj(A^T conj(y)).
+ *
+ * ls_apply_T: ATy = A^T y for n_rhs c128 fields (y, ATy must not overlap).  Asynchronous.
+ * ls_convolve: out = Gconv f (f a force density on the cells, c128): the zero-padded convolution
+ *   with h^3 G of Eq 21 alone.  Asynchronous.
+ * ls_solve_T: BiCGSTAB on A^T x = b, with the same contract as ls_solve (FP64 true residual of the
+ *   transposed system; mixed precision runs the FP32 transposed operator inside FP64 refinement).
+ * ls_grad_contrast: for forward fields u and fields mu (both device c128 [n_rhs][3][N3][N2][N1]),
+ *   accumulate into the device arrays g_dC [21][N3][N2][N1] and g_drho [N3][N2][N1] (doubles):
+ *     g_dC[JK] += -Re[conj(eps_J(mu)) eps_K(u) + (J != K) conj(eps_K(mu)) eps_J(u)]   (packed J <= K)
+ *     g_drho   += w^2 Re[sum_c conj(mu_c) u_c]
+ *   summed over the n_rhs pairs.  With r = P u - d the receiver residual of the misfit
+ *   J = 1/2 ||P u - d||^2, lambda_bar solving A^T lambda_bar = conj(P^H r) and mu = conj(Gconv
+ *   lambda_bar), these are dJ/d(dC) and dJ/d(drho) of one frequency.  Asynchronous. */
+int ls_apply_T(ls_ctx* ctx, int i_omega, const void* y, void* ATy, int n_rhs);
+int ls_convolve(ls_ctx* ctx, int i_omega, const void* f, void* out, int n_rhs);
+int ls_solve_T(ls_ctx* ctx, int i_omega, const void* b, int n_rhs, double tol, int maxit, int precision,
+               const void* x0, void* x_out, ls_info* info);
+int ls_grad_contrast(ls_ctx* ctx, int i_omega, const void* u, const void* mu, int n_rhs, double* g_dC,
+                     double* g_drho);
 
 /* Per-kernel timing of the library's own launches.  ls_profile(ctx, 1) starts recording a
  * HIP event pair around every kernel launch on the context's stream (at most a fixed number

@@ -30,4 +30,4 @@ operator).  The paper prints no numerical values for any worked example (its
 figures are placeholders), so no pin compares against a printed number.
 """
 
-from . import green, operator, solve  # noqa: F401
+from . import adjoint, green, operator, solve  # noqa: F401

@@ -91,7 +91,7 @@ static void release(Ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
-                    c->xd, c->bd, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
+                    c->xd, c->bd, c->gs, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
                     c->state, c->stage, c->red};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -115,6 +115,30 @@ int apply_op(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* Au, int nrhs) {
 
 template int apply_op<double>(Ctx*, int, const z128*, z128*, int);
 template int apply_op<float>(Ctx*, int, const z64*, z64*, int);
+
+// A^T y = y - B (Gconv y): Gconv and B are both symmetric, so the transpose applies the Green's
+// convolution first and the contrast second
+template <typename T>
+int apply_T_op(Ctx* c, int i_omega, const cpx<T>* y, cpx<T>* ATy, int nrhs) {
+    cpx<T>* work = (cpx<T>*)c->work;
+    cpx<T>* g = (cpx<T>*)c->gs;
+    int rc = to_work<T>(c, y, work, nrhs);
+    if (rc) return rc;
+    rc = fft_apply_passes<T>(c, i_omega, work, nullptr, g, nrhs, false);
+    if (rc) return rc;
+    return contrast_transposed_epilogue<T>(c, i_omega, g, y, ATy, (cpx<T>*)c->tau, nrhs);
+}
+
+template <typename T>
+int convolve_op(Ctx* c, int i_omega, const cpx<T>* f, cpx<T>* out, int nrhs) {
+    int rc = to_work<T>(c, f, (cpx<T>*)c->work, nrhs);
+    if (rc) return rc;
+    return fft_apply_passes<T>(c, i_omega, (cpx<T>*)c->work, nullptr, out, nrhs, false);
+}
+
+template int apply_T_op<double>(Ctx*, int, const z128*, z128*, int);
+template int apply_T_op<float>(Ctx*, int, const z64*, z64*, int);
+template int convolve_op<double>(Ctx*, int, const z128*, z128*, int);
 
 }  // namespace ls
 
@@ -248,6 +272,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     z128** v128[] = {&c->r, &c->rhat, &c->p, &c->v, &c->s, &c->t};
     for (auto pp : v128) A((void**)pp, fe * sizeof(z128));
     A((void**)&c->bd, 3 * n * sizeof(z128));
+    A(&c->gs, fe * sizeof(z128));
     if (c->mixed) {
         z64** v64[] = {&c->r32, &c->rhat32, &c->p32, &c->v32, &c->s32, &c->t32, &c->x32, &c->b32};
         for (auto pp : v64) A((void**)pp, fe * sizeof(z64));
@@ -289,6 +314,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
             hipMemcpy(d64, h64.data(), L * sizeof(z64), hipMemcpyHostToDevice) != hipSuccess)
             rc = fail(LS_ERR_HIP, "twiddle upload failed");
     }
+    std::copy(fold21, fold21 + 21, c->fold21);
     if (rc == LS_OK) rc = fold_background(c, dC, drho, fold21);
     if (rc == LS_OK) rc = build_green_tables(c);
     if (rc == LS_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LS_ERR_HIP, "setup synchronisation failed");
@@ -303,6 +329,13 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
 }
 
 void ls_destroy(ls_ctx* ctx) { release(ctx); }
+
+int ls_set_contrast(ls_ctx* c, const double* dC, const double* drho) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if (!dC || !drho) return fail(LS_ERR_ARG, "null argument");
+    return fold_background(c, dC, drho, c->fold21);
+}
 
 int ls_apply(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
     int rc;
@@ -319,6 +352,45 @@ int ls_apply_c64(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
     if (!u || !Au) return fail(LS_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
     return apply_op<float>(c, i_omega, (const z64*)u, (z64*)Au, n_rhs);
+}
+
+int ls_apply_T(ls_ctx* c, int i_omega, const void* y, void* ATy, int n_rhs) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!y || !ATy) return fail(LS_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    return apply_T_op<double>(c, i_omega, (const z128*)y, (z128*)ATy, n_rhs);
+}
+
+int ls_convolve(ls_ctx* c, int i_omega, const void* f, void* out, int n_rhs) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!f || !out) return fail(LS_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    return convolve_op<double>(c, i_omega, (const z128*)f, (z128*)out, n_rhs);
+}
+
+int ls_solve_T(ls_ctx* c, int i_omega, const void* b, int n_rhs, double tol, int maxit, int precision,
+               const void* x0, void* x_out, ls_info* info) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!b || !x_out) return fail(LS_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    if (!(tol > 0) || !(tol < 1)) return fail(LS_ERR_ARG, "tol must be in (0, 1)");
+    if (maxit < 1) return fail(LS_ERR_ARG, "maxit must be >= 1");
+    if (precision != LS_PREC_C128 && precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
+    if (precision == LS_PREC_MIXED && !c->mixed)
+        return fail(LS_ERR_STATE, "mixed precision needs a context built with LS_PREC_MIXED");
+    return solve_systems(c, i_omega, (const z128*)b, n_rhs, tol, maxit, precision, (const z128*)x0, (z128*)x_out,
+                         info, true);
+}
+
+int ls_grad_contrast(ls_ctx* c, int i_omega, const void* u, const void* mu, int n_rhs, double* g_dC, double* g_drho) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!u || !mu || !g_dC || !g_drho) return fail(LS_ERR_ARG, "null pointer");
+    if (n_rhs < 1) return fail(LS_ERR_ARG, "n_rhs must be >= 1");
+    return grad_contrast_launch(c, i_omega, (const z128*)u, (const z128*)mu, n_rhs, g_dC, g_drho);
 }
 
 int ls_rhs_moment(ls_ctx* c, int i_omega, const double M[6], const int src[3], double t0, void* b) {

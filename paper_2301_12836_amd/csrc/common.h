@@ -83,6 +83,7 @@ struct Ctx {
     int green_mode = LS_GREEN_EXACT;
     int max_rhs = 1;
     double rho0 = 0, alpha = 0, beta = 0;
+    double fold21[21] = {0};      // C0 - C_iso, packed, added to every cell's contrast
     std::vector<double> omega;
     hipStream_t stream = nullptr;
 
@@ -108,6 +109,7 @@ struct Ctx {
     // Krylov vectors, c128 [max_rhs][3][ncell] each
     z128 *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
     z128 *xd = nullptr, *bd = nullptr;           // FP64 iterate / rhs copies for refinement
+    void* gs = nullptr;          // Gconv y scratch of the transposed operator [max_rhs][3][ncell] (c128 size)
     // c64 Krylov vectors for the inner solve of the mixed path
     z64 *r32 = nullptr, *rhat32 = nullptr, *p32 = nullptr, *v32 = nullptr, *s32 = nullptr, *t32 = nullptr,
         *x32 = nullptr, *b32 = nullptr;
@@ -141,6 +143,12 @@ int supported_fft_length(int n);
 // contrast kernels; see contrast.hip
 template <typename T>
 int contrast_to_work(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* work, cpx<T>* tau, int nrhs);
+template <typename T>
+int contrast_transposed_epilogue(Ctx* c, int i_omega, const cpx<T>* g, const cpx<T>* y, cpx<T>* out, cpx<T>* tau,
+                                 int nrhs);
+template <typename T>
+int to_work(Ctx* c, const cpx<T>* f, cpx<T>* work, int nrhs);
+int grad_contrast_launch(Ctx* c, int i_omega, const z128* u, const z128* mu, int nrhs, double* g21, double* grho);
 int fold_background(Ctx* c, const double* dc_in, const double* drho_in, const double fold21[21]);
 int strain_launch(Ctx* c, const z128* u, z128* eps, int nrhs);
 
@@ -149,13 +157,17 @@ int build_green_tables(Ctx* c);
 int rhs_points_launch(Ctx* c, int i_omega, const int* cells, const double* forces, int npts, double t0,
                       z128* b);
 
-// the LS matvec Au = u - Gconv B u (or v = Gconv B u); see capi.hip
+// the LS matvec Au = u - Gconv B u, its transpose A^T y = y - B Gconv y, and Gconv f; see capi.hip
 template <typename T>
 int apply_op(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* Au, int nrhs);
+template <typename T>
+int apply_T_op(Ctx* c, int i_omega, const cpx<T>* y, cpx<T>* ATy, int nrhs);
+template <typename T>
+int convolve_op(Ctx* c, int i_omega, const cpx<T>* f, cpx<T>* out, int nrhs);
 
 // solver (BiCGSTAB, mixed-precision refinement); see solver.hip
 int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int maxit, int precision,
-                  const z128* x0, z128* u_out, ls_info* info);
+                  const z128* x0, z128* u_out, ls_info* info, bool transposed = false);
 
 constexpr int kRedBlocks = 1024;  // fixed partial count: reductions are deterministic
 constexpr int kRedSlots = 4;      // partial sums per right-hand side and pass

@@ -454,9 +454,15 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
 }
 
 // ||b - A x|| / ||b|| per system with the FP64 operator; writes r = b - A x if r != null.
+// the operator or its transpose
+template <typename T>
+int op_apply(Ctx* c, int i_omega, const cpx<T>* in, cpx<T>* out, int nrhs, bool transposed) {
+    return transposed ? apply_T_op<T>(c, i_omega, in, out, nrhs) : apply_op<T>(c, i_omega, in, out, nrhs);
+}
+
 int true_residual(Ctx* c, int i_omega, const z128* b, const z128* x, z128* ax, z128* r, int nrhs,
-                  std::vector<double>& rel, std::vector<double>& abs_) {
-    int rc = apply_op<double>(c, i_omega, x, ax, nrhs);
+                  std::vector<double>& rel, std::vector<double>& abs_, bool transposed) {
+    int rc = op_apply<double>(c, i_omega, x, ax, nrhs, transposed);
     if (rc) return rc;
     const long long m = (long long)c->field_elems();
     hipLaunchKernelGGL(k_residual, vgrid(nrhs), dim3(kThreads), 0, c->stream, b, ax, r, m, c->partials);
@@ -472,7 +478,7 @@ int true_residual(Ctx* c, int i_omega, const z128* b, const z128* x, z128* ax, z
 }  // namespace
 
 int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int maxit, int precision, const z128* x0,
-                  z128* u_out, ls_info* info) {
+                  z128* u_out, ls_info* info, bool transposed) {
     const long long m = (long long)c->field_elems();
     std::vector<ls_info> inf(nrhs);
     for (auto& q : inf) q = ls_info{0, 0, 0, LS_OK, 0.0, 0.0};
@@ -489,15 +495,15 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
     if (precision == LS_PREC_C128) {
         const z128* ax0 = nullptr;
         if (x0) {
-            if ((rc = apply_op<double>(c, i_omega, u_out, c->t, nrhs))) return rc;
+            if ((rc = op_apply<double>(c, i_omega, u_out, c->t, nrhs, transposed))) return rc;
             ax0 = c->t;
         }
-        auto apply = [&](const z128* in, z128* out) { return apply_op<double>(c, i_omega, in, out, nrhs); };
+        auto apply = [&](const z128* in, z128* out) { return op_apply<double>(c, i_omega, in, out, nrhs, transposed); };
         rc = bicgstab<double, double>(c, b, u_out, ax0, c->r, c->rhat, c->p, c->v, c->s, c->t, nrhs, tol, maxit, apply,
                                       iters);
         if (rc) return rc;
         std::vector<double> st(c->red_host, c->red_host + (size_t)nrhs * kStateLen);
-        if ((rc = true_residual(c, i_omega, b, u_out, c->v, nullptr, nrhs, rel, nrm))) return rc;
+        if ((rc = true_residual(c, i_omega, b, u_out, c->v, nullptr, nrhs, rel, nrm, transposed))) return rc;
         for (int q = 0; q < nrhs; ++q) {
             const double* sq = &st[(size_t)q * kStateLen];
             inf[q].iters = iters[q];
@@ -534,7 +540,7 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 rel.assign(c->red_host, c->red_host + nrhs);
                 nrm.assign(c->red_host + kRedBlocks, c->red_host + kRedBlocks + nrhs);
             } else {
-                if ((rc = true_residual(c, i_omega, b, u_out, c->v, c->r, nrhs, rel, nrm))) return rc;
+                if ((rc = true_residual(c, i_omega, b, u_out, c->v, c->r, nrhs, rel, nrm, transposed))) return rc;
                 for (int q = 0; q < nrhs; ++q) inf[q].matvecs += 1;
             }
             bool any = false;
@@ -554,7 +560,9 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
             LS_HIP(hipMemcpyAsync(dscale, scale.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
             hipLaunchKernelGGL(k_to32, vgrid(nrhs), dim3(kThreads), 0, c->stream, c->r, c->b32, m, dscale, c->x32);
             LS_HIP(hipGetLastError());
-            auto apply32 = [&](const z64* in, z64* out) { return apply_op<float>(c, i_omega, in, out, nrhs); };
+            auto apply32 = [&](const z64* in, z64* out) {
+                return op_apply<float>(c, i_omega, in, out, nrhs, transposed);
+            };
             rc = bicgstab<float, float>(c, c->b32, c->x32, nullptr, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32,
                                         nrhs, eta, maxit, apply32, iters);
             if (rc) return rc;

@@ -35,7 +35,8 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
                LS_ERR_NONFINITE: "LS_ERR_NONFINITE", LS_ERR_STATE: "LS_ERR_STATE"}
 
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
-            "ls_solve_moment", "ls_strain", "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_last_error")
+            "ls_solve_moment", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve", "ls_solve_T", "ls_grad_contrast",
+            "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_last_error")
 
 
 class LsError(RuntimeError):
@@ -84,6 +85,7 @@ def load():
         "ls_setup": (I, [ctypes.POINTER(Grid), dp, D, P, P, dp, I, ctypes.POINTER(Options), P,
                          ctypes.POINTER(P)]),
         "ls_destroy": (None, [P]),
+        "ls_set_contrast": (I, [P, P, P]),
         "ls_apply": (I, [P, I, P, P, I]),
         "ls_apply_c64": (I, [P, I, P, P, I]),
         "ls_rhs_moment": (I, [P, I, dp, ip, D, P]),
@@ -91,6 +93,10 @@ def load():
         "ls_solve": (I, [P, I, P, I, D, I, I, P, P, ctypes.POINTER(Info)]),
         "ls_solve_moment": (I, [P, I, dp, ip, D, D, I, I, P, ctypes.POINTER(Info)]),
         "ls_strain": (I, [P, P, P, I]),
+        "ls_apply_T": (I, [P, I, P, P, I]),
+        "ls_convolve": (I, [P, I, P, P, I]),
+        "ls_solve_T": (I, [P, I, P, I, D, I, I, P, P, ctypes.POINTER(Info)]),
+        "ls_grad_contrast": (I, [P, I, P, P, I, P, P]),
         "ls_profile": (I, [P, I]),
         "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, I]),
         "ls_device_bytes": (ctypes.c_longlong, [P]),
@@ -147,6 +153,10 @@ def ls_destroy(ctx):
     load().ls_destroy(ctx)
 
 
+def ls_set_contrast(ctx, dC, drho):
+    return _check(load().ls_set_contrast(ctx, _ptr(dC), _ptr(drho)))
+
+
 def ls_apply(ctx, i_omega, u, Au, n_rhs):
     return _check(load().ls_apply(ctx, int(i_omega), _ptr(u), _ptr(Au), int(n_rhs)))
 
@@ -191,6 +201,28 @@ def ls_strain(ctx, u, eps, n_rhs):
     return _check(load().ls_strain(ctx, _ptr(u), _ptr(eps), int(n_rhs)))
 
 
+def ls_apply_T(ctx, i_omega, y, ATy, n_rhs):
+    return _check(load().ls_apply_T(ctx, int(i_omega), _ptr(y), _ptr(ATy), int(n_rhs)))
+
+
+def ls_convolve(ctx, i_omega, f, out, n_rhs):
+    return _check(load().ls_convolve(ctx, int(i_omega), _ptr(f), _ptr(out), int(n_rhs)))
+
+
+def ls_solve_T(ctx, i_omega, b, n_rhs, tol, maxit, precision, x0, x_out, raise_on_error=True):
+    infos = (Info * int(n_rhs))()
+    code = load().ls_solve_T(ctx, int(i_omega), _ptr(b), int(n_rhs), float(tol), int(maxit), int(precision),
+                             _ptr(x0), _ptr(x_out), infos)
+    if raise_on_error:
+        _check(code)
+    return code, [i.as_dict() for i in infos]
+
+
+def ls_grad_contrast(ctx, i_omega, u, mu, n_rhs, g_dC, g_drho):
+    return _check(load().ls_grad_contrast(ctx, int(i_omega), _ptr(u), _ptr(mu), int(n_rhs), _ptr(g_dC),
+                                          _ptr(g_drho)))
+
+
 def ls_profile(ctx, enable):
     return _check(load().ls_profile(ctx, int(bool(enable))))
 
@@ -228,6 +260,7 @@ class Context:
         self.torch = torch
         self.device = torch.device(device)
         self.shape = tuple(int(v) for v in shape)
+        self.h = float(h)
         n1, n2, n3 = self.shape
         self.field_shape = (3, n3, n2, n1)
         self.max_rhs = int(max_rhs)
@@ -253,6 +286,14 @@ class Context:
         except Exception:
             pass
 
+    def set_contrast(self, dc21, drho):
+        """Replace the contrast (numpy or torch; [21, N3, N2, N1] and [N3, N2, N1], float64)."""
+        torch = self.torch
+        n1, n2, n3 = self.shape
+        dc = torch.as_tensor(dc21, dtype=torch.float64).reshape(21, n3, n2, n1).to(self.device).contiguous()
+        dr = torch.as_tensor(drho, dtype=torch.float64).reshape(n3, n2, n1).to(self.device).contiguous()
+        ls_set_contrast(self.handle, dc, dr)
+
     # helpers
     def _field(self, t, dtype=None):
         torch = self.torch
@@ -261,7 +302,8 @@ class Context:
             t = t.to(dtype)
         if t.dtype not in (torch.complex128, torch.complex64):
             t = t.to(torch.complex128)
-        t = t.contiguous()
+        # lazy conjugate / negative views keep the original data behind data_ptr(): materialise them
+        t = t.resolve_conj().resolve_neg().contiguous()
         if t.shape[-4:] != self.field_shape:
             raise ValueError(f"field shape {tuple(t.shape)} does not end in {self.field_shape}")
         nrhs = 1 if t.dim() == 4 else int(np.prod(t.shape[:-4]))
@@ -299,6 +341,41 @@ class Context:
         prec = LS_PREC_MIXED if (precision or ("mixed" if self.mixed else "c128")) == "mixed" else LS_PREC_C128
         code, infos = ls_solve(self.handle, i_omega, b, nrhs, tol, maxit, prec, x0, out, raise_on_error)
         return out, infos
+
+    def apply_T(self, y, i_omega=0, out=None):
+        y, nrhs = self._field(y, self.torch.complex128)
+        out = self.torch.empty_like(y) if out is None else out
+        ls_apply_T(self.handle, i_omega, y, out, nrhs)
+        return out
+
+    def convolve(self, f, i_omega=0, out=None):
+        f, nrhs = self._field(f, self.torch.complex128)
+        out = self.torch.empty_like(f) if out is None else out
+        ls_convolve(self.handle, i_omega, f, out, nrhs)
+        return out
+
+    def solve_T(self, b, i_omega=0, tol=1e-8, maxit=2000, precision=None, x0=None, out=None, raise_on_error=True):
+        b, nrhs = self._field(b, self.torch.complex128)
+        if x0 is not None:
+            x0, _ = self._field(x0, self.torch.complex128)
+        out = self.torch.empty_like(b) if out is None else out
+        prec = LS_PREC_MIXED if (precision or ("mixed" if self.mixed else "c128")) == "mixed" else LS_PREC_C128
+        code, infos = ls_solve_T(self.handle, i_omega, b, nrhs, tol, maxit, prec, x0, out, raise_on_error)
+        return out, infos
+
+    def grad_contrast(self, u, mu, i_omega=0, g_dC=None, g_drho=None):
+        """Accumulate dJ/d(dC) [21, N3, N2, N1] and dJ/d(drho) [N3, N2, N1] (float64, on the device)."""
+        torch = self.torch
+        u, nrhs = self._field(u, torch.complex128)
+        mu, nrhs2 = self._field(mu, torch.complex128)
+        if nrhs != nrhs2:
+            raise ValueError("u and mu must hold the same number of fields")
+        if g_dC is None:
+            g_dC = torch.zeros((21,) + self.field_shape[1:], dtype=torch.float64, device=self.device)
+        if g_drho is None:
+            g_drho = torch.zeros(self.field_shape[1:], dtype=torch.float64, device=self.device)
+        ls_grad_contrast(self.handle, i_omega, u, mu, nrhs, g_dC, g_drho)
+        return g_dC, g_drho
 
     def strain(self, u):
         u, nrhs = self._field(u, self.torch.complex128)

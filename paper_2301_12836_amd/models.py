@@ -222,6 +222,30 @@ def config4(n=96):
     return Model((n, n, n), h, C0, rho0, dc, drho, [8.0, 16.0, 24.0, 32.0], srcs, 1e-6, "config4")
 
 
+def config4_receivers(n=96):
+    """64 receivers on a surface line: z = 0, y = n/2, x = n/6 ... n/6 + 63 (clipped to the grid)."""
+    x0 = 16 * n // 96
+    xs = [min(x0 + i, n - 1) for i in range(64)] if n >= 80 else list(range(0, n, max(1, n // 8)))
+    return np.array([[x, 48 * n // 96, 0] for x in xs])
+
+
+def config4_observed(n=96, seed=3):
+    """The 'true' model whose data the misfit compares against: config 4's ellipsoid with its C33 and
+    rho anomalies each scaled by (1 + 0.25 xi), xi uniform in [-1, 1] (seed 3), plus a 2 % random
+    perturbation of C33 and rho inside the ellipsoid."""
+    m = config4(n)
+    rng = np.random.default_rng(seed)
+    a, b = 1.0 + 0.25 * rng.uniform(-1, 1, size=2)
+    inside = m.drho != 0.0
+    q33 = UPPER21.index((2, 2))
+    dc = m.dc21.copy()
+    dc[q33] *= a
+    dc[q33][inside] *= 1.0 + 0.02 * rng.uniform(-1, 1, size=int(inside.sum()))
+    drho = m.drho * b
+    drho[inside] *= 1.0 + 0.02 * rng.uniform(-1, 1, size=int(inside.sum()))
+    return Model(m.shape, m.h, m.C0, m.rho0, dc, drho, m.freqs, m.sources, m.tol, "config4-observed")
+
+
 def random_field(shape, seed, complex_=True):
     """Seeded standard-normal test field [3, N3, N2, N1] (complex by default)."""
     rng = np.random.default_rng(seed)
