@@ -64,8 +64,16 @@ typedef struct {
     int green_mode; /* LS_GREEN_EXACT (default): the closed-form solution of Eq 7;
                        LS_GREEN_PAPER_SUM: the near-field A.4 plus far-field A.5 tensors   */
     int max_rhs;    /* largest batch of right-hand sides one call may carry (>= 1)         */
-    int reserved[5];
+    int flags;      /* LS_FLAG_* bits (0: defaults)                                          */
+    int reserved[4];
 } ls_options;
+
+/* ls_options.flags:
+ *   LS_FLAG_NO_GRAPH  run every BiCGSTAB iteration as separate launches instead of replaying one
+ *                     captured hipGraph per iteration (the default when the stream can be captured).
+ *   LS_FLAG_AUTOTUNE  at set-up, time the available kernel variants of every FFT pass (register
+ *                     four-step and LDS Stockham) at the context's sizes and keep the fastest. */
+enum { LS_FLAG_NO_GRAPH = 1, LS_FLAG_AUTOTUNE = 2 };
 
 typedef struct {
     int iters;           /* BiCGSTAB iterations (inner iterations summed for mixed solves)  */
@@ -179,6 +187,11 @@ int ls_profile_read(ls_ctx* ctx, char* names, int* counts, double* ms, int n_max
 
 /* Bytes of device memory the context holds. */
 long long ls_device_bytes(const ls_ctx* ctx);
+
+/* The FFT kernel variant each pass uses (0 register four-step, 1 LDS Stockham): variants[5 p + q]
+ * for precision p (0 c128, 1 c64) and pass q (0 x forward, 1 y forward, 2 z with the Green's
+ * multiply, 3 y inverse, 4 x inverse).  Chosen by timing when built with LS_FLAG_AUTOTUNE. */
+int ls_kernel_variants(const ls_ctx* ctx, int* variants);
 
 /* Message of the last error on this host thread ("" if none). */
 const char* ls_last_error(void);

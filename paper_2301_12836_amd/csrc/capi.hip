@@ -100,6 +100,7 @@ static void release(Ctx* c) {
     for (auto q : c->tw128) (void)hipFree(q);
     for (auto q : c->tw64) (void)hipFree(q);
     if (c->red_host) (void)hipHostFree(c->red_host);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete static_cast<ls_ctx*>(c);
 }
 
@@ -205,7 +206,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
         for (int J = 0; J < I; ++J)
             if (std::fabs(C0[I * 6 + J] - C0[J * 6 + I]) > 1e-12 * cmax)
                 return fail(LS_ERR_ARG, "background stiffness must be symmetric");
-    ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, {0, 0, 0, 0, 0}};
+    ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, 0, {0, 0, 0, 0}};
     if (opt) o = *opt;
     if (o.precision != LS_PREC_C128 && o.precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
     if (o.green_mode != LS_GREEN_EXACT && o.green_mode != LS_GREEN_PAPER_SUM) return fail(LS_ERR_ARG, "bad green_mode");
@@ -247,6 +248,17 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     c->beta = std::sqrt(c44 / rho0);
     c->omega.assign(omega, omega + n_omega);
     c->stream = (hipStream_t)stream;
+    c->flags = o.flags;
+    if (!c->stream) {
+        // the legacy null stream cannot be captured into graphs: work on a private blocking stream,
+        // which the runtime keeps ordered with the caller's work on the null stream
+        if (hipStreamCreate(&c->own_stream) != hipSuccess) {
+            (void)hipGetLastError();
+            delete static_cast<ls_ctx*>(c);
+            return fail(LS_ERR_HIP, "stream creation failed");
+        }
+        c->stream = c->own_stream;
+    }
 
     const size_t n = (size_t)c->ncell;
     const size_t fe = 3 * n * (size_t)c->max_rhs;  // field elements of a batch
@@ -317,6 +329,13 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     std::copy(fold21, fold21 + 21, c->fold21);
     if (rc == LS_OK) rc = fold_background(c, dC, drho, fold21);
     if (rc == LS_OK) rc = build_green_tables(c);
+    if (rc == LS_OK && (c->flags & LS_FLAG_AUTOTUNE)) {
+        if (hipMemsetAsync(c->work, 0, (size_t)c->max_rhs * 3 * c->n3 * c->L2 * c->L1 * sizeof(z128), c->stream) !=
+            hipSuccess)
+            rc = fail(LS_ERR_HIP, "autotune buffer clear failed");
+        if (rc == LS_OK) rc = autotune_passes<double>(c);
+        if (rc == LS_OK && c->mixed) rc = autotune_passes<float>(c);
+    }
     if (rc == LS_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LS_ERR_HIP, "setup synchronisation failed");
     if (rc) {
         const std::string msg = g_last_error;
@@ -519,5 +538,12 @@ int ls_profile_read(ls_ctx* c, char* names, int* counts, double* ms, int n_max) 
 }
 
 long long ls_device_bytes(const ls_ctx* c) { return c ? c->bytes : 0; }
+
+int ls_kernel_variants(const ls_ctx* c, int* variants) {
+    if (!c || !variants) return fail(LS_ERR_ARG, "null argument");
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 5; ++q) variants[p * 5 + q] = c->variant[p][q];
+    return LS_OK;
+}
 
 }  // extern "C"

@@ -86,6 +86,12 @@ struct Ctx {
     double fold21[21] = {0};      // C0 - C_iso, packed, added to every cell's contrast
     std::vector<double> omega;
     hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;  // created when the caller passes the null stream (a blocking stream,
+                                       // so it stays ordered with work on the legacy default stream)
+    int flags = 0;
+    // FFT kernel variant per pass and precision: 0 register four-step, 1 LDS Stockham
+    // passes: 0 x forward, 1 y forward, 2 z with Green multiply, 3 y inverse, 4 x inverse
+    int variant[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
 
     // medium (folded contrast), FP64 and (mixed) FP32
     double* dc = nullptr;     // [21][ncell]
@@ -138,6 +144,8 @@ int fft_apply_passes(Ctx* c, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>*
                      bool subtract_from_u);
 template <typename T>
 int fft_full_3d_forward(Ctx* c, cpx<T>* buf);
+template <typename T>
+int autotune_passes(Ctx* c);
 int supported_fft_length(int n);
 
 // contrast kernels; see contrast.hip

@@ -412,9 +412,9 @@ bool use_fourstep() {
 
 template <typename T, int SIGN, int MODE, bool PRUNE>
 int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long long S1, long long S2, int n_in,
-                  int n_out, const cpx<T>* tw, const cpx<T>* u, cpx<T>* out, const char* name) {
+                  int n_out, const cpx<T>* tw, const cpx<T>* u, cpx<T>* out, const char* name, int variant = 0) {
     c->prof.begin(c->stream, name);
-    const bool fs = use_fourstep();
+    const bool fs = variant == 0 && use_fourstep();
     switch (L) {
 #define CASE(LL)                                                                                             \
     case LL: {                                                                                               \
@@ -446,12 +446,12 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
 
 template <typename T, int SIGN, bool PRUNE>
 int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long long S1, long long S2, long long ES,
-                   int n_in, int n_out, const cpx<T>* tw, const char* name) {
+                   int n_in, int n_out, const cpx<T>* tw, const char* name, int variant = 0) {
     constexpr int TX = strided_cols<T>();
     static_assert(TX == seg_cols<T>(), "both strided kernels use 128-byte column tiles");
     if (NX % TX) return fail(LS_ERR_ARG, "x length not a multiple of the column tile");
     c->prof.begin(c->stream, name);
-    const bool fs = use_fourstep();
+    const bool fs = variant == 0 && use_fourstep();
     switch (L) {
 #define CASE(LL)                                                                                             \
     case LL: {                                                                                               \
@@ -478,13 +478,13 @@ int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long lon
 }
 
 template <typename T>
-int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<T>* tw) {
+int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<T>* tw, int variant = 0) {
     const int L1 = c->L1, L2 = c->L2, L = c->L3;
     const long long CS = (long long)c->n3 * L2 * L1;
     const long long RS = 3 * CS;
     const long long ES = (long long)L2 * L1;
     c->prof.begin(c->stream, LS_PNAME(T, "fft_z_green"));
-    const bool fs = use_fourstep();
+    const bool fs = variant == 0 && use_fourstep();
     switch (L) {
 #define CASE(LL)                                                                                              \
     case LL: {                                                                                                \
@@ -538,34 +538,87 @@ int supported_fft_length(int n) {
     return 0;
 }
 
+// One pass of the apply (0 x forward, 1 y forward, 2 z with the Green multiply, 3 y inverse,
+// 4 x inverse with the epilogue) with kernel variant 0 (register four-step) or 1 (LDS Stockham).
+template <typename T>
+int run_pass(Ctx* c, int pass, int variant, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, int nrhs,
+             bool subtract_from_u) {
+    const int N1 = c->n1, N2 = c->n2, N3 = c->n3, L1 = c->L1, L2 = c->L2, L3 = c->L3;
+    const long long rc = 3LL * nrhs;
+    const long long plane = (long long)L2 * L1;
+    switch (pass) {
+        case 0:  // x forward on the N2 x N3 data lines
+            return launch_contig<T, -1, 0, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, N1, L1, twiddles<T>(c, L1),
+                                                 nullptr, nullptr, LS_PNAME(T, "fft_x_fwd"), variant);
+        case 1:  // y forward on all L1 columns of the N3 data planes
+            return launch_strided<T, -1, true>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, N2, L2,
+                                               twiddles<T>(c, L2), LS_PNAME(T, "fft_y_fwd"), variant);
+        case 2:
+            return launch_zgreen<T>(c, work, nrhs, green_table<T>(c, i_omega), twiddles<T>(c, L3), variant);
+        case 3:
+            return launch_strided<T, +1, true>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, L2, N2,
+                                               twiddles<T>(c, L2), LS_PNAME(T, "fft_y_inv"), variant);
+        default:
+            if (subtract_from_u)
+                return launch_contig<T, +1, 1, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1,
+                                                     twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant);
+            return launch_contig<T, +1, 2, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, twiddles<T>(c, L1),
+                                                 u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant);
+    }
+}
+
 // Au = u - Gconv(f) (subtract_from_u) or Au = Gconv(f), where f already sits in work.
 template <typename T>
 int fft_apply_passes(Ctx* c, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, int nrhs,
                      bool subtract_from_u) {
-    const int N1 = c->n1, N2 = c->n2, N3 = c->n3, L1 = c->L1, L2 = c->L2, L3 = c->L3;
-    const long long rc = 3LL * nrhs;
-    const long long plane = (long long)L2 * L1;
-    const cpx<T>* tw1 = twiddles<T>(c, L1);
-    const cpx<T>* tw2 = twiddles<T>(c, L2);
-    const cpx<T>* tw3 = twiddles<T>(c, L3);
+    const int prec = sizeof(T) == 8 ? 0 : 1;
+    for (int pass = 0; pass < 5; ++pass) {
+        const int rc_ = run_pass<T>(c, pass, c->variant[prec][pass], i_omega, work, u, Au, nrhs, subtract_from_u);
+        if (rc_) return rc_;
+    }
+    return LS_OK;
+}
+
+// Time both kernel variants of every pass at the context's sizes (max_rhs right-hand sides, first
+// frequency) and keep the faster; the work buffer contents are scratch.
+template <typename T>
+int autotune_passes(Ctx* c) {
+    const int prec = sizeof(T) == 8 ? 0 : 1;
+    cpx<T>* work = (cpx<T>*)c->work;
+    cpx<T>* out = (cpx<T>*)c->gs;
+    const int nrhs = c->max_rhs;
+    hipEvent_t a, b;
+    LS_HIP(hipEventCreate(&a));
+    LS_HIP(hipEventCreate(&b));
     int rc_ = LS_OK;
-    // x forward on the N2 x N3 data lines
-    rc_ = launch_contig<T, -1, 0, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, N1, L1, tw1, nullptr, nullptr,
-                                  LS_PNAME(T, "fft_x_fwd"));
-    if (rc_) return rc_;
-    // y forward on all L1 columns of the N3 data planes
-    rc_ = launch_strided<T, -1, true>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, N2, L2, tw2, LS_PNAME(T, "fft_y_fwd"));
-    if (rc_) return rc_;
-    rc_ = launch_zgreen<T>(c, work, nrhs, green_table<T>(c, i_omega), tw3);
-    if (rc_) return rc_;
-    rc_ = launch_strided<T, +1, true>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, L2, N2, tw2, LS_PNAME(T, "fft_y_inv"));
-    if (rc_) return rc_;
-    if (subtract_from_u)
-        rc_ = launch_contig<T, +1, 1, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, LS_PNAME(T, "fft_x_inv_epi"));
-    else
-        rc_ = launch_contig<T, +1, 2, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, tw1, u, Au, LS_PNAME(T, "fft_x_inv_epi"));
+    for (int pass = 0; pass < 5 && rc_ == LS_OK; ++pass) {
+        float best = 0.f;
+        for (int variant = 0; variant < 2 && rc_ == LS_OK; ++variant) {
+            rc_ = run_pass<T>(c, pass, variant, 0, work, out, out, nrhs, false);  // warm-up
+            if (rc_) break;
+            if (hipEventRecord(a, c->stream) != hipSuccess) rc_ = fail(LS_ERR_HIP, "autotune event");
+            for (int k = 0; k < 3 && rc_ == LS_OK; ++k)
+                rc_ = run_pass<T>(c, pass, variant, 0, work, out, out, nrhs, false);
+            if (rc_) break;
+            float ms = 0.f;
+            if (hipEventRecord(b, c->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+                rc_ = fail(LS_ERR_HIP, "autotune timing");
+                break;
+            }
+            if (variant == 0 || ms < best) {
+                best = ms;
+                c->variant[prec][pass] = variant;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     return rc_;
 }
+
+template int autotune_passes<double>(Ctx*);
+template int autotune_passes<float>(Ctx*);
 
 // In-place unnormalised forward 3-D FFT of one [L3][L2][L1] array (Green's table setup).
 template <typename T>

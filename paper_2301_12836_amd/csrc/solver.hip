@@ -412,33 +412,66 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
     LS_HIP(hipGetLastError());
     int rc = finalize(c, PH_INIT, 2, nrhs, tol * tol);
     if (rc) return rc;
-    std::vector<double> st((size_t)nrhs * kStateLen);
-    for (int it = 0; it < maxit; ++it) {
+    // One iteration is a fixed sequence of launches whose scalars live on the device, so it is
+    // captured once into a graph and replayed; the host only reads the active flags in between.
+    auto body = [&]() -> int {
+        int brc;
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_update_p<T>), g, dim3(kThreads), 0, c->stream, r, p, v, m, c->state);
         c->prof.end(c->stream);
-        if ((rc = apply(p, v))) return rc;
+        if ((brc = apply(p, v))) return brc;
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_dot<T>), g, dim3(kThreads), 0, c->stream, rhat, v, m, c->state, c->partials);
         c->prof.end(c->stream);
-        if ((rc = finalize(c, PH_ALPHA, 2, nrhs))) return rc;
+        if ((brc = finalize(c, PH_ALPHA, 2, nrhs))) return brc;
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_update_s<T>), g, dim3(kThreads), 0, c->stream, r, v, s, m, c->state, c->partials);
         c->prof.end(c->stream);
-        if ((rc = finalize(c, PH_S, 1, nrhs))) return rc;
+        if ((brc = finalize(c, PH_S, 1, nrhs))) return brc;
         hipLaunchKernelGGL((k_update_x_half<T, X>), g, dim3(kThreads), 0, c->stream, x, p, m, c->state);
         hipLaunchKernelGGL(k_clear_half, dim3(1), dim3(64), 0, c->stream, c->state, nrhs);
-        if ((rc = apply(s, t))) return rc;
+        if ((brc = apply(s, t))) return brc;
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_dot_ts<T>), g, dim3(kThreads), 0, c->stream, t, s, m, c->state, c->partials);
         c->prof.end(c->stream);
-        if ((rc = finalize(c, PH_OMEGA, 3, nrhs))) return rc;
+        if ((brc = finalize(c, PH_OMEGA, 3, nrhs))) return brc;
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_update_xr<T, X>), g, dim3(kThreads), 0, c->stream, x, p, s, t, r, rhat, m, c->state,
                            c->partials);
         c->prof.end(c->stream);
-        if ((rc = finalize(c, PH_RHO, 4, nrhs))) return rc;
+        if ((brc = finalize(c, PH_RHO, 4, nrhs))) return brc;
         LS_HIP(hipGetLastError());
+        return LS_OK;
+    };
+    struct GraphGuard {
+        hipGraphExec_t exec = nullptr;
+        ~GraphGuard() {
+            if (exec) (void)hipGraphExecDestroy(exec);
+        }
+    } guard;
+    if (!(c->flags & LS_FLAG_NO_GRAPH) && !c->prof.on && c->stream != nullptr) {
+        LS_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        const int brc = body();
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+        if (brc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return brc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "BiCGSTAB iteration capture");
+        const hipError_t e2 = hipGraphInstantiate(&guard.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) {
+            guard.exec = nullptr;
+            return hip_fail(e2, "BiCGSTAB iteration graph instantiation");
+        }
+    }
+    for (int it = 0; it < maxit; ++it) {
+        if (guard.exec) {
+            LS_HIP(hipGraphLaunch(guard.exec, c->stream));
+        } else if ((rc = body())) {
+            return rc;
+        }
         LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * nrhs * kStateLen, hipMemcpyDeviceToHost,
                               c->stream));
         LS_HIP(hipStreamSynchronize(c->stream));

@@ -29,6 +29,9 @@ LS_PREC_C128 = 0
 LS_PREC_MIXED = 1
 LS_GREEN_EXACT = 0
 LS_GREEN_PAPER_SUM = 1
+LS_FLAG_NO_GRAPH = 1
+LS_FLAG_AUTOTUNE = 2
+PASS_NAMES = ("x_fwd", "y_fwd", "z_green", "y_inv", "x_inv")
 
 ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "LS_ERR_HIP",
                LS_ERR_BREAKDOWN: "LS_ERR_BREAKDOWN", LS_ERR_NOT_CONVERGED: "LS_ERR_NOT_CONVERGED",
@@ -36,7 +39,7 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
 
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
             "ls_solve_moment", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve", "ls_solve_T", "ls_grad_contrast",
-            "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_last_error")
+            "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_last_error")
 
 
 class LsError(RuntimeError):
@@ -51,7 +54,7 @@ class Grid(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("green_mode", ctypes.c_int), ("max_rhs", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("flags", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class Info(ctypes.Structure):
@@ -100,6 +103,7 @@ def load():
         "ls_profile": (I, [P, I]),
         "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, I]),
         "ls_device_bytes": (ctypes.c_longlong, [P]),
+        "ls_kernel_variants": (I, [P, ip]),
         "ls_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -136,11 +140,11 @@ def _ptr(t):
 # C-named entry points (torch tensors in, plain pointers to the library)
 
 def ls_setup(shape, h, C0, rho0, dC, drho, omegas, precision=LS_PREC_C128, green_mode=LS_GREEN_EXACT,
-             max_rhs=1, stream=None):
+             max_rhs=1, stream=None, flags=0):
     """dC, drho: contiguous float64 CUDA tensors [21, N3, N2, N1] and [N3, N2, N1]; returns a handle."""
     lib = load()
     g = Grid((ctypes.c_int * 3)(*[int(v) for v in shape]), float(h))
-    opt = Options(int(precision), int(green_mode), int(max_rhs), (ctypes.c_int * 5)())
+    opt = Options(int(precision), int(green_mode), int(max_rhs), int(flags), (ctypes.c_int * 4)())
     c0, c0p = _dbl(C0, 36)
     om, omp = _dbl(omegas, len(np.atleast_1d(omegas)))
     out = ctypes.c_void_p()
@@ -241,6 +245,13 @@ def ls_profile_read(ctx, n_max=64):
     return out
 
 
+def ls_kernel_variants(ctx):
+    v = (ctypes.c_int * 10)()
+    _check(load().ls_kernel_variants(ctx, v))
+    return {prec: {PASS_NAMES[q]: ("fourstep", "stockham")[v[5 * p + q]] for q in range(5)}
+            for p, prec in enumerate(("c128", "c64"))}
+
+
 def ls_device_bytes(ctx):
     return int(load().ls_device_bytes(ctx))
 
@@ -253,7 +264,7 @@ class Context:
     """One grid + medium + frequency set on one GPU (owns the library context)."""
 
     def __init__(self, shape, h, C0, rho0, dc21, drho, omegas, precision="c128", green_mode="exact", max_rhs=1,
-                 device="cuda:0"):
+                 device="cuda:0", graphs=True, autotune=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the LS library runs only on the GPU")
@@ -272,7 +283,8 @@ class Context:
         self.handle = ls_setup(self.shape, h, C0, rho0, dc, dr, self.omegas,
                                LS_PREC_MIXED if self.mixed else LS_PREC_C128,
                                LS_GREEN_PAPER_SUM if green_mode == "paper_sum" else LS_GREEN_EXACT, max_rhs,
-                               self.stream.cuda_stream)
+                               self.stream.cuda_stream,
+                               (0 if graphs else LS_FLAG_NO_GRAPH) | (LS_FLAG_AUTOTUNE if autotune else 0))
         del dc, dr
 
     def close(self):
@@ -390,11 +402,16 @@ class Context:
         return ls_profile_read(self.handle)
 
     @property
+    def kernel_variants(self):
+        return ls_kernel_variants(self.handle)
+
+    @property
     def device_bytes(self):
         return ls_device_bytes(self.handle)
 
 
-def context_from_model(model, precision="c128", max_rhs=1, green_mode="exact", device="cuda:0", omegas=None):
+def context_from_model(model, precision="c128", max_rhs=1, green_mode="exact", device="cuda:0", omegas=None,
+                       graphs=True, autotune=False):
     return Context(model.shape, model.h, model.C0, model.rho0, model.dc21, model.drho,
                    model.omegas if omegas is None else omegas, precision=precision, green_mode=green_mode,
-                   max_rhs=max_rhs, device=device)
+                   max_rhs=max_rhs, device=device, graphs=graphs, autotune=autotune)
