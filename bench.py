@@ -52,6 +52,8 @@ def kernel_bytes(fam, n1, n2, n3, L1, L2, L3, nrhs):
     table = {
         "contrast_strain_stress": (3 * R * n + 6 * R * n) * sc + 21 * n * sr,
         "contrast_divergence": (6 * R * n + 3 * R * n + 3 * R * n) * sc + n * sr,
+        "contrast_fused": (3 * R * n + 3 * R * n) * sc + 22 * n * sr,
+        "contrast_fused_T": (3 * R * n + 3 * R * n + 3 * R * n) * sc + 22 * n * sr,
         "fft_x_fwd": (x_lines * n1 + x_lines * L1) * sc,
         "fft_y_fwd": (plane_cols * n2 + plane_cols * L2) * sc,
         "fft_z_green": (2 * 3 * R * n3 * L2 * L1) * sc + 6 * oct_ * sc,
@@ -61,12 +63,17 @@ def kernel_bytes(fam, n1, n2, n3, L1, L2, L3, nrhs):
     return table.get(name)
 
 
+def split_contrast():
+    """True when the two-kernel contrast (strain/stress, then divergence) is selected instead of the fused one."""
+    return os.environ.get("LS_CONTRAST", "") == "split"
+
+
 def apply_bytes(n, prec, nrhs):
     """Algorithmic bytes of one LS matvec for nrhs right-hand sides (L = 2N): the sum over its kernels."""
     L = 2 * n
+    contrast = ("contrast_strain_stress", "contrast_divergence") if split_contrast() else ("contrast_fused",)
     return sum(kernel_bytes(f + "." + prec, n, n, n, L, L, L, nrhs) for f in
-               ("contrast_strain_stress", "contrast_divergence", "fft_x_fwd", "fft_y_fwd", "fft_z_green",
-                "fft_y_inv", "fft_x_inv_epi"))
+               contrast + ("fft_x_fwd", "fft_y_fwd", "fft_z_green", "fft_y_inv", "fft_x_inv_epi"))
 
 
 def source_hash():

@@ -136,6 +136,22 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def check_buffer(t, shape, dtype, device, name="out"):
+    """Return a caller-supplied buffer unchanged once it is known to have exactly the given shape, dtype
+    and device and to be contiguous; raise ValueError otherwise.  The library writes through a plain
+    pointer, sized by the grid and the number of right-hand sides, so a buffer of another element
+    type or shape would be written past its end."""
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous() or t.is_conj() or t.is_neg():
+        raise ValueError(f"{name} must be a contiguous tensor without lazy conjugate or negative bits")
+    return t
+
+
 # ------------------------------------------------------------------------------------------
 # C-named entry points (torch tensors in, plain pointers to the library)
 
@@ -321,6 +337,19 @@ class Context:
         nrhs = 1 if t.dim() == 4 else int(np.prod(t.shape[:-4]))
         return t, nrhs
 
+    def _check(self, t, shape, dtype, name="out"):
+        return check_buffer(t, shape, dtype, self._device_index(), name)
+
+    def _device_index(self):
+        d = self.device
+        return d if d.index is not None else self.torch.device(d.type, self.torch.cuda.current_device())
+
+    def _out(self, out, like):
+        """A fresh output like the (already converted) input, or the caller's buffer once checked."""
+        if out is None:
+            return self.torch.empty_like(like)
+        return self._check(out, like.shape, like.dtype)
+
     def empty(self, nrhs=None, dtype=None):
         torch = self.torch
         shape = self.field_shape if nrhs is None else (nrhs,) + self.field_shape
@@ -328,7 +357,7 @@ class Context:
 
     def apply(self, u, i_omega=0, out=None):
         u, nrhs = self._field(u)
-        out = self.torch.empty_like(u) if out is None else out
+        out = self._out(out, u)
         if u.dtype == self.torch.complex64:
             ls_apply_c64(self.handle, i_omega, u, out, nrhs)
         else:
@@ -336,12 +365,12 @@ class Context:
         return out
 
     def rhs_moment(self, M, src, i_omega=0, t0=0.0, out=None):
-        out = self.empty() if out is None else out
+        out = self.empty() if out is None else self._check(out, self.field_shape, self.torch.complex128)
         ls_rhs_moment(self.handle, i_omega, M, src, t0, out)
         return out
 
     def rhs_force(self, F, cell, i_omega=0, out=None):
-        out = self.empty() if out is None else out
+        out = self.empty() if out is None else self._check(out, self.field_shape, self.torch.complex128)
         ls_rhs_force(self.handle, i_omega, F, cell, out)
         return out
 
@@ -349,20 +378,20 @@ class Context:
         b, nrhs = self._field(b, self.torch.complex128)
         if x0 is not None:
             x0, _ = self._field(x0, self.torch.complex128)
-        out = self.torch.empty_like(b) if out is None else out
+        out = self._out(out, b)
         prec = LS_PREC_MIXED if (precision or ("mixed" if self.mixed else "c128")) == "mixed" else LS_PREC_C128
         code, infos = ls_solve(self.handle, i_omega, b, nrhs, tol, maxit, prec, x0, out, raise_on_error)
         return out, infos
 
     def apply_T(self, y, i_omega=0, out=None):
         y, nrhs = self._field(y, self.torch.complex128)
-        out = self.torch.empty_like(y) if out is None else out
+        out = self._out(out, y)
         ls_apply_T(self.handle, i_omega, y, out, nrhs)
         return out
 
     def convolve(self, f, i_omega=0, out=None):
         f, nrhs = self._field(f, self.torch.complex128)
-        out = self.torch.empty_like(f) if out is None else out
+        out = self._out(out, f)
         ls_convolve(self.handle, i_omega, f, out, nrhs)
         return out
 
@@ -370,7 +399,7 @@ class Context:
         b, nrhs = self._field(b, self.torch.complex128)
         if x0 is not None:
             x0, _ = self._field(x0, self.torch.complex128)
-        out = self.torch.empty_like(b) if out is None else out
+        out = self._out(out, b)
         prec = LS_PREC_MIXED if (precision or ("mixed" if self.mixed else "c128")) == "mixed" else LS_PREC_C128
         code, infos = ls_solve_T(self.handle, i_omega, b, nrhs, tol, maxit, prec, x0, out, raise_on_error)
         return out, infos
@@ -384,8 +413,12 @@ class Context:
             raise ValueError("u and mu must hold the same number of fields")
         if g_dC is None:
             g_dC = torch.zeros((21,) + self.field_shape[1:], dtype=torch.float64, device=self.device)
+        else:
+            self._check(g_dC, (21,) + self.field_shape[1:], torch.float64, "g_dC")
         if g_drho is None:
             g_drho = torch.zeros(self.field_shape[1:], dtype=torch.float64, device=self.device)
+        else:
+            self._check(g_drho, self.field_shape[1:], torch.float64, "g_drho")
         ls_grad_contrast(self.handle, i_omega, u, mu, nrhs, g_dC, g_drho)
         return g_dC, g_drho
 

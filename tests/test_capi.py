@@ -61,3 +61,21 @@ def test_null_context_is_rejected():
     assert lib.ls_solve(None, 0, None, 1, 1e-6, 10, 0, None, None, None) == lsvie.LS_ERR_ARG
     lib.ls_destroy(None)
     assert lib.ls_device_bytes(None) == 0
+
+
+def test_output_buffers_are_checked_before_the_library_writes():
+    """A caller-supplied output must match the input's dtype and shape exactly: the library writes
+    complex128 or complex64 fields through a plain pointer sized by the grid and right-hand sides."""
+    torch = pytest.importorskip("torch")
+    dev = torch.device("cpu")
+    shape = (2, 3, 4, 5, 6)
+    good = torch.zeros(shape, dtype=torch.complex128)
+    assert lsvie.check_buffer(good, shape, torch.complex128, dev) is good
+    bad = [torch.zeros(shape, dtype=torch.complex64),             # half the bytes
+           torch.zeros((1,) + shape[1:], dtype=torch.complex128),  # fewer right-hand sides
+           torch.zeros(shape[::-1], dtype=torch.complex128).permute(4, 3, 2, 1, 0),  # not contiguous
+           good.conj(),                                            # lazy conjugate view
+           torch.zeros(shape, dtype=torch.float64)]
+    for t in bad:
+        with pytest.raises(ValueError):
+            lsvie.check_buffer(t, shape, torch.complex128, dev)

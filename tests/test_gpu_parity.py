@@ -219,6 +219,18 @@ def test_error_paths_on_gpu():
     assert e.value.code == lsvie.LS_ERR_STATE
     with pytest.raises(lsvie.LsError):
         ctx.apply(torch.from_numpy(models.random_field(m.shape, 1)), i_omega=3)
+    # outputs of the wrong element type or shape are refused before anything is launched
+    u128 = torch.from_numpy(models.random_field(m.shape, 1)).to(ctx.device)
+    for call in (ctx.apply, ctx.apply_T, ctx.convolve):
+        with pytest.raises(ValueError):
+            call(u128, out=torch.empty(u128.shape, dtype=torch.complex64, device=ctx.device))
+        with pytest.raises(ValueError):
+            call(u128, out=torch.empty((2,) + u128.shape, dtype=torch.complex128, device=ctx.device))
+    with pytest.raises(ValueError):
+        ctx.solve(b, out=torch.empty(b.shape, dtype=torch.complex64, device=ctx.device))
+    with pytest.raises(ValueError):
+        ctx.rhs_moment(models.EXPLOSION, (3, 3, 3), out=torch.empty((1, 1), dtype=torch.complex128,
+                                                                    device=ctx.device))
     # zero right-hand side: immediate u = 0
     x, infos = ctx.solve(torch.zeros_like(b), tol=1e-8)
     assert float(torch.abs(x).max()) == 0.0 and infos[0]["iters"] == 0
