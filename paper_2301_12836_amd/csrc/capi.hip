@@ -249,6 +249,13 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     c->omega.assign(omega, omega + n_omega);
     c->stream = (hipStream_t)stream;
     c->flags = o.flags;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            c->num_cu = cus;
+        (void)hipGetLastError();
+    }
     if (!c->stream) {
         // the legacy null stream cannot be captured into graphs: work on a private blocking stream,
         // which the runtime keeps ordered with the caller's work on the null stream

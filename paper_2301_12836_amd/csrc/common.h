@@ -89,6 +89,7 @@ struct Ctx {
     hipStream_t own_stream = nullptr;  // created when the caller passes the null stream (a blocking stream,
                                        // so it stays ordered with work on the legacy default stream)
     int flags = 0;
+    int num_cu = 256;  // compute units of the device (block-count heuristics)
     // FFT kernel variant per pass and precision: 0 register four-step, 1 LDS Stockham
     // passes: 0 x forward, 1 y forward, 2 z with Green multiply, 3 y inverse, 4 x inverse
     int variant[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};

@@ -5,6 +5,11 @@
 // divergence of the contrast stress is -E^T tau.  Per cell, tau = dC eps with dC the symmetric
 // 6x6 of the cell (21 packed values).  The first kernel writes tau for every cell, the second
 // forms f and writes it straight into the zero-padded FFT work buffer.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <type_traits>
+
 #include "fft_reg.h"
 
 namespace ls {
@@ -43,6 +48,25 @@ __device__ __forceinline__ cpx<T> deriv_t(const cpx<T>* __restrict__ v, long lon
         acc = acc + cp * v[p + stride];
     }
     return acc;
+}
+
+// Voigt strain at the cell with grid indices (i, j, k) of an N1 x N2 x N3 grid; the field's values sit
+// at element p of three component arrays n apart, with neighbours 1, sy and sz elements away (the
+// grid itself, or a tile of it staged in LDS).
+template <typename T>
+__device__ __forceinline__ void strain_at_strided(const cpx<T>* __restrict__ u, long long n, long long p, int i,
+                                                  int j, int k, long long sy, long long sz, int N1, int N2, int N3,
+                                                  T inv_h, cpx<T> eps[6]) {
+    const long long sx = 1;
+    const cpx<T>* u0 = u;
+    const cpx<T>* u1 = u + n;
+    const cpx<T>* u2 = u + 2 * n;
+    eps[0] = deriv(u0, p, sx, i, N1, inv_h);
+    eps[1] = deriv(u1, p, sy, j, N2, inv_h);
+    eps[2] = deriv(u2, p, sz, k, N3, inv_h);
+    eps[3] = deriv(u1, p, sz, k, N3, inv_h) + deriv(u2, p, sy, j, N2, inv_h);
+    eps[4] = deriv(u0, p, sz, k, N3, inv_h) + deriv(u2, p, sx, i, N1, inv_h);
+    eps[5] = deriv(u0, p, sy, j, N2, inv_h) + deriv(u1, p, sx, i, N1, inv_h);
 }
 
 template <typename T>
@@ -129,6 +153,281 @@ __global__ __launch_bounds__(kThreads) void k_divergence(const cpx<T>* __restric
             o[p] = yr[p] - (wr * ur[p] - f0);
             o[n + p] = yr[n + p] - (wr * ur[n + p] - f1);
             o[2 * n + p] = yr[2 * n + p] - (wr * ur[2 * n + p] - f2);
+        }
+    }
+}
+
+// Weights of the values at i-1, i, i+1 in one derivative along an axis of n >= 2 cells: of the
+// strain stencil d/dx (Eq 18: central inside, one-sided at the ends) and of its transpose D^T.
+template <typename T>
+struct W3 {
+    T m, z, p;
+};
+
+template <typename T>
+__device__ __forceinline__ W3<T> d_weights(int i, int n, T inv_h) {
+    if (i == 0) return {T(0), -inv_h, inv_h};
+    if (i == n - 1) return {-inv_h, inv_h, T(0)};
+    return {T(-0.5) * inv_h, T(0), T(0.5) * inv_h};
+}
+
+template <typename T>
+__device__ __forceinline__ W3<T> dt_weights(int i, int n, T inv_h) {
+    W3<T> w;
+    w.m = i >= 1 ? (i - 1 == 0 ? inv_h : T(0.5) * inv_h) : T(0);
+    w.z = (i == 0 ? -inv_h : T(0)) + (i == n - 1 ? inv_h : T(0));
+    w.p = i <= n - 2 ? (i + 1 == n - 1 ? -inv_h : T(-0.5) * inv_h) : T(0);
+    return w;
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> w3(const W3<T>& w, cpx<T> fm, cpx<T> f0, cpx<T> fp) {
+    return w.m * fm + w.z * f0 + w.p * fp;
+}
+
+// Fused contrast, marching in z: f = w^2 drho u - E^T (dC E u) in one pass over u.
+//
+// One block = one right-hand side, one BX x BY column of cells and a chunk of z planes.  LDS holds a
+// ring of four u planes with a 2-cell xy halo and two tau planes with a 1-cell xy halo (no corners).
+// Thread roles: the first BX*BY threads own one cell each (full tau, then f); the next 2*BX threads
+// take the halo rows below and above the column and the next 2*BY the halo columns left and right,
+// and compute only the tau components that the divergence reads there (Voigt 22, 23, 12 across a y
+// face; 11, 13, 12 across an x face).  With BX = 32 every wave has one role, so each step is one
+// tau pass per wave.  The z neighbours of tau at the owned cells stay in registers.
+// Step k: store the prefetched plane u(k+2), start loading u(k+3) and the dC and drho of the next
+// step, tau(k+1), then f(k).  Each u plane is read from HBM once per chunk (plus the xy halo, served
+// mostly from L2), each dC once per chunk and right-hand side (right-hand sides are the fastest
+// logical block index, so the blocks of one column share dC through one L2), and f is written once
+// as full 128-byte rows.  Derivatives use per-lane weights (no divergent branches at the model
+// boundary): every LDS value they touch is finite, since u planes are stored whole (zeros outside the
+// grid) and the tau planes start zeroed and only ever receive finite values.
+// OUT 0: f into the padded work buffer; OUT 1: out = y - f (the transposed operator's epilogue).
+template <typename T, int BX, int BY, int NT, int OUT>
+__global__ __launch_bounds__(NT, sizeof(T) == 4 ? 2 : 1) void k_contrast_zmarch(
+    const cpx<T>* __restrict__ u, const T* __restrict__ dc, const T* __restrict__ drho, cpx<T>* __restrict__ out,
+    const cpx<T>* __restrict__ y, int nrhs, int N1, int N2, int N3, int L1, int L2, T inv_h, T w2, int tx, int ty,
+    int nzc, long long nb_real) {
+    constexpr int NOWN = BX * BY;
+    constexpr int UX = BX + 4, UY = BY + 4, UP = UX * UY;  // u plane (halo 2)
+    constexpr int SX = BX + 2, SY = BY + 2, SP = SX * SY;  // tau plane (halo 1)
+    constexpr int NLOAD = (3 * UP + NT - 1) / NT;
+    constexpr int NRING = 2 * BX + 2 * BY;
+    static_assert(NOWN + NRING <= NT, "one tau cell per thread");
+    static_assert(NLOAD <= 32, "validity mask of the plane loads");
+    __shared__ cpx<T> us[4 * 3 * UP];
+    __shared__ cpx<T> ts[2 * 6 * SP];
+
+    const long long lb = xcd_logical_block(blockIdx.x, nb_real);
+    if (lb < 0) return;
+    const int t = threadIdx.x;
+    const int rhs = (int)(lb % nrhs);
+    const long long col = lb / nrhs;
+    const int x0 = (int)(col % tx) * BX;
+    const int y0 = (int)((col / tx) % ty) * BY;
+    const int z0 = (int)(col / ((long long)tx * ty)) * nzc;
+    const int zend = min(z0 + nzc, N3);
+    const long long n = (long long)N1 * N2 * N3;
+    const long long plane = (long long)N1 * N2;
+    const cpx<T>* ur = u + (long long)rhs * 3 * n;
+
+    // role: 0 owned cell, 1 y-face halo cell, 2 x-face halo cell, 3 idle; (lx, ly) in plane coordinates
+    int role, lx, ly;
+    if (t < NOWN) {
+        role = 0, lx = t % BX, ly = t / BX;
+    } else if (t < NOWN + 2 * BX) {
+        const int r = t - NOWN;
+        role = 1, lx = r % BX, ly = r < BX ? -1 : BY;
+    } else if (t < NOWN + NRING) {
+        const int r = t - NOWN - 2 * BX;
+        role = 2, lx = r < BY ? -1 : BX, ly = r % BY;
+    } else {
+        role = 3, lx = 0, ly = 0;
+    }
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool cell = role != 3 && gx >= 0 && gx < N1 && gy >= 0 && gy < N2;
+    const bool own = role == 0 && cell;
+    const W3<T> dxw = d_weights(gx, N1, inv_h), dyw = d_weights(gy, N2, inv_h);
+    const W3<T> txw = dt_weights(gx, N1, inv_h), tyw = dt_weights(gy, N2, inv_h);
+    const unsigned cell_xy = cell ? (unsigned)(gy * N1 + gx) : 0u;  // clamped: never used when !cell
+
+    // plane loads: element e = t + m NT of the [3][UY][UX] box; its offset in plane 0 and validity
+    unsigned ldoff[NLOAD];
+    unsigned ldok = 0;
+#pragma unroll
+    for (int m = 0; m < NLOAD; ++m) {
+        const int e = t + m * NT;
+        const int c = e / UP, rem = e - c * UP;
+        const int bly = rem / UX, blx = rem - bly * UX;
+        const int bx = x0 - 2 + blx, by = y0 - 2 + bly;
+        ldoff[m] = 0;
+        if (e < 3 * UP && bx >= 0 && bx < N1 && by >= 0 && by < N2) {
+            ldoff[m] = (unsigned)(c * n + (long long)by * N1 + bx);
+            ldok |= 1u << m;
+        }
+    }
+    // Prefetched plane, raw (scalar arrays: kept in registers).  Loads are unconditional (invalid
+    // elements read a valid address: ldoff = 0 of a clamped plane), so no load sits behind a branch,
+    // and the zeroing select is applied only when the plane is stored, a step later, so that the
+    // load's latency is not waited for at the load.
+    T pfr[NLOAD], pfi[NLOAD];
+    bool pf_in = false;
+    auto load_plane = [&](int q) __attribute__((always_inline)) {
+        pf_in = q >= 0 && q < N3;
+        const cpx<T>* src = ur + (long long)min(max(q, 0), N3 - 1) * plane;
+#pragma unroll
+        for (int m = 0; m < NLOAD; ++m) {
+            const cpx<T> v = src[ldoff[m]];
+            pfr[m] = v.x;
+            pfi[m] = v.y;
+        }
+    };
+    auto store_plane = [&](int q) __attribute__((always_inline)) {
+        cpx<T>* s = us + (q & 3) * 3 * UP;
+#pragma unroll
+        for (int m = 0; m < NLOAD; ++m) {
+            const int e = t + m * NT;
+            const bool ok = pf_in && ((ldok >> m) & 1u);
+            if (e < 3 * UP) s[e] = cpx<T>{ok ? pfr[m] : T(0), ok ? pfi[m] : T(0)};
+        }
+    };
+    // dC of this thread's cell (a clamped valid cell when the thread has none): C for the tau plane of
+    // this step, Cn loaded for the next one
+    T C[21], Cn[21];
+    auto load_C = [&](T* dst, int q) __attribute__((always_inline)) {
+        const T* base = dc + (long long)min(max(q, 0), N3 - 1) * plane;
+#pragma unroll
+        for (int qq = 0; qq < 21; ++qq) dst[qq] = (base + qq * n)[cell_xy];
+    };
+    // tau on plane q at this thread's cell, from u planes q-1, q, q+1: rows I of dC eps for which
+    // the mask bit I is set
+    auto tau_cell = [&](int q, auto rows) __attribute__((always_inline)) {
+        constexpr int mask = decltype(rows)::value;
+        const cpx<T>* um = us + ((q - 1) & 3) * 3 * UP;
+        const cpx<T>* u0 = us + (q & 3) * 3 * UP;
+        const cpx<T>* up = us + ((q + 1) & 3) * 3 * UP;
+        const W3<T> dz = d_weights(q, N3, inv_h);
+        const int pu = (ly + 2) * UX + (lx + 2);
+        auto ddx = [&](int c) __attribute__((always_inline)) {
+            const cpx<T>* f = u0 + c * UP + pu;
+            return w3(dxw, f[-1], f[0], f[1]);
+        };
+        auto ddy = [&](int c) __attribute__((always_inline)) {
+            const cpx<T>* f = u0 + c * UP + pu;
+            return w3(dyw, f[-UX], f[0], f[UX]);
+        };
+        auto ddz = [&](int c) __attribute__((always_inline)) {
+            return w3(dz, um[c * UP + pu], u0[c * UP + pu], up[c * UP + pu]);
+        };
+        cpx<T> eps[6];
+        eps[0] = ddx(0);
+        eps[1] = ddy(1);
+        eps[2] = ddz(2);
+        eps[3] = ddz(1) + ddy(2);
+        eps[4] = ddz(0) + ddx(2);
+        eps[5] = ddy(0) + ddx(1);
+        cpx<T>* s = ts + (q & 1) * 6 * SP + (ly + 1) * SX + (lx + 1);
+#pragma unroll
+        for (int I = 0; I < 6; ++I) {
+            if (!((mask >> I) & 1)) continue;
+            cpx<T> acc = {T(0), T(0)};
+#pragma unroll
+            for (int J = 0; J < 6; ++J) acc = acc + C[packed(I, J)] * eps[J];
+            s[I * SP] = acc;
+        }
+    };
+    auto tau_plane = [&](int q) __attribute__((always_inline)) {
+        if (q < 0 || q >= N3 || !cell) return;  // never read with a nonzero weight
+        if (role == 0)
+            tau_cell(q, std::integral_constant<int, 0x3f>{});
+        else if (role == 1)
+            tau_cell(q, std::integral_constant<int, (1 << 1) | (1 << 3) | (1 << 5)>{});
+        else
+            tau_cell(q, std::integral_constant<int, (1 << 0) | (1 << 4) | (1 << 5)>{});
+    };
+
+    // prologue: zero tau planes, u planes z0-2 .. z0+1, tau planes z0-1 and z0
+    for (int e = t; e < 2 * 6 * SP; e += NT) ts[e] = cpx<T>{T(0), T(0)};
+    for (int q = z0 - 2; q <= z0 + 1; ++q) {
+        load_plane(q);
+        store_plane(q);
+    }
+    __syncthreads();
+    load_C(C, z0 - 1);
+    tau_plane(z0 - 1);
+    load_C(C, z0);
+    tau_plane(z0);
+    load_C(C, z0 + 1);
+    load_plane(z0 + 2);
+    T dro = (drho + (long long)z0 * plane)[cell_xy], dron = T(0);
+    __syncthreads();
+    const int po = (ly + 1) * SX + (lx + 1);
+    cpx<T> tprev[3] = {};  // tau_{3,4,5} (Voigt 33, 23, 13) of the owned cell one plane below
+    if (own && z0 >= 1) {
+        const cpx<T>* s = ts + ((z0 - 1) & 1) * 6 * SP + po;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tprev[c] = s[(2 + c) * SP];
+    }
+
+    // Every load for step k+1 is issued at the top of step k, so that each has a whole step to land
+    // (the wait counter retires loads in order, so late loads would hold up earlier consumers).
+    for (int k = z0; k < zend; ++k) {
+        const bool more = k + 1 < zend;
+        store_plane(k + 2);
+        if (more) {
+            load_plane(k + 3);
+            load_C(Cn, k + 2);
+            dron = (drho + (long long)(k + 1) * plane)[cell_xy];
+        }
+        __syncthreads();
+        tau_plane(k + 1);
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int qq = 0; qq < 21; ++qq) C[qq] = Cn[qq];
+        }
+        if (!own) {
+            dro = dron;
+            continue;
+        }
+        const cpx<T>* s0 = ts + (k & 1) * 6 * SP + po;
+        const cpx<T>* s1 = ts + ((k + 1) & 1) * 6 * SP + po;
+        const W3<T> tz = dt_weights(k, N3, inv_h);
+        auto tdx = [&](int I) __attribute__((always_inline)) {
+            const cpx<T>* v = s0 + I * SP;
+            return w3(txw, v[-1], v[0], v[1]);
+        };
+        auto tdy = [&](int I) __attribute__((always_inline)) {
+            const cpx<T>* v = s0 + I * SP;
+            return w3(tyw, v[-SX], v[0], v[SX]);
+        };
+        cpx<T> tcur[3], tnext[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            tcur[c] = s0[(2 + c) * SP];
+            tnext[c] = s1[(2 + c) * SP];  // weight 0 on the last plane
+        }
+        const cpx<T> f0 = tdx(0) + tdy(5) + w3(tz, tprev[2], tcur[2], tnext[2]);
+        const cpx<T> f1 = tdx(5) + tdy(1) + w3(tz, tprev[1], tcur[1], tnext[1]);
+        const cpx<T> f2 = tdx(4) + tdy(3) + w3(tz, tprev[0], tcur[0], tnext[0]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) tprev[c] = tcur[c];
+        const long long p = (long long)k * plane + cell_xy;
+        const cpx<T>* uk = us + (k & 3) * 3 * UP + (ly + 2) * UX + (lx + 2);
+        const T wr = w2 * dro;
+        dro = dron;
+        const cpx<T> g0 = wr * uk[0] - f0, g1 = wr * uk[UP] - f1, g2 = wr * uk[2 * UP] - f2;
+        if constexpr (OUT == 0) {
+            const long long cpitch = (long long)N3 * L2 * L1;
+            cpx<T>* w_ = out + (long long)rhs * 3 * cpitch + ((long long)k * L2 + gy) * L1 + gx;
+            w_[0] = g0;
+            w_[cpitch] = g1;
+            w_[2 * cpitch] = g2;
+        } else {
+            const cpx<T>* yr = y + (long long)rhs * 3 * n;
+            cpx<T>* o_ = out + (long long)rhs * 3 * n;
+            o_[p] = yr[p] - g0;
+            o_[n + p] = yr[n + p] - g1;
+            o_[2 * n + p] = yr[2 * n + p] - g2;
         }
     }
 }
@@ -234,8 +533,51 @@ const float* density_of<float>(const Ctx* c) { return c->drho32; }
 
 }  // namespace
 
+// LS_CONTRAST=split selects the two-kernel contrast (strain/stress, then divergence) everywhere; both
+// paths are kept under test.
+bool use_fused_contrast() {
+    static const bool fused = [] {
+        const char* e = std::getenv("LS_CONTRAST");
+        return !(e && std::strcmp(e, "split") == 0);
+    }();
+    return fused;
+}
+
+// z chunk of the fused kernel: blocks run in rounds of (CUs x resident blocks per CU), each block
+// costs its chunk plus about three planes of prologue; pick the chunk (at least 8 planes) that
+// minimises rounds x (chunk + 3).
+inline int fused_z_chunk(int n3, long long cols, long long slots) {
+    int best = n3;
+    long long best_cost = -1;
+    for (int nzc = std::min(8, n3); nzc <= n3; ++nzc) {
+        const long long nb = cols * ((n3 + nzc - 1) / nzc);
+        const long long cost = ((nb + slots - 1) / slots) * (nzc + 3);
+        if (best_cost < 0 || cost < best_cost) best = nzc, best_cost = cost;
+    }
+    return best;
+}
+
+template <typename T, int OUT>
+int launch_fused(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* out, const cpx<T>* y, int nrhs) {
+    constexpr int BX = 32, BY = 8, NT = 384;  // 256 owned + 80 halo cells; LDS 72 KB (c64) or 145 KB (c128)
+    const int tx = (c->n1 + BX - 1) / BX, ty = (c->n2 + BY - 1) / BY;
+    const long long cols = (long long)tx * ty * nrhs;
+    const int nzc = fused_z_chunk(c->n3, cols, (long long)c->num_cu * (sizeof(T) == 4 ? 2 : 1));
+    const long long nb = cols * ((c->n3 + nzc - 1) / nzc);
+    const unsigned nbl = (unsigned)((nb + 7) / 8 * 8);
+    const double w = c->omega[i_omega];
+    c->prof.begin(c->stream, OUT == 0 ? LS_PNAME(T, "contrast_fused") : LS_PNAME(T, "contrast_fused_T"));
+    hipLaunchKernelGGL((k_contrast_zmarch<T, BX, BY, NT, OUT>), dim3(nbl), dim3(NT), 0, c->stream, u,
+                       contrast_of<T>(c), density_of<T>(c), out, y, nrhs, c->n1, c->n2, c->n3, c->L1, c->L2,
+                       T(1.0 / c->h), T(w * w), tx, ty, nzc, nb);
+    c->prof.end(c->stream);
+    LS_HIP(hipGetLastError());
+    return LS_OK;
+}
+
 template <typename T>
 int contrast_to_work(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* work, cpx<T>* tau, int nrhs) {
+    if (use_fused_contrast()) return launch_fused<T, 0>(c, i_omega, u, work, nullptr, nrhs);
     const long long n = c->ncell;
     // XCD-aware order: grid padded to a multiple of 8, neighbouring cells share an L2
     const unsigned nb = (unsigned)(((n + kThreads - 1) / kThreads + 7) / 8 * 8);
@@ -261,6 +603,7 @@ template int contrast_to_work<float>(Ctx*, int, const z64*, z64*, z64*, int);
 template <typename T>
 int contrast_transposed_epilogue(Ctx* c, int i_omega, const cpx<T>* g, const cpx<T>* y, cpx<T>* out, cpx<T>* tau,
                                  int nrhs) {
+    if (use_fused_contrast()) return launch_fused<T, 1>(c, i_omega, g, out, y, nrhs);
     const long long n = c->ncell;
     const unsigned nb = (unsigned)(((n + kThreads - 1) / kThreads + 7) / 8 * 8);
     const T inv_h = T(1.0 / c->h);
