@@ -202,8 +202,8 @@ __device__ __forceinline__ cpx<T> w3(const W3<T>& w, cpx<T> fm, cpx<T> f0, cpx<T
 // boundary): every LDS value they touch is finite, since u planes are stored whole (zeros outside the
 // grid) and the tau planes start zeroed and only ever receive finite values.
 // OUT 0: f into the padded work buffer; OUT 1: out = y - f (the transposed operator's epilogue).
-template <typename T, int BX, int BY, int NT, int OUT>
-__global__ __launch_bounds__(NT, sizeof(T) == 4 ? 2 : 1) void k_contrast_zmarch(
+template <typename T, int BX, int BY, int NT, int MINB, bool DB, int OUT>
+__global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     const cpx<T>* __restrict__ u, const T* __restrict__ dc, const T* __restrict__ drho, cpx<T>* __restrict__ out,
     const cpx<T>* __restrict__ y, int nrhs, int N1, int N2, int N3, int L1, int L2, T inv_h, T w2, int tx, int ty,
     int nzc, long long nb_real) {
@@ -291,8 +291,9 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 2 : 1) void k_contrast_zmarch(
         }
     };
     // dC of this thread's cell (a clamped valid cell when the thread has none): C for the tau plane of
-    // this step, Cn loaded for the next one
-    T C[21], Cn[21];
+    // this step; with DB, Cn is loaded for the next one at the top of the step, else C is reloaded
+    // right after its tau plane (fewer registers)
+    T C[21], Cn[DB ? 21 : 1];
     auto load_C = [&](T* dst, int q) __attribute__((always_inline)) {
         const T* base = dc + (long long)min(max(q, 0), N3 - 1) * plane;
 #pragma unroll
@@ -375,15 +376,20 @@ __global__ __launch_bounds__(NT, sizeof(T) == 4 ? 2 : 1) void k_contrast_zmarch(
         store_plane(k + 2);
         if (more) {
             load_plane(k + 3);
-            load_C(Cn, k + 2);
+            if constexpr (DB) load_C(Cn, k + 2);
             dron = (drho + (long long)(k + 1) * plane)[cell_xy];
         }
         __syncthreads();
         tau_plane(k + 1);
+        if constexpr (!DB) {
+            if (more) load_C(C, k + 2);
+        }
         __syncthreads();
-        if (more) {
+        if constexpr (DB) {
+            if (more) {
 #pragma unroll
-            for (int qq = 0; qq < 21; ++qq) C[qq] = Cn[qq];
+                for (int qq = 0; qq < 21; ++qq) C[qq] = Cn[qq];
+            }
         }
         if (!own) {
             dro = dron;
@@ -557,19 +563,34 @@ inline int fused_z_chunk(int n3, long long cols, long long slots) {
     return best;
 }
 
+// Tile, block size and resident blocks per CU: c64 32x4 cells, 256 threads (128 owned, 72 halo), 47 KB
+// LDS, three blocks per CU; c128 32x8 cells, 384 threads (256 owned, 80 halo), 145 KB LDS, one block.
+template <typename T>
+struct FusedShape;
+template <>
+struct FusedShape<float> {
+    static constexpr int BX = 32, BY = 4, NT = 256, PER_CU = 3;
+    static constexpr bool DB = true;
+};
+template <>
+struct FusedShape<double> {
+    static constexpr int BX = 32, BY = 8, NT = 384, PER_CU = 1;
+    static constexpr bool DB = false;
+};
+
 template <typename T, int OUT>
 int launch_fused(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* out, const cpx<T>* y, int nrhs) {
-    constexpr int BX = 32, BY = 8, NT = 384;  // 256 owned + 80 halo cells; LDS 72 KB (c64) or 145 KB (c128)
-    const int tx = (c->n1 + BX - 1) / BX, ty = (c->n2 + BY - 1) / BY;
+    using S = FusedShape<T>;
+    const int tx = (c->n1 + S::BX - 1) / S::BX, ty = (c->n2 + S::BY - 1) / S::BY;
     const long long cols = (long long)tx * ty * nrhs;
-    const int nzc = fused_z_chunk(c->n3, cols, (long long)c->num_cu * (sizeof(T) == 4 ? 2 : 1));
+    const int nzc = fused_z_chunk(c->n3, cols, (long long)c->num_cu * S::PER_CU);
     const long long nb = cols * ((c->n3 + nzc - 1) / nzc);
     const unsigned nbl = (unsigned)((nb + 7) / 8 * 8);
     const double w = c->omega[i_omega];
     c->prof.begin(c->stream, OUT == 0 ? LS_PNAME(T, "contrast_fused") : LS_PNAME(T, "contrast_fused_T"));
-    hipLaunchKernelGGL((k_contrast_zmarch<T, BX, BY, NT, OUT>), dim3(nbl), dim3(NT), 0, c->stream, u,
-                       contrast_of<T>(c), density_of<T>(c), out, y, nrhs, c->n1, c->n2, c->n3, c->L1, c->L2,
-                       T(1.0 / c->h), T(w * w), tx, ty, nzc, nb);
+    hipLaunchKernelGGL((k_contrast_zmarch<T, S::BX, S::BY, S::NT, S::PER_CU, S::DB, OUT>), dim3(nbl), dim3(S::NT), 0,
+                       c->stream, u, contrast_of<T>(c), density_of<T>(c), out, y, nrhs, c->n1, c->n2, c->n3, c->L1,
+                       c->L2, T(1.0 / c->h), T(w * w), tx, ty, nzc, nb);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
