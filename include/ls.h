@@ -149,6 +149,11 @@ int ls_solve(ls_ctx* ctx, int i_omega, const void* b, int n_rhs, double tol, int
 int ls_solve_moment(ls_ctx* ctx, int i_omega, const double M[6], const int src[3], double t0,
                     double tol, int maxit, int precision, void* u_out, ls_info* info);
 
+/* Convenience form for one unit point force: builds b with ls_rhs_force (F delta_cell / h^3,
+ * Eq 6), then ls_solve.  Used for reciprocity checks and receiver-side Green's functions. */
+int ls_solve_force(ls_ctx* ctx, int i_omega, const double F[3], const int cell[3], double tol, int maxit,
+                   int precision, void* u_out, ls_info* info);
+
 /* Voigt engineering strain of n_rhs fields (Eq 17-18): eps device c128 [n_rhs][6][N3][N2][N1]. */
 int ls_strain(ls_ctx* ctx, const void* u, void* eps, int n_rhs);
 
@@ -175,6 +180,17 @@ int ls_solve_T(ls_ctx* ctx, int i_omega, const void* b, int n_rhs, double tol, i
                const void* x0, void* x_out, ls_info* info);
 int ls_grad_contrast(ls_ctx* ctx, int i_omega, const void* u, const void* mu, int n_rhs, double* g_dC,
                      double* g_drho);
+
+/* The whole gradient of one frequency from the forward fields u and the adjoint solutions lam_bar
+ * (lam_bar solving A^T lam_bar = conj(P^H r), from ls_solve_T), both device c128
+ * [n_rhs][3][N3][N2][N1], n_rhs <= max_rhs: forms mu = conj(Gconv lam_bar) in the context's
+ * workspace, accumulates g_dC and g_drho as ls_grad_contrast does, and, when g_M is not NULL,
+ * writes the moment-tensor gradient of each right-hand side's source (Eq 13-16)
+ *     g_M[r][J] = Re[e^{i w t0[r]} conj(eps_J(mu_r)(src_r))] / h^3
+ * into the host array g_M [n_rhs][6] (src: host [n_rhs][3] cells inside the grid; t0: host
+ * [n_rhs]).  Synchronises the stream when g_M is given, else asynchronous. */
+int ls_grad(ls_ctx* ctx, int i_omega, const void* u, const void* lam_bar, int n_rhs, const int* src,
+            const double* t0, double* g_dC, double* g_drho, double* g_M);
 
 /* Per-kernel timing of the library's own launches.  ls_profile(ctx, 1) starts recording a
  * HIP event pair around every kernel launch on the context's stream (at most a fixed number

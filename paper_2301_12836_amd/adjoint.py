@@ -7,9 +7,10 @@ components at the receiver cells are returned, complex [n_freq, n_src, 3, n_rec]
 Backward (adjoint-state method): with g = dL/d(data) (PyTorch's convention: for L = 1/2 ||data - d||^2
 it is the residual data - d), per frequency
   A^T lambda_bar = conj(P^H g)         (ls_solve_T; A^H lambda = P^H g with lambda_bar = conj(lambda))
-  mu = conj(Gconv lambda_bar)          (ls_convolve)
-  dL/d dC, dL/d drho                   (ls_grad_contrast, accumulated over frequencies and sources)
-  dL/d M_J = Re[e^{i w t0} conj(eps_J(mu)(s))] / h^3   (ls_strain at the source cell)
+  then, in one ls_grad call:
+  mu = conj(Gconv lambda_bar)
+  dL/d dC, dL/d drho                   (accumulated over frequencies and sources)
+  dL/d M_J = Re[e^{i w t0} conj(eps_J(mu)(s))] / h^3   (strain of mu at the source cell)
 because dA = -Gconv dB, du0/dM_J = e^{i w t0} Gconv E^T (e_J delta_s)/h^3 and Gconv^H = conj(Gconv).
 All field work runs in the HIP library; torch only gathers receiver values and adds small arrays.
 """
@@ -75,7 +76,6 @@ class _LSData(torch.autograd.Function):
         g21 = torch.zeros((21,) + ctx.field_shape[1:], dtype=torch.float64, device=ctx.device)
         grho = torch.zeros(ctx.field_shape[1:], dtype=torch.float64, device=ctx.device)
         gM = torch.zeros((setup.n_src, 6), dtype=torch.float64, device=ctx.device)
-        h3 = ctx.h ** 3
         for iw, w in enumerate(ctx.omegas):
             adj = torch.zeros((setup.n_src,) + ctx.field_shape, dtype=torch.complex128, device=ctx.device)
             for s in range(setup.n_src):
@@ -84,12 +84,10 @@ class _LSData(torch.autograd.Function):
                     comp[c].index_put_((setup.rk, setup.rj, setup.ri), g[iw, s, c].conj().to(torch.complex128),
                                        accumulate=True)
             lam_bar, _ = ctx.solve_T(adj, i_omega=iw, tol=setup.tol, maxit=setup.maxit, precision=setup.precision)
-            mu = torch.conj_physical(ctx.convolve(lam_bar, i_omega=iw))
-            ctx.grad_contrast(setup.fields[iw], mu, i_omega=iw, g_dC=g21, g_drho=grho)
-            eps = ctx.strain(mu)
-            for s, (i, j, k) in enumerate(setup.source_cells):
-                phase = complex(np.exp(1j * w * setup.t0[s]))
-                gM[s] += (phase * eps[s, :, k, j, i].conj()).real / h3
+            # one library call: mu = conj(Gconv lam_bar), then the dC, drho and moment-tensor gradients
+            _, _, gMw = ctx.grad(setup.fields[iw], lam_bar, i_omega=iw, src=setup.source_cells, t0=setup.t0,
+                                 g_dC=g21, g_drho=grho)
+            gM += torch.from_numpy(gMw).to(gM.device)
         return g21, grho, gM.to(torch.float64), None
 
 

@@ -299,7 +299,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     A((void**)&c->partials, (size_t)c->max_rhs * kRedSlots * kRedBlocks * sizeof(double));
     A((void**)&c->state, (size_t)c->max_rhs * kStateLen * sizeof(double));
     A((void**)&c->red, 4 * kRedBlocks * sizeof(double));
-    A(&c->stage, 4096);
+    A(&c->stage, 8192);
     if (rc == LS_OK) {
         const size_t hb = std::max<size_t>(4 * kRedBlocks, (size_t)c->max_rhs * kStateLen) * sizeof(double);
         if (hipHostMalloc((void**)&c->red_host, hb, hipHostMallocDefault) != hipSuccess) {
@@ -419,6 +419,27 @@ int ls_grad_contrast(ls_ctx* c, int i_omega, const void* u, const void* mu, int 
     return grad_contrast_launch(c, i_omega, (const z128*)u, (const z128*)mu, n_rhs, g_dC, g_drho);
 }
 
+int ls_grad(ls_ctx* c, int i_omega, const void* u, const void* lam_bar, int n_rhs, const int* src, const double* t0,
+            double* g_dC, double* g_drho, double* g_M) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!u || !lam_bar || !g_dC || !g_drho) return fail(LS_ERR_ARG, "null pointer");
+    if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    if (g_M) {
+        if (!src || !t0) return fail(LS_ERR_ARG, "g_M needs the source cells and times");
+        for (int r = 0; r < n_rhs; ++r) {
+            if ((rc = check_cell(c, src + 3 * r))) return rc;
+            if (!std::isfinite(t0[r])) return fail(LS_ERR_ARG, "non-finite source time");
+        }
+    }
+    z128* mu = (z128*)c->gs;  // mu = conj(Gconv lam_bar), in the workspace of the transposed operator
+    if ((rc = convolve_op<double>(c, i_omega, (const z128*)lam_bar, mu, n_rhs))) return rc;
+    if ((rc = conj_launch(c, mu, 3 * c->ncell * n_rhs))) return rc;
+    if ((rc = grad_contrast_launch(c, i_omega, (const z128*)u, mu, n_rhs, g_dC, g_drho))) return rc;
+    if (g_M) return grad_moment_launch(c, i_omega, mu, n_rhs, src, t0, g_M);
+    return LS_OK;
+}
+
 int ls_rhs_moment(ls_ctx* c, int i_omega, const double M[6], const int src[3], double t0, void* b) {
     int rc;
     if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega)) || (rc = check_cell(c, src))) return rc;
@@ -493,6 +514,13 @@ int ls_solve(ls_ctx* c, int i_omega, const void* b, int n_rhs, double tol, int m
 int ls_solve_moment(ls_ctx* c, int i_omega, const double M[6], const int src[3], double t0, double tol, int maxit,
                     int precision, void* u_out, ls_info* info) {
     int rc = ls_rhs_moment(c, i_omega, M, src, t0, c ? (void*)c->bd : nullptr);
+    if (rc) return rc;
+    return ls_solve(c, i_omega, c->bd, 1, tol, maxit, precision, nullptr, u_out, info);
+}
+
+int ls_solve_force(ls_ctx* c, int i_omega, const double F[3], const int cell[3], double tol, int maxit, int precision,
+                   void* u_out, ls_info* info) {
+    int rc = ls_rhs_force(c, i_omega, F, cell, c ? (void*)c->bd : nullptr);
     if (rc) return rc;
     return ls_solve(c, i_omega, c->bd, 1, tol, maxit, precision, nullptr, u_out, info);
 }

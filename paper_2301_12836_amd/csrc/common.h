@@ -122,7 +122,7 @@ struct Ctx {
         *x32 = nullptr, *b32 = nullptr;
     double* partials = nullptr;  // reduction partials [max_rhs][kRedSlots][kRedBlocks]
     double* state = nullptr;     // BiCGSTAB scalars per right-hand side [max_rhs][kStateLen]
-    void* stage = nullptr;       // small host-to-device staging area (4 KB)
+    void* stage = nullptr;       // small host/device staging area (8 KB)
     double* red = nullptr;       // reduction results (device)
     double* red_host = nullptr;  // pinned host mirror
     long long bytes = 0;
@@ -159,6 +159,9 @@ template <typename T>
 int to_work(Ctx* c, const cpx<T>* f, cpx<T>* work, int nrhs);
 int grad_contrast_launch(Ctx* c, int i_omega, const z128* u, const z128* mu, int nrhs, double* g21, double* grho);
 int fold_background(Ctx* c, const double* dc_in, const double* drho_in, const double fold21[21]);
+int conj_launch(Ctx* c, z128* a, long long m);
+int grad_moment_launch(Ctx* c, int i_omega, const z128* mu, int nrhs, const int* src, const double* t0,
+                       double* gM);
 int strain_launch(Ctx* c, const z128* u, z128* eps, int nrhs);
 
 // Green's tables and incident fields; see green.hip

@@ -493,6 +493,30 @@ __global__ __launch_bounds__(kThreads) void k_grad_contrast(const z128* __restri
     grho[p] += w2 * ar;
 }
 
+// a[p] = conj(a[p])
+__global__ void k_conj(z128* __restrict__ a, long long m) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < m) a[p].y = -a[p].y;
+}
+
+// Moment-tensor gradient: gM[r][J] = Re[e^{i w t0_r} conj(eps_J(mu_r)(s_r))] / h^3 (one thread per
+// right-hand side; s_r inside the grid, checked on the host)
+__global__ void k_grad_moment(const z128* __restrict__ mu, const int* __restrict__ src, const double* __restrict__ t0,
+                              double* __restrict__ gM, int nrhs, int N1, int N2, int N3, double inv_h, double w,
+                              double inv_h3) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const long long n = (long long)N1 * N2 * N3;
+    const int i = src[3 * r], j = src[3 * r + 1], k = src[3 * r + 2];
+    const long long p = ((long long)k * N2 + j) * N1 + i;
+    z128 eps[6];
+    strain_at(mu + (long long)r * 3 * n, n, p, i, j, k, N1, N2, N3, inv_h, eps);
+    double sn, cs;
+    sincos(w * t0[r], &sn, &cs);
+#pragma unroll
+    for (int J = 0; J < 6; ++J) gM[6 * r + J] = (cs * eps[J].x + sn * eps[J].y) * inv_h3;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_strain_out(const cpx<T>* __restrict__ u, cpx<T>* __restrict__ eps_out,
                                                          int nrhs, int N1, int N2, int N3, T inv_h) {
@@ -669,6 +693,30 @@ int grad_contrast_launch(Ctx* c, int i_omega, const z128* u, const z128* mu, int
                        c->n3, 1.0 / c->h, w * w);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
+    return LS_OK;
+}
+
+int conj_launch(Ctx* c, z128* a, long long m) {
+    hipLaunchKernelGGL(k_conj, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, c->stream, a, m);
+    LS_HIP(hipGetLastError());
+    return LS_OK;
+}
+
+// src: host [nrhs][3] cells (inside the grid); t0: host [nrhs]; gM: host [nrhs][6].  Stages src and t0
+// through the context's staging area and waits for the result.
+int grad_moment_launch(Ctx* c, int i_omega, const z128* mu, int nrhs, const int* src, const double* t0, double* gM) {
+    char* st = (char*)c->stage;
+    int* dsrc = (int*)st;
+    double* dt0 = (double*)(st + 1024);
+    double* dgM = (double*)(st + 2048);
+    LS_HIP(hipMemcpyAsync(dsrc, src, 3 * nrhs * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    LS_HIP(hipMemcpyAsync(dt0, t0, nrhs * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const double h3 = c->h * c->h * c->h;
+    hipLaunchKernelGGL(k_grad_moment, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, c->stream, mu, dsrc, dt0, dgM,
+                       nrhs, c->n1, c->n2, c->n3, 1.0 / c->h, c->omega[i_omega], 1.0 / h3);
+    LS_HIP(hipGetLastError());
+    LS_HIP(hipMemcpyAsync(gM, dgM, 6 * nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    LS_HIP(hipStreamSynchronize(c->stream));
     return LS_OK;
 }
 

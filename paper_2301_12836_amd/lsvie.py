@@ -5,9 +5,10 @@ torch tensors to device pointers and checks shapes.  If the shared library has n
 loading fails loudly (there is no CPU fallback).
 
 The module-level functions carry the C names (``ls_setup``, ``ls_apply``, ``ls_apply_c64``,
-``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_moment``, ``ls_strain``,
-``ls_profile``, ``ls_profile_read``, ``ls_device_bytes``, ``ls_destroy``); ``Context`` wraps them
-for convenience.
+``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_moment``, ``ls_solve_force``,
+``ls_strain``, ``ls_apply_T``, ``ls_convolve``, ``ls_solve_T``, ``ls_grad_contrast``, ``ls_grad``,
+``ls_profile``, ``ls_profile_read``, ``ls_device_bytes``, ``ls_kernel_variants``, ``ls_destroy``);
+``Context`` wraps them for convenience.
 """
 
 import ctypes
@@ -38,7 +39,8 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
                LS_ERR_NONFINITE: "LS_ERR_NONFINITE", LS_ERR_STATE: "LS_ERR_STATE"}
 
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
-            "ls_solve_moment", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve", "ls_solve_T", "ls_grad_contrast",
+            "ls_solve_moment", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve",
+            "ls_solve_T", "ls_grad_contrast", "ls_grad",
             "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_last_error")
 
 
@@ -100,6 +102,8 @@ def load():
         "ls_convolve": (I, [P, I, P, P, I]),
         "ls_solve_T": (I, [P, I, P, I, D, I, I, P, P, ctypes.POINTER(Info)]),
         "ls_grad_contrast": (I, [P, I, P, P, I, P, P]),
+        "ls_grad": (I, [P, I, P, P, I, ip, dp, P, P, dp]),
+        "ls_solve_force": (I, [P, I, dp, ip, D, I, I, P, ctypes.POINTER(Info)]),
         "ls_profile": (I, [P, I]),
         "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, I]),
         "ls_device_bytes": (ctypes.c_longlong, [P]),
@@ -217,6 +221,17 @@ def ls_solve_moment(ctx, i_omega, M, src, t0, tol, maxit, precision, u_out, rais
     return code, info.as_dict()
 
 
+def ls_solve_force(ctx, i_omega, F, cell, tol, maxit, precision, u_out, raise_on_error=True):
+    f, fp = _dbl(F, 3)
+    s, sp = _int3(cell)
+    info = Info()
+    code = load().ls_solve_force(ctx, int(i_omega), fp, sp, float(tol), int(maxit), int(precision), _ptr(u_out),
+                                 ctypes.byref(info))
+    if raise_on_error:
+        _check(code)
+    return code, info.as_dict()
+
+
 def ls_strain(ctx, u, eps, n_rhs):
     return _check(load().ls_strain(ctx, _ptr(u), _ptr(eps), int(n_rhs)))
 
@@ -241,6 +256,23 @@ def ls_solve_T(ctx, i_omega, b, n_rhs, tol, maxit, precision, x0, x_out, raise_o
 def ls_grad_contrast(ctx, i_omega, u, mu, n_rhs, g_dC, g_drho):
     return _check(load().ls_grad_contrast(ctx, int(i_omega), _ptr(u), _ptr(mu), int(n_rhs), _ptr(g_dC),
                                           _ptr(g_drho)))
+
+
+def ls_grad(ctx, i_omega, u, lam_bar, n_rhs, g_dC, g_drho, src=None, t0=None):
+    """Returns g_M as a numpy [n_rhs, 6] array when src (cells [n_rhs, 3]) is given, else None."""
+    if src is None:
+        _check(load().ls_grad(ctx, int(i_omega), _ptr(u), _ptr(lam_bar), int(n_rhs), None, None, _ptr(g_dC),
+                              _ptr(g_drho), None))
+        return None
+    cells = np.ascontiguousarray(np.asarray(src, dtype=np.int32).reshape(int(n_rhs), 3))
+    times = np.ascontiguousarray(np.broadcast_to(np.asarray(0.0 if t0 is None else t0, dtype=np.float64),
+                                                 (int(n_rhs),)))
+    gM = np.zeros((int(n_rhs), 6), dtype=np.float64)
+    _check(load().ls_grad(ctx, int(i_omega), _ptr(u), _ptr(lam_bar), int(n_rhs),
+                          cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                          times.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(g_dC), _ptr(g_drho),
+                          gM.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return gM
 
 
 def ls_profile(ctx, enable):
@@ -421,6 +453,33 @@ class Context:
             self._check(g_drho, self.field_shape[1:], torch.float64, "g_drho")
         ls_grad_contrast(self.handle, i_omega, u, mu, nrhs, g_dC, g_drho)
         return g_dC, g_drho
+
+    def solve_force(self, F, cell, i_omega=0, tol=1e-8, maxit=2000, precision=None, out=None,
+                    raise_on_error=True):
+        out = self.empty() if out is None else self._check(out, self.field_shape, self.torch.complex128)
+        prec = LS_PREC_MIXED if (precision or ("mixed" if self.mixed else "c128")) == "mixed" else LS_PREC_C128
+        code, info = ls_solve_force(self.handle, i_omega, F, cell, tol, maxit, prec, out, raise_on_error)
+        return out, info
+
+    def grad(self, u, lam_bar, i_omega=0, src=None, t0=None, g_dC=None, g_drho=None):
+        """Gradient of one frequency from forward fields u and adjoint solutions lam_bar (A^T lam_bar =
+        conj(P^H r)): accumulates g_dC [21, N3, N2, N1] and g_drho [N3, N2, N1] (float64, on the device) and
+        returns (g_dC, g_drho, g_M) with g_M a numpy [n_rhs, 6] array when src is given, else None."""
+        torch = self.torch
+        u, nrhs = self._field(u, torch.complex128)
+        lam_bar, nrhs2 = self._field(lam_bar, torch.complex128)
+        if nrhs != nrhs2:
+            raise ValueError("u and lam_bar must hold the same number of fields")
+        if g_dC is None:
+            g_dC = torch.zeros((21,) + self.field_shape[1:], dtype=torch.float64, device=self.device)
+        else:
+            self._check(g_dC, (21,) + self.field_shape[1:], torch.float64, "g_dC")
+        if g_drho is None:
+            g_drho = torch.zeros(self.field_shape[1:], dtype=torch.float64, device=self.device)
+        else:
+            self._check(g_drho, self.field_shape[1:], torch.float64, "g_drho")
+        gM = ls_grad(self.handle, i_omega, u, lam_bar, nrhs, g_dC, g_drho, src=src, t0=t0)
+        return g_dC, g_drho, gM
 
     def strain(self, u):
         u, nrhs = self._field(u, self.torch.complex128)

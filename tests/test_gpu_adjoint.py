@@ -148,3 +148,16 @@ def test_lazy_conjugate_views_are_materialised():
     assert torch.equal(ctx.apply(u.conj()), ctx.apply(torch.conj_physical(u)))
     assert torch.equal(ctx.apply(-u), ctx.apply(torch.neg(u).clone()))
     ctx.close()
+
+
+def test_solve_force_matches_dense():
+    """Unit point-force solve (the convenience entry point) against the oracle's dense solve."""
+    m = models.random_medium((7, 6, 5), seed=4, rel=0.1, aniso_background=True)
+    ctx = lsvie.context_from_model(m, omegas=[W])
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, W)
+    F, cell = (0.3, -1.0, 0.7), (2, 4, 1)
+    want = solve.solve_dense(P.dense_A(), P.rhs_force(np.array(F), cell))
+    x, info = ctx.solve_force(F, cell, tol=1e-12, maxit=1000)
+    assert info["status"] == 0 and info["rel_res_true"] <= 1e-12
+    assert rel(to_np(x), want) < 1e-10
+    ctx.close()
