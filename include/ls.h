@@ -154,6 +154,33 @@ int ls_solve_moment(ls_ctx* ctx, int i_omega, const double M[6], const int src[3
 int ls_solve_force(ls_ctx* ctx, int i_omega, const double F[3], const int cell[3], double tol, int maxit,
                    int precision, void* u_out, ls_info* info);
 
+/* One moment-tensor solve of a batch: the source M (Voigt 11,22,33,23,13,12) at cell src with rupture
+ * time t0, on context ctxs[ctx] at frequency index i_omega; the solution goes to u_out (device c128
+ * [3][N3][N2][N1] of that context's grid, owned by the caller). */
+typedef struct ls_job {
+    int ctx;
+    int i_omega;
+    double M[6];
+    int src[3];
+    double t0;
+    void* u_out;
+} ls_job;
+
+/* Solve every job of a batch over several contexts, whose grids may differ (the paper treats each
+ * frequency and source as an independent system, Eq 21-22).  Per context the jobs are grouped by
+ * frequency and solved max_rhs at a time as one multi-right-hand-side solve (ls_solve with the given
+ * precision), so device residency stays within what the contexts were built for; contexts are
+ * driven concurrently, one host thread and the context's own stream each (contexts must be
+ * distinct and are used exclusively for the duration of the call).  The first call on a context
+ * allocates two [max_rhs][3][N3][N2][N1] c128 batch buffers that it keeps until ls_destroy.
+ * infos: host array of n_jobs entries (may be NULL).  All arguments are checked before any work.
+ * Returns LS_OK when every job met tol; a hard error (LS_ERR_HIP, LS_ERR_OOM) of any context stops
+ * that context and is returned first; otherwise the first context's LS_ERR_NOT_CONVERGED /
+ * LS_ERR_BREAKDOWN / LS_ERR_NONFINITE (every job's u_out and info are still written).
+ * Synchronises every context's stream. */
+int ls_solve_batch(ls_ctx* const* ctxs, int n_ctx, const ls_job* jobs, int n_jobs, double tol, int maxit,
+                   int precision, ls_info* infos);
+
 /* Voigt engineering strain of n_rhs fields (Eq 17-18): eps device c128 [n_rhs][6][N3][N2][N1]. */
 int ls_strain(ls_ctx* ctx, const void* u, void* eps, int n_rhs);
 

@@ -6,6 +6,9 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "common.h"
 
@@ -92,7 +95,7 @@ static void release(Ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
                     c->xd, c->bd, c->gs, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
-                    c->state, c->stage, c->red};
+                    c->state, c->stage, c->red, c->batch_b, c->batch_x};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto q : c->ghat) (void)hipFree(q);
@@ -181,6 +184,63 @@ bool is_isotropic(const double* C) {
 
 }  // namespace
 
+namespace {
+
+int check_moment(const ls_ctx* c, int i_omega, const double M[6], const int src[3], double t0) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega)) || (rc = check_cell(c, src))) return rc;
+    if (!M) return fail(LS_ERR_ARG, "null moment tensor");
+    for (int J = 0; J < 6; ++J)
+        if (!std::isfinite(M[J])) return fail(LS_ERR_ARG, "non-finite moment tensor");
+    if (!std::isfinite(t0)) return fail(LS_ERR_ARG, "non-finite rupture time");
+    return LS_OK;
+}
+
+// incident field of a moment tensor into b (arguments already checked)
+int rhs_moment_into(Ctx* c, int i_omega, const double M[6], const int src[3], double t0, z128* b) {
+    // E^T (M delta_src): for each axis a and component c, row src_a of the 1-D difference matrix
+    // D_a, weighted by the moment component of the Voigt pair (a, c)
+    static const int voigt[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+    const int n[3] = {c->n1, c->n2, c->n3};
+    const double ih = 1.0 / c->h;
+    std::map<std::array<int, 3>, std::array<double, 3>> pts;
+    for (int a = 0; a < 3; ++a) {
+        int cols[2];
+        double coef[2];
+        const int s = src[a];
+        if (s == 0) {
+            cols[0] = 0, coef[0] = -ih, cols[1] = 1, coef[1] = ih;
+        } else if (s == n[a] - 1) {
+            cols[0] = s, coef[0] = ih, cols[1] = s - 1, coef[1] = -ih;
+        } else {
+            cols[0] = s + 1, coef[0] = 0.5 * ih, cols[1] = s - 1, coef[1] = -0.5 * ih;
+        }
+        for (int cc = 0; cc < 3; ++cc) {
+            const double m = M[voigt[a][cc]];
+            if (m == 0.0) continue;
+            for (int q = 0; q < 2; ++q) {
+                std::array<int, 3> cell = {src[0], src[1], src[2]};
+                cell[a] = cols[q];
+                auto& f = pts[cell];
+                f[cc] += m * coef[q];
+            }
+        }
+    }
+    std::vector<int> cells;
+    std::vector<double> F;
+    for (auto& kv : pts) {
+        for (int a = 0; a < 3; ++a) cells.push_back(kv.first[a]);
+        for (int a = 0; a < 3; ++a) F.push_back(kv.second[a]);
+    }
+    if (cells.empty()) {
+        LS_HIP(hipMemsetAsync(b, 0, sizeof(z128) * c->field_elems(), c->stream));
+        return LS_OK;
+    }
+    return rhs_points_launch(c, i_omega, cells.data(), F.data(), (int)pts.size(), t0, b);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* ls_last_error(void) { return g_last_error.c_str(); }
@@ -251,9 +311,11 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     c->flags = o.flags;
     {
         int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-            c->num_cu = cus;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            c->device = dev;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+                c->num_cu = cus;
+        }
         (void)hipGetLastError();
     }
     if (!c->stream) {
@@ -440,52 +502,12 @@ int ls_grad(ls_ctx* c, int i_omega, const void* u, const void* lam_bar, int n_rh
     return LS_OK;
 }
 
+
 int ls_rhs_moment(ls_ctx* c, int i_omega, const double M[6], const int src[3], double t0, void* b) {
     int rc;
-    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega)) || (rc = check_cell(c, src))) return rc;
-    if (!M || !b) return fail(LS_ERR_ARG, "null argument");
-    for (int J = 0; J < 6; ++J)
-        if (!std::isfinite(M[J])) return fail(LS_ERR_ARG, "non-finite moment tensor");
-    if (!std::isfinite(t0)) return fail(LS_ERR_ARG, "non-finite rupture time");
-    // E^T (M delta_src): for each axis a and component c, row src_a of the 1-D difference matrix
-    // D_a, weighted by the moment component of the Voigt pair (a, c)
-    static const int voigt[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
-    const int n[3] = {c->n1, c->n2, c->n3};
-    const double ih = 1.0 / c->h;
-    std::map<std::array<int, 3>, std::array<double, 3>> pts;
-    for (int a = 0; a < 3; ++a) {
-        int cols[2];
-        double coef[2];
-        const int s = src[a];
-        if (s == 0) {
-            cols[0] = 0, coef[0] = -ih, cols[1] = 1, coef[1] = ih;
-        } else if (s == n[a] - 1) {
-            cols[0] = s, coef[0] = ih, cols[1] = s - 1, coef[1] = -ih;
-        } else {
-            cols[0] = s + 1, coef[0] = 0.5 * ih, cols[1] = s - 1, coef[1] = -0.5 * ih;
-        }
-        for (int cc = 0; cc < 3; ++cc) {
-            const double m = M[voigt[a][cc]];
-            if (m == 0.0) continue;
-            for (int q = 0; q < 2; ++q) {
-                std::array<int, 3> cell = {src[0], src[1], src[2]};
-                cell[a] = cols[q];
-                auto& f = pts[cell];
-                f[cc] += m * coef[q];
-            }
-        }
-    }
-    std::vector<int> cells;
-    std::vector<double> F;
-    for (auto& kv : pts) {
-        for (int a = 0; a < 3; ++a) cells.push_back(kv.first[a]);
-        for (int a = 0; a < 3; ++a) F.push_back(kv.second[a]);
-    }
-    if (cells.empty()) {
-        LS_HIP(hipMemsetAsync(b, 0, sizeof(z128) * c->field_elems(), c->stream));
-        return LS_OK;
-    }
-    return rhs_points_launch(c, i_omega, cells.data(), F.data(), (int)pts.size(), t0, (z128*)b);
+    if ((rc = check_moment(c, i_omega, M, src, t0))) return rc;
+    if (!b) return fail(LS_ERR_ARG, "null argument");
+    return rhs_moment_into(c, i_omega, M, src, t0, (z128*)b);
 }
 
 int ls_rhs_force(ls_ctx* c, int i_omega, const double F[3], const int cell[3], void* b) {
@@ -523,6 +545,122 @@ int ls_solve_force(ls_ctx* c, int i_omega, const double F[3], const int cell[3],
     int rc = ls_rhs_force(c, i_omega, F, cell, c ? (void*)c->bd : nullptr);
     if (rc) return rc;
     return ls_solve(c, i_omega, c->bd, 1, tol, maxit, precision, nullptr, u_out, info);
+}
+
+}  // extern "C"
+
+namespace {
+
+bool soft_failure(int rc) { return rc == LS_ERR_NOT_CONVERGED || rc == LS_ERR_BREAKDOWN || rc == LS_ERR_NONFINITE; }
+
+// One multi-right-hand-side solve of the jobs idx (all of context c and one frequency): incident
+// fields into the context's batch buffer, the batched solve, then each solution copied to its job.
+int run_batch(Ctx* c, const ls_job* jobs, const std::vector<int>& idx, double tol, int maxit, int precision,
+              ls_info* infos) {
+    const size_t fe = c->field_elems();
+    if (!c->batch_b) {
+        LS_HIP(hipMalloc((void**)&c->batch_b, (size_t)c->max_rhs * fe * sizeof(z128)));
+        LS_HIP(hipMalloc((void**)&c->batch_x, (size_t)c->max_rhs * fe * sizeof(z128)));
+    }
+    const int nr = (int)idx.size();
+    const int iw = jobs[idx[0]].i_omega;
+    int rc;
+    for (int r = 0; r < nr; ++r) {
+        const ls_job& j = jobs[idx[r]];
+        if ((rc = rhs_moment_into(c, iw, j.M, j.src, j.t0, c->batch_b + r * fe))) return rc;
+    }
+    std::vector<ls_info> inf(nr);
+    rc = solve_systems(c, iw, c->batch_b, nr, tol, maxit, precision, nullptr, c->batch_x, inf.data());
+    if (rc != LS_OK && !soft_failure(rc)) return rc;
+    for (int r = 0; r < nr; ++r) {
+        LS_HIP(hipMemcpyAsync(jobs[idx[r]].u_out, c->batch_x + r * fe, fe * sizeof(z128), hipMemcpyDeviceToDevice,
+                              c->stream));
+        if (infos) infos[idx[r]] = inf[r];
+    }
+    LS_HIP(hipStreamSynchronize(c->stream));
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ls_solve_batch(ls_ctx* const* ctxs, int n_ctx, const ls_job* jobs, int n_jobs, double tol, int maxit,
+                   int precision, ls_info* infos) {
+    int rc;
+    if (!ctxs || n_ctx < 1 || n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(LS_ERR_ARG, "bad batch arguments");
+    if (!(tol > 0) || !(tol < 1)) return fail(LS_ERR_ARG, "tol must be in (0, 1)");
+    if (maxit < 1) return fail(LS_ERR_ARG, "maxit must be >= 1");
+    if (precision != LS_PREC_C128 && precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
+    for (int i = 0; i < n_ctx; ++i) {
+        if ((rc = check_ctx(ctxs[i]))) return rc;
+        if (precision == LS_PREC_MIXED && !ctxs[i]->mixed)
+            return fail(LS_ERR_STATE, "mixed precision needs contexts built with LS_PREC_MIXED");
+        for (int k = 0; k < i; ++k)
+            if (ctxs[k] == ctxs[i]) return fail(LS_ERR_ARG, "a context appears twice in the batch");
+    }
+    for (int j = 0; j < n_jobs; ++j) {
+        if (jobs[j].ctx < 0 || jobs[j].ctx >= n_ctx) return fail(LS_ERR_ARG, "job context index out of range");
+        if ((rc = check_moment(ctxs[jobs[j].ctx], jobs[j].i_omega, jobs[j].M, jobs[j].src, jobs[j].t0))) return rc;
+        if (!jobs[j].u_out) return fail(LS_ERR_ARG, "null job output");
+    }
+    // plan: per context, its jobs grouped by frequency (in order of first appearance), in chunks of max_rhs
+    std::vector<std::vector<std::vector<int>>> plan(n_ctx);
+    for (int i = 0; i < n_ctx; ++i) {
+        std::vector<int> freqs;
+        for (int j = 0; j < n_jobs; ++j)
+            if (jobs[j].ctx == i && std::find(freqs.begin(), freqs.end(), jobs[j].i_omega) == freqs.end())
+                freqs.push_back(jobs[j].i_omega);
+        for (int w : freqs) {
+            std::vector<int> chunk;
+            for (int j = 0; j < n_jobs; ++j) {
+                if (jobs[j].ctx != i || jobs[j].i_omega != w) continue;
+                chunk.push_back(j);
+                if ((int)chunk.size() == ctxs[i]->max_rhs) {
+                    plan[i].push_back(chunk);
+                    chunk.clear();
+                }
+            }
+            if (!chunk.empty()) plan[i].push_back(chunk);
+        }
+    }
+    // one worker per context with work, each driving its context's stream (the solves synchronise
+    // for their convergence tests, so contexts on different streams overlap on the device)
+    std::vector<int> codes(n_ctx, LS_OK);
+    std::vector<std::string> msgs(n_ctx);
+    auto work = [&](int i) {
+        Ctx* c = ctxs[i];
+        if (hipSetDevice(c->device) != hipSuccess) {
+            (void)hipGetLastError();
+            codes[i] = LS_ERR_HIP;
+            msgs[i] = "hipSetDevice failed";
+            return;
+        }
+        for (const auto& batch : plan[i]) {
+            const int r = run_batch(c, jobs, batch, tol, maxit, precision, infos);
+            if (r == LS_OK) continue;
+            if (codes[i] == LS_OK || !soft_failure(r)) {
+                codes[i] = r;
+                msgs[i] = ls_last_error();
+            }
+            if (!soft_failure(r)) return;
+        }
+    };
+    std::vector<int> active;
+    for (int i = 0; i < n_ctx; ++i)
+        if (!plan[i].empty()) active.push_back(i);
+    if (active.size() == 1) {
+        work(active[0]);
+    } else if (!active.empty()) {
+        std::vector<std::thread> th;
+        for (int i : active) th.emplace_back(work, i);
+        for (auto& t : th) t.join();
+    }
+    for (int i = 0; i < n_ctx; ++i)  // hard errors first, then the first unconverged context
+        if (codes[i] != LS_OK && !soft_failure(codes[i])) return fail(codes[i], msgs[i]);
+    for (int i = 0; i < n_ctx; ++i)
+        if (codes[i] != LS_OK) return fail(codes[i], msgs[i]);
+    return LS_OK;
 }
 
 int ls_strain(ls_ctx* c, const void* u, void* eps, int n_rhs) {

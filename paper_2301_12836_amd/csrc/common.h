@@ -90,6 +90,7 @@ struct Ctx {
                                        // so it stays ordered with work on the legacy default stream)
     int flags = 0;
     int num_cu = 256;  // compute units of the device (block-count heuristics)
+    int device = 0;    // the HIP device the context was set up on
     // FFT kernel variant per pass and precision: 0 register four-step, 1 LDS Stockham
     // passes: 0 x forward, 1 y forward, 2 z with Green multiply, 3 y inverse, 4 x inverse
     int variant[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
@@ -123,6 +124,7 @@ struct Ctx {
     double* partials = nullptr;  // reduction partials [max_rhs][kRedSlots][kRedBlocks]
     double* state = nullptr;     // BiCGSTAB scalars per right-hand side [max_rhs][kStateLen]
     void* stage = nullptr;       // small host/device staging area (8 KB)
+    z128 *batch_b = nullptr, *batch_x = nullptr;  // [max_rhs][3][n] right-hand sides / solutions of ls_solve_batch (allocated on its first use)
     double* red = nullptr;       // reduction results (device)
     double* red_host = nullptr;  // pinned host mirror
     long long bytes = 0;

@@ -6,9 +6,10 @@ loading fails loudly (there is no CPU fallback).
 
 The module-level functions carry the C names (``ls_setup``, ``ls_apply``, ``ls_apply_c64``,
 ``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_moment``, ``ls_solve_force``,
-``ls_strain``, ``ls_apply_T``, ``ls_convolve``, ``ls_solve_T``, ``ls_grad_contrast``, ``ls_grad``,
-``ls_profile``, ``ls_profile_read``, ``ls_device_bytes``, ``ls_kernel_variants``, ``ls_destroy``);
-``Context`` wraps them for convenience.
+``ls_solve_batch``, ``ls_strain``, ``ls_apply_T``, ``ls_convolve``, ``ls_solve_T``,
+``ls_grad_contrast``, ``ls_grad``, ``ls_profile``, ``ls_profile_read``, ``ls_device_bytes``,
+``ls_kernel_variants``, ``ls_destroy``); ``Context`` wraps them for convenience, and
+``solve_batch`` wraps ``ls_solve_batch`` over several contexts.
 """
 
 import ctypes
@@ -40,7 +41,7 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
 
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
             "ls_solve_moment", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve",
-            "ls_solve_T", "ls_grad_contrast", "ls_grad",
+            "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch",
             "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_last_error")
 
 
@@ -65,6 +66,11 @@ class Info(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_int), ("i_omega", ctypes.c_int), ("M", ctypes.c_double * 6),
+                ("src", ctypes.c_int * 3), ("t0", ctypes.c_double), ("u_out", ctypes.c_void_p)]
 
 
 _lib = None
@@ -103,6 +109,7 @@ def load():
         "ls_solve_T": (I, [P, I, P, I, D, I, I, P, P, ctypes.POINTER(Info)]),
         "ls_grad_contrast": (I, [P, I, P, P, I, P, P]),
         "ls_grad": (I, [P, I, P, P, I, ip, dp, P, P, dp]),
+        "ls_solve_batch": (I, [ctypes.POINTER(P), I, ctypes.POINTER(Job), I, D, I, I, ctypes.POINTER(Info)]),
         "ls_solve_force": (I, [P, I, dp, ip, D, I, I, P, ctypes.POINTER(Info)]),
         "ls_profile": (I, [P, I]),
         "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, I]),
@@ -273,6 +280,17 @@ def ls_grad(ctx, i_omega, u, lam_bar, n_rhs, g_dC, g_drho, src=None, t0=None):
                           times.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(g_dC), _ptr(g_drho),
                           gM.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return gM
+
+
+def ls_solve_batch(ctxs, jobs, tol, maxit, precision, raise_on_error=True):
+    """ctxs: context handles; jobs: sequence of Job.  Returns (code, [info dict per job])."""
+    handles = (ctypes.c_void_p * len(ctxs))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in ctxs])
+    arr = (Job * max(len(jobs), 1))(*jobs)
+    infos = (Info * max(len(jobs), 1))()
+    code = load().ls_solve_batch(handles, len(ctxs), arr, len(jobs), float(tol), int(maxit), int(precision), infos)
+    if raise_on_error:
+        _check(code)
+    return code, [infos[i].as_dict() for i in range(len(jobs))]
 
 
 def ls_profile(ctx, enable):
@@ -500,6 +518,23 @@ class Context:
     @property
     def device_bytes(self):
         return ls_device_bytes(self.handle)
+
+
+def solve_batch(contexts, jobs, tol=1e-8, maxit=2000, precision="c128", raise_on_error=True):
+    """Solve moment-tensor jobs over several contexts (grids may differ) in one library call.
+
+    jobs: sequence of (context index, frequency index, M[6], (i, j, k), t0).  Returns (fields, infos):
+    one new complex128 [3, N3, N2, N1] tensor per job on its context's device, and the per-job info."""
+    outs, arr = [], []
+    for ci, iw, M, src, t0 in jobs:
+        ctx = contexts[ci]
+        out = ctx.empty()
+        outs.append(out)
+        arr.append(Job(int(ci), int(iw), (ctypes.c_double * 6)(*np.asarray(M, dtype=np.float64).reshape(6)),
+                       (ctypes.c_int * 3)(*[int(v) for v in src]), float(t0), out.data_ptr()))
+    prec = LS_PREC_MIXED if precision == "mixed" else LS_PREC_C128
+    code, infos = ls_solve_batch([c.handle for c in contexts], arr, tol, maxit, prec, raise_on_error)
+    return outs, infos
 
 
 def context_from_model(model, precision="c128", max_rhs=1, green_mode="exact", device="cuda:0", omegas=None,

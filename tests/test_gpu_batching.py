@@ -54,3 +54,42 @@ def test_autotuned_variants_keep_parity():
         assert rel(got[r], want) < 1e-10
         assert rel(got32[r], want) < 1e-5
     ctx.close()
+
+
+def test_solve_batch_over_uneven_grids():
+    """Jobs over two contexts with different grids, frequency sets and max_rhs, interleaved in the job
+    list (one frequency group larger than max_rhs): every job equals its own single solve; one equals the
+    oracle's dense solve; the mixed-precision batch meets tol; bad jobs are refused before any work."""
+    from oracle import solve
+    ma = models.random_medium((14, 12, 10), seed=21, rel=0.1, aniso_background=True)
+    mb = models.random_medium((20, 18, 16), seed=22, rel=0.1)
+    wa = [2 * np.pi * 11.0, 2 * np.pi * 23.0]
+    wb = [2 * np.pi * 17.0]
+    A = lsvie.context_from_model(ma, omegas=wa, precision="mixed", max_rhs=2)
+    B = lsvie.context_from_model(mb, omegas=wb, precision="mixed", max_rhs=3)
+    dcpl = models.double_couple(30, 60, 90)
+    jobs = [(0, 0, models.EXPLOSION, (7, 6, 5), 0.0), (1, 0, dcpl, (10, 9, 8), 0.002),
+            (0, 1, dcpl, (3, 4, 2), 0.004), (0, 0, np.eye(6)[3], (0, 11, 9), 0.0),
+            (1, 0, np.eye(6)[0], (19, 0, 15), 0.0), (0, 0, dcpl, (7, 6, 5), 0.001)]
+    tol = 1e-11
+    outs, infos = lsvie.solve_batch([A, B], jobs, tol=tol, maxit=2000, precision="c128")
+    for (ci, iw, M, src, t0), u, info in zip(jobs, outs, infos):
+        ctx = (A, B)[ci]
+        want, _ = ctx.solve(ctx.rhs_moment(M, src, i_omega=iw, t0=t0), i_omega=iw, tol=tol, precision="c128")
+        assert info["status"] == 0 and info["rel_res_true"] <= tol
+        assert rel(u.cpu().numpy(), want.cpu().numpy()) < 1e-9, (ci, iw, src)
+    P = op.Problem(ma.shape, ma.h, ma.C0, ma.rho0, ma.dc21, ma.drho, wa[1])
+    dense = solve.solve_dense(P.dense_A(), P.rhs_moment(dcpl, (3, 4, 2), 0.004))
+    assert rel(outs[2].cpu().numpy(), dense) < 1e-9
+    outs_m, infos_m = lsvie.solve_batch([A, B], jobs, tol=1e-7, precision="mixed")
+    for u, um, info in zip(outs, outs_m, infos_m):
+        assert info["status"] == 0 and info["rel_res_true"] <= 1e-7
+        assert rel(um.cpu().numpy(), u.cpu().numpy()) < 1e-5
+    with pytest.raises(lsvie.LsError) as e:
+        lsvie.solve_batch([A, B], [(1, 0, dcpl, (20, 0, 0), 0.0)])
+    assert e.value.code == lsvie.LS_ERR_ARG
+    with pytest.raises(lsvie.LsError) as e:
+        lsvie.solve_batch([A, B], [(0, 2, dcpl, (1, 1, 1), 0.0)])
+    assert e.value.code == lsvie.LS_ERR_ARG
+    A.close()
+    B.close()
