@@ -246,6 +246,53 @@ def config4_observed(n=96, seed=3):
     return Model(m.shape, m.h, m.C0, m.rho0, dc, drho, m.freqs, m.sources, m.tol, "config4-observed")
 
 
+# the nine orthorhombic stiffnesses (Voigt index pairs) and their packed upper-triangle positions
+ORTHO_PAIRS = ((0, 0), (1, 1), (2, 2), (3, 3), (4, 4), (5, 5), (0, 1), (0, 2), (1, 2))
+
+
+def packed_index(I, J):
+    I, J = min(I, J), max(I, J)
+    return I * 6 - I * (I - 1) // 2 + (J - I)
+
+
+def ortho_background(seed=4, rel=0.12):
+    """Orthorhombic background: the nine constants of the isotropic (3000, 1700, 2400) medium scaled by
+    1 + rel * U(-1, 1) (seed), redrawn until the 6x6 is positive definite.  Returns (C0, rho0)."""
+    base = iso_C(3000.0, 1700.0, 2400.0)
+    rng = np.random.default_rng(seed)
+    while True:
+        f = 1.0 + rel * rng.uniform(-1.0, 1.0, size=9)
+        C = np.zeros((6, 6))
+        for q, (I, J) in enumerate(ORTHO_PAIRS):
+            C[I, J] = C[J, I] = base[I, J] * f[q]
+        if np.linalg.eigvalsh(C).min() > 0.0:
+            return C, 2400.0
+
+
+CONFIG5_GRIDS = ((256, 6.0), (192, 8.0), (128, 12.0))
+
+
+def config5(n=256, seed=4, freqs=(10.0, 70.0 / 3.0, 110.0 / 3.0, 50.0), corr_len=40.0, layers=5):
+    """The large uneven batch: grid n^3 of (256, 192, 128) with h = 6, 8, 12 m; orthorhombic background
+    (seed 4); contrast = five z layers, each scaling the nine orthorhombic constants and rho by
+    1 + 0.1 U(-1, 1), times 1 + 0.05 g (Gaussian random field, correlation length 40 m; 0.03 g on rho);
+    6 elementary moment tensors at the centre x 4 frequencies 10-50 Hz; tol 1e-6."""
+    h = dict(CONFIG5_GRIDS)[n]
+    C0, rho0 = ortho_background(seed)
+    rng = np.random.default_rng(1000 * seed + n)
+    lf = 1.0 + 0.10 * rng.uniform(-1.0, 1.0, size=(layers, 10))
+    layer = np.minimum((np.arange(n) * layers) // n, layers - 1)
+    dc = np.zeros((21, n, n, n))
+    for q, (I, J) in enumerate(ORTHO_PAIRS):
+        g = gaussian_random_fields(rng, 1, n, h, corr_len)[0]
+        dc[packed_index(I, J)] = C0[I, J] * (lf[layer, q][:, None, None] * (1.0 + 0.05 * g) - 1.0)
+    g = gaussian_random_fields(rng, 1, n, h, corr_len)[0]
+    drho = rho0 * (lf[layer, 9][:, None, None] * (1.0 + 0.03 * g) - 1.0)
+    m = n // 2
+    sources = [(np.eye(6)[J], (m, m, m)) for J in range(6)]
+    return Model((n, n, n), h, C0, rho0, dc, drho, list(map(float, freqs)), sources, 1e-6, f"config5_{n}")
+
+
 def random_field(shape, seed, complex_=True):
     """Seeded standard-normal test field [3, N3, N2, N1] (complex by default)."""
     rng = np.random.default_rng(seed)
