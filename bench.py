@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--compare-c128", action="store_true",
+                    help="also time the same 48 systems as sequential single-source plain c128 solves")
     ap.add_argument("--mode", choices=["bench", "apply-profile"], default="bench",
                     help="apply-profile: only a few batched applies plus a copy of known size, for counter runs")
     args = ap.parse_args()
@@ -280,6 +282,26 @@ def main():
             del u
     log(f"apply rates: {json.dumps(rates)}")
     ctx.close()
+    del out, bufs
+
+    seq = None
+    if args.compare_c128:
+        # the same 48 systems, one source per call, plain FP64 operator (outside the timed steps)
+        ctx1 = lsvie.context_from_model(model, precision="c128", max_rhs=1)
+        b1, x1 = ctx1.empty(), ctx1.empty()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mv1 = 0
+        for iw in range(len(model.omegas)):
+            for M, src in model.sources:
+                ctx1.rhs_moment(M, src, i_omega=iw, out=b1)
+                _, infos = ctx1.solve(b1, i_omega=iw, tol=model.tol, maxit=args.maxit, precision="c128", out=x1)
+                mv1 += infos[0]["matvecs"]
+        torch.cuda.synchronize()
+        seq_s = time.perf_counter() - t0
+        seq = {"time_s": round(seq_s, 3), "matvecs": mv1, "speedup_of_batched_mixed": round(seq_s / (ms_per_step / 1e3), 2)}
+        log(f"sequential plain c128: {seq_s:.2f} s for the same systems ({mv1} matvecs)")
+        ctx1.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -299,6 +321,7 @@ def main():
         "iterations_per_frequency": [max(i) for i in its],
         "worst_rel_res_true": max(res),
         "apply": rates,
+        "sequential_c128": seq,
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,

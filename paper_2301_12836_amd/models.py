@@ -255,10 +255,10 @@ def packed_index(I, J):
     return I * 6 - I * (I - 1) // 2 + (J - I)
 
 
-def ortho_background(seed=4, rel=0.12):
-    """Orthorhombic background: the nine constants of the isotropic (3000, 1700, 2400) medium scaled by
+def ortho_background(seed=4, rel=0.10):
+    """Orthorhombic background: the nine orthorhombic constants of config 2's VTI medium scaled by
     1 + rel * U(-1, 1) (seed), redrawn until the 6x6 is positive definite.  Returns (C0, rho0)."""
-    base = iso_C(3000.0, 1700.0, 2400.0)
+    base = vti_from_thomsen(**VTI_CFG2)
     rng = np.random.default_rng(seed)
     while True:
         f = 1.0 + rel * rng.uniform(-1.0, 1.0, size=9)
@@ -266,17 +266,18 @@ def ortho_background(seed=4, rel=0.12):
         for q, (I, J) in enumerate(ORTHO_PAIRS):
             C[I, J] = C[J, I] = base[I, J] * f[q]
         if np.linalg.eigvalsh(C).min() > 0.0:
-            return C, 2400.0
+            return C, VTI_CFG2["rho"]
 
 
 CONFIG5_GRIDS = ((256, 6.0), (192, 8.0), (128, 12.0))
 
 
-def config5(n=256, seed=4, freqs=(10.0, 70.0 / 3.0, 110.0 / 3.0, 50.0), corr_len=40.0, layers=5):
-    """The large uneven batch: grid n^3 of (256, 192, 128) with h = 6, 8, 12 m; orthorhombic background
-    (seed 4); contrast = five z layers, each scaling the nine orthorhombic constants and rho by
-    1 + 0.1 U(-1, 1), times 1 + 0.05 g (Gaussian random field, correlation length 40 m; 0.03 g on rho);
-    6 elementary moment tensors at the centre x 4 frequencies 10-50 Hz; tol 1e-6."""
+def config5(n=256, seed=4, freqs=(10.0, 70.0 / 3.0, 110.0 / 3.0, 50.0), corr_len=40.0, layers=3):
+    """The large uneven batch: grid n^3 of (256, 192, 128) with h = 6, 8, 12 m (1536 m cubes);
+    orthorhombic background (seed 4); contrast = three z layers, each scaling the nine orthorhombic
+    constants and rho by 1 + 0.1 U(-1, 1), times 1 + 0.08 g (0.04 g on rho), g Gaussian random fields
+    with correlation length 40 m; 6 elementary moment tensors at the centre x 4 frequencies 10-50 Hz;
+    tol 1e-6.  (At 50 Hz the 12 m grid has fewer than 4 cells per S wavelength.)"""
     h = dict(CONFIG5_GRIDS)[n]
     C0, rho0 = ortho_background(seed)
     rng = np.random.default_rng(1000 * seed + n)
@@ -285,9 +286,9 @@ def config5(n=256, seed=4, freqs=(10.0, 70.0 / 3.0, 110.0 / 3.0, 50.0), corr_len
     dc = np.zeros((21, n, n, n))
     for q, (I, J) in enumerate(ORTHO_PAIRS):
         g = gaussian_random_fields(rng, 1, n, h, corr_len)[0]
-        dc[packed_index(I, J)] = C0[I, J] * (lf[layer, q][:, None, None] * (1.0 + 0.05 * g) - 1.0)
+        dc[packed_index(I, J)] = C0[I, J] * (lf[layer, q][:, None, None] * (1.0 + 0.08 * g) - 1.0)
     g = gaussian_random_fields(rng, 1, n, h, corr_len)[0]
-    drho = rho0 * (lf[layer, 9][:, None, None] * (1.0 + 0.03 * g) - 1.0)
+    drho = rho0 * (lf[layer, 9][:, None, None] * (1.0 + 0.04 * g) - 1.0)
     m = n // 2
     sources = [(np.eye(6)[J], (m, m, m)) for J in range(6)]
     return Model((n, n, n), h, C0, rho0, dc, drho, list(map(float, freqs)), sources, 1e-6, f"config5_{n}")
