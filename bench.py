@@ -76,26 +76,28 @@ def apply_bytes(n, prec, nrhs):
                contrast + ("fft_x_fwd", "fft_y_fwd", "fft_z_green", "fft_y_inv", "fft_x_inv_epi"))
 
 
-def source_hash():
-    """sha256 (first 16 hex digits) of the HIP sources, to match counter summaries to the built kernels."""
-    import glob
+# the sources each kernel family is compiled from (a change to any of them voids its counter figures)
+FAMILY_SOURCES = {"fft_": ("common.h", "fft_core.h", "fft_reg.h", "fft.hip"),
+                  "contrast_": ("common.h", "fft_reg.h", "contrast.hip")}
+
+
+def file_hash(name):
+    """sha256 (first 16 hex digits) of one HIP source file of the library."""
     import hashlib
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2301_12836_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".h")):
-            h.update(open(f, "rb").read())
-    return h.hexdigest()[:16]
+    with open(os.path.join(ROOT, "paper_2301_12836_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def measured_traffic(family):
     """HBM bytes per launch of a kernel family from the committed rocprofv3 counter summary, or None when
-    the summary was taken from different kernel sources."""
+    any source the family is compiled from differs from the one the counters were taken with."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_config3_apply.txt")
-    if not os.path.exists(path):
+    srcs = next((v for k, v in FAMILY_SOURCES.items() if family.startswith(k)), None)
+    if srcs is None or not os.path.exists(path):
         return None
     lines = open(path).read().splitlines()
-    tag = [ln.split()[1] for ln in lines if ln.startswith("source_sha256 ")]
-    if not tag or tag[0] != source_hash():
+    recorded = {p[1]: p[2] for p in (ln.split() for ln in lines) if len(p) == 3 and p[0] == "file_sha256"}
+    if any(recorded.get(f) != file_hash(f) for f in srcs):
         return None
     for ln in lines:
         parts = ln.split()

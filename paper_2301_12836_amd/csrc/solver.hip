@@ -12,6 +12,8 @@
 // use a fixed number of blocks and a fixed tree, so results are bitwise reproducible.
 #include <cmath>
 
+#include <limits>
+
 #include "common.h"
 
 namespace ls {
@@ -466,6 +468,13 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
             return hip_fail(e2, "BiCGSTAB iteration graph instantiation");
         }
     }
+    // FP32 inner solves stop a right-hand side whose residual has not improved on its best by 10 % for
+    // kStall iterations (its attainable accuracy is reached; the FP64 refinement restarts from the true
+    // residual).  FP64 solves run to tol or maxit.
+    constexpr int kStall = 30;
+    std::vector<double> best(nrhs, std::numeric_limits<double>::infinity());
+    std::vector<int> since(nrhs, 0);
+    static const double zero = 0.0;
     for (int it = 0; it < maxit; ++it) {
         if (guard.exec) {
             LS_HIP(hipGraphLaunch(guard.exec, c->stream));
@@ -476,7 +485,21 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
                               c->stream));
         LS_HIP(hipStreamSynchronize(c->stream));
         bool any = false;
-        for (int q = 0; q < nrhs; ++q) any = any || c->red_host[q * kStateLen + S_ACTIVE] != 0.0;
+        for (int q = 0; q < nrhs; ++q) {
+            const double* sq = &c->red_host[q * kStateLen];
+            if (sq[S_ACTIVE] == 0.0) continue;
+            if (sizeof(T) == 4) {
+                if (sq[S_RNORM2] < 0.81 * best[q]) {  // 10 % on the norm
+                    best[q] = sq[S_RNORM2];
+                    since[q] = 0;
+                } else if (++since[q] >= kStall) {
+                    LS_HIP(hipMemcpyAsync(c->state + q * kStateLen + S_ACTIVE, &zero, sizeof(double),
+                                          hipMemcpyHostToDevice, c->stream));
+                    continue;
+                }
+            }
+            any = true;
+        }
         if (!any) break;
     }
     LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * nrhs * kStateLen, hipMemcpyDeviceToHost, c->stream));
@@ -584,8 +607,9 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 if (active[q]) worst = std::max(worst, rel[q]);
             }
             if (!any || outer == max_outer) break;
-            // inner tolerance: enough reduction to reach tol, but not below the FP32 operator's accuracy
-            const double eta = std::min(1e-1, std::max(1e-4, 0.3 * tol / worst));
+            // inner tolerance: the reduction that reaches 0.3 tol, capped at 0.1 and floored at 1e-7 (near
+            // the FP32 operator's relative accuracy; a stagnating inner solve is stopped early anyway)
+            const double eta = std::min(1e-1, std::max(1e-7, 0.3 * tol / worst));
             for (int q = 0; q < nrhs; ++q) {
                 scale[q] = active[q] ? 1.0 / nrm[q] : 0.0;
                 inv[q] = active[q] ? nrm[q] : 0.0;
