@@ -102,10 +102,11 @@ __global__ __launch_bounds__(kThreads) void k_fft_strided(cpx<T>* __restrict__ d
     }
 }
 
-// Visit y and its mirror L2 - y in consecutive blocks so both read the same octant rows of G^.
+// Visit y and its mirror L2 - y in consecutive blocks so both read the same octant rows of G^: a
+// permutation of 0..L2-1 for any count (an even count ends on its self-mirrored middle row L2/2).
 __device__ __forceinline__ int paired_row(int by, int L2) {
     if (by == 0) return 0;
-    if (by == L2 - 1) return L2 / 2;
+    if (L2 % 2 == 0 && by == L2 - 1) return L2 / 2;
     const int m = (by + 1) >> 1;
     return (by & 1) ? m : L2 - m;
 }
@@ -193,10 +194,11 @@ constexpr int seg_cols() {
     return 128 / (int)sizeof(cpx<T>);
 }
 
-// usable when the transpose buffer stays within 64 KB (all lengths but c128 at 512)
+// usable for powers of two whose transpose buffer stays within 64 KB (all but c128 at 512); lengths
+// with a factor 3 run the LDS Stockham kernels
 template <typename T, int L>
 constexpr bool fs_ok() {
-    return L * seg_cols<T>() * (int)sizeof(cpx<T>) <= 65536;
+    return (L & (L - 1)) == 0 && L * seg_cols<T>() * (int)sizeof(cpx<T>) <= 65536;
 }
 
 template <typename T, int L>
@@ -392,13 +394,16 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_zgreen(cpx<T>* __re
 // z pass in registers where three components of N2 values fit (c64 up to 512, c128 up to 256)
 template <typename T, int L>
 constexpr bool fs_z_ok() {
-    return fs_ok<T, L>() && 3 * FourStep<L>::N2 * (int)sizeof(cpx<T>) <= 3 * 32 * 8;
+    if constexpr (!fs_ok<T, L>())
+        return false;
+    else
+        return 3 * FourStep<L>::N2 * (int)sizeof(cpx<T>) <= 3 * 32 * 8;
 }
 
 // ------------------------------------------------------------------------------------------
 // host dispatch over the supported lengths
 
-#define LS_FOR_LENGTHS(X) X(16) X(32) X(64) X(128) X(256) X(512)
+#define LS_FOR_LENGTHS(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 
 // LS_FFT=stockham in the environment selects the LDS Stockham kernels everywhere (both paths are
 // kept under test); otherwise the register four-step kernels run wherever they fit.
@@ -532,8 +537,10 @@ const z64* green_table<float>(const Ctx* c, int i) { return c->ghat32[i]; }
 
 }  // namespace
 
+// the smallest supported length (2^a or 3 * 2^a, 16..512) that holds the linear convolution of n cells
 int supported_fft_length(int n) {
-    for (int L = 16; L <= 512; L *= 2)
+    static const int lengths[] = {16, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+    for (int L : lengths)
         if (L >= 2 * n - 1) return L;
     return 0;
 }

@@ -1,6 +1,6 @@
 // Device building blocks of the Stockham FFT used for the zero-padded convolutions of Eq 21.
 //
-// Lines of length L (a power of two) are held in LDS as s[e * LDP + t] (element e of line t,
+// Lines of length L (2^a or 3 * 2^a) are held in LDS as s[e * LDP + t] (element e of line t,
 // line index fastest).  Each stage reads R elements spaced L/R apart, applies the twiddles
 // W_{Ns R}^{r k} (k = j mod Ns), a radix-R DFT in registers, and writes them back spaced Ns
 // apart from (j / Ns) Ns R + k: the self-sorting (Stockham) form, so no bit reversal is needed.
@@ -28,6 +28,19 @@ struct SmallDft<SIGN, 2, T> {
         const cpx<T> a = v[0];
         v[0] = a + v[1];
         v[1] = a - v[1];
+    }
+};
+
+// X1,2 = a - (b + c)/2 +- SIGN i (sqrt(3)/2)(b - c)  (the cube roots of unity e^{SIGN 2 pi i/3})
+template <int SIGN, typename T>
+struct SmallDft<SIGN, 3, T> {
+    static __device__ __forceinline__ void run(cpx<T>* v) {
+        const cpx<T> t1 = v[1] + v[2];
+        const cpx<T> t2 = v[0] - T(0.5) * t1;
+        const cpx<T> t3 = mul_si<SIGN>(T(0.86602540378443864676) * (v[1] - v[2]));
+        v[0] = v[0] + t1;
+        v[1] = t2 + t3;
+        v[2] = t2 - t3;
     }
 };
 
@@ -67,9 +80,10 @@ struct SmallDft<SIGN, 8, T> {
     }
 };
 
+// the factor 3 first (at NS = 1 it needs no twiddles), then 8, 4, 2
 template <int REM>
 constexpr int pick_radix() {
-    return (REM % 8 == 0 && REM != 16) ? 8 : ((REM % 4 == 0) ? 4 : 2);
+    return (REM % 3 == 0) ? 3 : (REM % 8 == 0 && REM != 16) ? 8 : ((REM % 4 == 0) ? 4 : 2);
 }
 
 // One Stockham stage over NL lines of length L in LDS (leading dimension LDP), NT threads.

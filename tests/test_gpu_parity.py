@@ -271,3 +271,20 @@ def test_apply_config3_sampled_cells_batched():
         assert rel(g, want) < 1e-10
         assert rel(g32, want) < 1e-5
     ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(20, 24, 40), (17, 40, 9), (48, 33, 10)])
+def test_radix3_lengths_match_oracle(shape):
+    """Grids whose padded FFT lengths carry a factor 3 (48, 96) on some axes and are powers of two on
+    others: c128 and c64 applies against the oracle (which pads to 2N independently)."""
+    m = models.random_medium(shape, seed=sum(shape) + 3, rel=0.1, aniso_background=True)
+    w = 2 * np.pi * 18.0
+    ctx, (P,) = ctx_and_problem(m, omegas=[w], precision="mixed")
+    u = models.random_field(shape, 4)
+    want = P.apply_fft(u)
+    got = to_np(ctx.apply(torch.from_numpy(u)))
+    got32 = to_np(ctx.apply(torch.from_numpy(u).to(torch.complex64)))
+    print(shape, "c128", rel(got, want), "c64", rel(got32, want), flush=True)
+    assert rel(got, want) < 1e-10
+    assert rel(got32, want) < 1e-5
+    ctx.close()
