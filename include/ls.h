@@ -65,8 +65,16 @@ typedef struct {
                        LS_GREEN_PAPER_SUM: the near-field A.4 plus far-field A.5 tensors   */
     int max_rhs;    /* largest batch of right-hand sides one call may carry (>= 1)         */
     int flags;      /* LS_FLAG_* bits (0: defaults)                                          */
-    int reserved[4];
+    int taper;      /* absorbing boundary layer thickness in cells (0: off); see below        */
+    int reserved[3];
 } ls_options;
+
+/* ls_options.taper = d > 0 weights the total contrast (input plus background fold) of every cell within
+ * d cells of a face by 1 - exp(-l^2 / (N_a h^2)) (the absorbing boundary of Eq 23-25), at set-up and
+ * in ls_set_contrast: l is the distance from the cell centre to the point where the ray from the model
+ * centre through it leaves the box (the faces lie half a cell outside the outer cell centres), N_a the
+ * number of cells along the axis of the face it crosses.  Gradients (ls_grad_contrast, ls_grad) are
+ * taken with respect to the input contrast, so they carry the same weight.  0 <= d <= min(N)/2. */
 
 /* ls_options.flags:
  *   LS_FLAG_NO_GRAPH  run every BiCGSTAB iteration as separate launches instead of replaying one

@@ -88,6 +88,39 @@ def total_contrast21(C0, rho0, dc21):
     return np.asarray(dc21, dtype=np.float64) + fold.reshape((21,) + (1,) * (np.ndim(dc21) - 1))
 
 
+def taper_weights(shape, d):
+    """Absorbing-boundary weight of every cell (Eq 23-25): 1 - exp(-l^2 / (N_a h^2)) inside the boundary
+    layer, 1 elsewhere.  Readings (the paper leaves them open): the layer is the cells within d cells of a
+    face; x_L is where the ray from the model centre through the cell centre leaves the box, whose faces
+    lie half a cell outside the outer cell centres; l = |x_L - x_B|; N_a is the number of cells along the
+    axis a whose face the ray crosses.  Lengths in cells (h cancels).  shape (N1, N2, N3) -> [N3, N2, N1]."""
+    n = np.array(shape, dtype=np.int64)
+    w = np.ones((n[2], n[1], n[0]))
+    if d <= 0:
+        return w
+    centre = (n - 1) / 2.0
+    for k in range(n[2]):
+        for j in range(n[1]):
+            for i in range(n[0]):
+                p = np.array([i, j, k], dtype=np.float64)
+                if all(d <= p[a] <= n[a] - 1 - d for a in range(3)):
+                    continue                          # not in the layer
+                v = p - centre
+                best, axis = np.inf, -1
+                for a in range(3):
+                    if v[a] == 0.0:
+                        continue
+                    face = n[a] - 0.5 if v[a] > 0 else -0.5
+                    s_ = (face - centre[a]) / v[a]   # ray parameter of the face crossing
+                    if s_ < best:
+                        best, axis = s_, a
+                if axis < 0:
+                    continue                          # the centre itself
+                l = (best - 1.0) * np.linalg.norm(v)
+                w[k, j, i] = 1.0 - np.exp(-l * l / n[axis])
+    return w
+
+
 # ----------------------------------------------------------------------------------------------
 # strain stencil (Eq 18)
 
@@ -268,15 +301,16 @@ def convolve_fft(f, T):
 class Problem:
     """One (grid, medium, frequency) instance of the discrete LS system."""
 
-    def __init__(self, shape, h, C0, rho0, dc21, drho, omega, mode='exact'):
+    def __init__(self, shape, h, C0, rho0, dc21, drho, omega, mode='exact', taper=0):
         self.shape = tuple(int(v) for v in shape)
         self.h = float(h)
         self.omega = omega
         self.rho0 = float(rho0)
         self.alpha, self.beta, self.c_iso = iso_reference(C0, rho0)
         n3, n2, n1 = self.shape[2], self.shape[1], self.shape[0]
-        self.dc21 = total_contrast21(C0, rho0, np.asarray(dc21).reshape(21, n3, n2, n1))
-        self.drho = np.asarray(drho, dtype=np.float64).reshape(n3, n2, n1)
+        w = taper_weights(self.shape, taper)   # the absorbing layer weights the total contrast (Eq 25)
+        self.dc21 = total_contrast21(C0, rho0, np.asarray(dc21).reshape(21, n3, n2, n1)) * w[None]
+        self.drho = np.asarray(drho, dtype=np.float64).reshape(n3, n2, n1) * w
         self.mode = mode
         self._T = None
 

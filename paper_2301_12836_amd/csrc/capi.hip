@@ -266,11 +266,13 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
         for (int J = 0; J < I; ++J)
             if (std::fabs(C0[I * 6 + J] - C0[J * 6 + I]) > 1e-12 * cmax)
                 return fail(LS_ERR_ARG, "background stiffness must be symmetric");
-    ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, 0, {0, 0, 0, 0}};
+    ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, 0, 0, {0, 0, 0}};
     if (opt) o = *opt;
     if (o.precision != LS_PREC_C128 && o.precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
     if (o.green_mode != LS_GREEN_EXACT && o.green_mode != LS_GREEN_PAPER_SUM) return fail(LS_ERR_ARG, "bad green_mode");
     if (o.max_rhs < 1 || o.max_rhs > 64) return fail(LS_ERR_ARG, "max_rhs must be in [1, 64]");
+    if (o.taper < 0 || 2 * o.taper > std::min(grid->n[0], std::min(grid->n[1], grid->n[2])))
+        return fail(LS_ERR_ARG, "taper must be in [0, min(N)/2]");
 
     // isotropic reference and the anisotropic remainder folded into the contrast
     double c11, c44;
@@ -309,6 +311,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     c->omega.assign(omega, omega + n_omega);
     c->stream = (hipStream_t)stream;
     c->flags = o.flags;
+    c->taper = o.taper;
     {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess) {

@@ -91,6 +91,7 @@ struct Ctx {
     int flags = 0;
     int num_cu = 256;  // compute units of the device (block-count heuristics)
     int device = 0;    // the HIP device the context was set up on
+    int taper = 0;     // absorbing-layer thickness in cells (0: off)
     // FFT kernel variant per pass and precision: 0 register four-step, 1 LDS Stockham
     // passes: 0 x forward, 1 y forward, 2 z with Green multiply, 3 y inverse, 4 x inverse
     int variant[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};

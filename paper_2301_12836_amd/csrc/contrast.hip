@@ -453,6 +453,31 @@ __global__ __launch_bounds__(kThreads) void k_to_work(const cpx<T>* __restrict__
     for (int r = 0; r < 3 * nrhs; ++r) work[r * cpitch + wpos] = f[r * n + p];
 }
 
+// Absorbing-layer weight of cell (i, j, k) (Eq 23-25): 1 - exp(-l^2 / (N_a h^2)) within d cells of a face,
+// 1 elsewhere; l is the distance from the cell centre to where the ray from the model centre through it
+// leaves the box (faces half a cell outside the outer cell centres), N_a the cell count along the axis of
+// the face it crosses (the lower axis on ties).  Lengths in cells.
+__device__ double taper_weight(int i, int j, int k, int N1, int N2, int N3, int d) {
+    if (d <= 0) return 1.0;
+    const int p[3] = {i, j, k}, n[3] = {N1, N2, N3};
+    bool layer = false;
+    for (int a = 0; a < 3; ++a) layer = layer || p[a] < d || p[a] > n[a] - 1 - d;
+    if (!layer) return 1.0;
+    double v[3], best = 0.0;
+    int axis = -1;
+    for (int a = 0; a < 3; ++a) {
+        const double c = 0.5 * (n[a] - 1);
+        v[a] = p[a] - c;
+        if (v[a] == 0.0) continue;
+        const double face = v[a] > 0.0 ? n[a] - 0.5 : -0.5;
+        const double s = (face - c) / v[a];
+        if (axis < 0 || s < best) best = s, axis = a;
+    }
+    if (axis < 0) return 1.0;
+    const double l = (best - 1.0) * sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    return 1.0 - exp(-l * l / n[axis]);
+}
+
 // Gradient of a real misfit with respect to the contrast at every cell, for forward fields u and
 // adjoint-side fields mu = conj(Gconv lambda_bar) (lambda_bar solving A^T lambda_bar = conj(P^H r)):
 //   g21[JK](p) += -Re[conj(eps_J(mu)) eps_K(u) + (J != K) conj(eps_K(mu)) eps_J(u)]   (packed J <= K)
@@ -460,7 +485,8 @@ __global__ __launch_bounds__(kThreads) void k_to_work(const cpx<T>* __restrict__
 // summed over the nrhs (u, mu) pairs.
 __global__ __launch_bounds__(kThreads) void k_grad_contrast(const z128* __restrict__ u, const z128* __restrict__ mu,
                                                             double* __restrict__ g21, double* __restrict__ grho,
-                                                            int nrhs, int N1, int N2, int N3, double inv_h, double w2) {
+                                                            int nrhs, int N1, int N2, int N3, double inv_h, double w2,
+                                                            int taper) {
     const long long n = (long long)N1 * N2 * N3;
     const long long p = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (p >= n) return;
@@ -488,9 +514,11 @@ __global__ __launch_bounds__(kThreads) void k_grad_contrast(const z128* __restri
 #pragma unroll
         for (int c = 0; c < 3; ++c) ar += cmulc(mr[c * n + p], ur[c * n + p]).x;
     }
+    // the contrast the operator sees is the input times the absorbing-layer weight
+    const double tw = taper_weight(i, j, k, N1, N2, N3, taper);
 #pragma unroll
-    for (int q = 0; q < 21; ++q) g21[q * n + p] += acc[q];
-    grho[p] += w2 * ar;
+    for (int q = 0; q < 21; ++q) g21[q * n + p] += tw * acc[q];
+    grho[p] += tw * w2 * ar;
 }
 
 // a[p] = conj(a[p])
@@ -534,18 +562,22 @@ __global__ __launch_bounds__(kThreads) void k_strain_out(const cpx<T>* __restric
     }
 }
 
+// total contrast = (input contrast + background fold) x absorbing-layer weight, in FP64 and FP32
 __global__ void k_fold(const double* __restrict__ dc_in, const double* __restrict__ drho_in, double* __restrict__ dc,
-                       double* __restrict__ drho, float* __restrict__ dc32, float* __restrict__ drho32, long long n,
-                       const double* __restrict__ fold21) {
+                       double* __restrict__ drho, float* __restrict__ dc32, float* __restrict__ drho32, int N1, int N2,
+                       int N3, int taper, const double* __restrict__ fold21) {
+    const long long n = (long long)N1 * N2 * N3;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
+    const double w = taper_weight((int)(p % N1), (int)((p / N1) % N2), (int)(p / ((long long)N1 * N2)), N1, N2, N3,
+                                  taper);
     for (int q = 0; q < 21; ++q) {
-        const double v = dc_in[q * n + p] + fold21[q];
+        const double v = (dc_in[q * n + p] + fold21[q]) * w;
         dc[q * n + p] = v;
         if (dc32) dc32[q * n + p] = (float)v;
     }
-    drho[p] = drho_in[p];
-    if (drho32) drho32[p] = (float)drho_in[p];
+    drho[p] = drho_in[p] * w;
+    if (drho32) drho32[p] = (float)(drho_in[p] * w);
 }
 
 template <typename T>
@@ -690,7 +722,7 @@ int grad_contrast_launch(Ctx* c, int i_omega, const z128* u, const z128* mu, int
     const double w = c->omega[i_omega];
     c->prof.begin(c->stream, "grad_contrast.c128");
     hipLaunchKernelGGL(k_grad_contrast, dim3(nb), dim3(kThreads), 0, c->stream, u, mu, g21, grho, nrhs, c->n1, c->n2,
-                       c->n3, 1.0 / c->h, w * w);
+                       c->n3, 1.0 / c->h, w * w, c->taper);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
@@ -735,7 +767,7 @@ int fold_background(Ctx* c, const double* dc_in, const double* drho_in, const do
     LS_HIP(hipMemcpyAsync(dfold, fold21, 21 * sizeof(double), hipMemcpyHostToDevice, c->stream));
     const long long n = c->ncell;
     hipLaunchKernelGGL(k_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, dc_in, drho_in, c->dc, c->drho,
-                       c->dc32, c->drho32, n, dfold);
+                       c->dc32, c->drho32, c->n1, c->n2, c->n3, c->taper, dfold);
     LS_HIP(hipGetLastError());
     LS_HIP(hipStreamSynchronize(c->stream));
     LS_HIP(hipFreeAsync(dfold, c->stream));

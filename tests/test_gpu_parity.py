@@ -288,3 +288,28 @@ def test_radix3_lengths_match_oracle(shape):
     assert rel(got, want) < 1e-10
     assert rel(got32, want) < 1e-5
     ctx.close()
+
+
+def test_absorbing_taper_apply_and_gradient_weight():
+    """The absorbing layer (Eq 23-25) against the oracle's tapered problem, and the gradient's chain rule
+    through the weight: with the same fields, tapered gradients are the oracle's weights times untapered."""
+    m = models.random_medium((14, 12, 10), seed=31, rel=0.1, aniso_background=True)
+    d = 3
+    ctx = lsvie.context_from_model(m, omegas=[W15], precision="mixed", taper=d)
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, W15, taper=d)
+    u = models.random_field(m.shape, 8)
+    want = P.apply_fft(u)
+    assert rel(to_np(ctx.apply(torch.from_numpy(u))), want) < 1e-10
+    assert rel(to_np(ctx.apply(torch.from_numpy(u).to(torch.complex64))), want) < 1e-5
+    ctx0 = lsvie.context_from_model(m, omegas=[W15])
+    mu = torch.from_numpy(models.random_field(m.shape, 9))
+    g, gr = ctx.grad_contrast(torch.from_numpy(u), mu)
+    g0, gr0 = ctx0.grad_contrast(torch.from_numpy(u), mu)
+    w = op.taper_weights(m.shape, d)
+    assert np.allclose(to_np(g), w[None] * to_np(g0), rtol=1e-13, atol=0)
+    assert np.allclose(to_np(gr), w * to_np(gr0), rtol=1e-13, atol=0)
+    ctx.close()
+    ctx0.close()
+    with pytest.raises(lsvie.LsError) as e:
+        lsvie.context_from_model(m, omegas=[W15], taper=6)
+    assert e.value.code == lsvie.LS_ERR_ARG

@@ -260,3 +260,27 @@ def test_bicgstab_reaches_lu_solution():
     assert hist[-1] <= 1e-12
     assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-10
     assert solve.relative_residual(P.apply_fft, x, b) < 1e-11
+
+
+def test_taper_weights_geometry():
+    """Absorbing-layer weights (Eq 23-25): 1 outside the layer; on the axis through the centre of a face the
+    ray meets that face at right angles, so l is the distance from the cell centre to the face; the
+    weights share the grid's mirror symmetries and grow along a ray away from the boundary."""
+    shape, d = (14, 12, 10), 3
+    w = op.taper_weights(shape, d)
+    assert w.shape == (10, 12, 14)
+    assert np.all(w[d:10 - d, d:12 - d, d:14 - d] == 1.0)
+    assert np.all((w > 0) & (w <= 1))
+    # mirror symmetries of the box
+    assert np.allclose(w, w[::-1]) and np.allclose(w, w[:, ::-1]) and np.allclose(w, w[:, :, ::-1])
+    # on an odd cube the centre is a cell, so the axis lines through it are face-normal rays
+    w2 = op.taper_weights((9, 9, 9), 2)
+    for i, dist in [(0, 0.5), (1, 1.5), (8, 0.5), (7, 1.5)]:
+        assert np.isclose(w2[4, 4, i], 1.0 - np.exp(-dist ** 2 / 9.0))
+        assert np.isclose(w2[i, 4, 4], 1.0 - np.exp(-dist ** 2 / 9.0))
+    # along the diagonal ray from the centre the weight increases inwards
+    diag = [w2[k, k, k] for k in range(2)]
+    assert diag[0] < diag[1]
+    # the corner cell's ray leaves through the corner: l = sqrt(3) / 2
+    assert np.isclose(w2[0, 0, 0], 1.0 - np.exp(-0.75 / 9.0))
+    assert np.all(op.taper_weights(shape, 0) == 1.0)
