@@ -189,6 +189,22 @@ typedef struct ls_job {
 int ls_solve_batch(ls_ctx* const* ctxs, int n_ctx, const ls_job* jobs, int n_jobs, double tol, int maxit,
                    int precision, ls_info* infos);
 
+/* Receiver samples of n_rhs fields: out[r][m][c] = u[r][c][rec_m] for the n_rec cells rec (host int
+ * [n_rec][3] = (i, j, k), each inside the grid, else LS_ERR_ARG).  u: device c128 [n_rhs][3][N3][N2][N1];
+ * out: device c128 [n_rhs][n_rec][3].  Synchronises the context's stream. */
+int ls_sample(ls_ctx* ctx, const void* u, int n_rhs, const int* rec, int n_rec, void* out);
+
+/* Time-domain traces from one-sided spectra (the frequency loop up to Nyquist and inverse transform of the
+ * paper's comparisons with finite differences).  With time dependence e^{-i w t} and w_k = 2 pi k / (nt dt),
+ *   traces[j][n] = (1/(nt dt)) sum_q c_q Re[S(w_{k_q}) spectra[q][j] e^{-i w_{k_q} n dt}],
+ * c_q = 1 for k_q = 0 or 2 k_q = nt, else 2 (the negative frequencies of a real signal); S is the Ricker
+ * wavelet of peak frequency fp delayed by ts (Tables 1 and 3), S(w) = (4 sqrt(pi) w^2 / wp^3)
+ * e^{-w^2/wp^2} e^{i w ts} with wp = 2 pi fp, or 1 when fp <= 0.  Frequencies not listed count as zero.
+ *   spectra: device c128 [n_freq][n_trace];  k: host [n_freq], 0 <= k <= nt/2;
+ *   traces: device double [n_trace][nt].  Uses the context's stream; synchronises it. */
+int ls_synthesize(ls_ctx* ctx, const void* spectra, const int* k, int n_freq, int n_trace, int nt, double dt,
+                  double fp, double ts, double* traces);
+
 /* Voigt engineering strain of n_rhs fields (Eq 17-18): eps device c128 [n_rhs][6][N3][N2][N1]. */
 int ls_strain(ls_ctx* ctx, const void* u, void* eps, int n_rhs);
 

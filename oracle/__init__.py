@@ -17,6 +17,10 @@ in anisotropic elastic media" (arXiv 2301.12836):
   brute-force O(n^2) apply and a zero-padded FFT apply.
 * ``oracle.solve``    - the dense direct solve and a textbook BiCGSTAB with the
   relative residual of Eq 22.
+* ``oracle.adjoint``  - the transposed operator, receiver sampling and the dense
+  adjoint-state gradient of a receiver misfit.
+* ``oracle.synthesis`` - the Ricker wavelet of Tables 1 and 3, its spectrum,
+  and time-domain traces from one-sided frequency-domain solutions.
 
 Everything is float64 / complex128.  Arrays use the layout
 ``u[3][N3][N2][N1]`` (component, z, y, x), contrast ``dC[21][N3][N2][N1]``
@@ -30,4 +34,4 @@ operator).  The paper prints no numerical values for any worked example (its
 figures are placeholders), so no pin compares against a printed number.
 """
 
-from . import adjoint, green, operator, solve  # noqa: F401
+from . import adjoint, green, operator, solve, synthesis  # noqa: F401

@@ -95,7 +95,7 @@ static void release(Ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
                     c->xd, c->bd, c->gs, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
-                    c->state, c->stage, c->red, c->batch_b, c->batch_x};
+                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto q : c->ghat) (void)hipFree(q);
@@ -664,6 +664,29 @@ int ls_solve_batch(ls_ctx* const* ctxs, int n_ctx, const ls_job* jobs, int n_job
     for (int i = 0; i < n_ctx; ++i)
         if (codes[i] != LS_OK) return fail(codes[i], msgs[i]);
     return LS_OK;
+}
+
+int ls_sample(ls_ctx* c, const void* u, int n_rhs, const int* rec, int n_rec, void* out) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if (!u || !out || !rec) return fail(LS_ERR_ARG, "null argument");
+    if (n_rhs < 1 || n_rec < 1) return fail(LS_ERR_ARG, "n_rhs and n_rec must be >= 1");
+    for (int m = 0; m < n_rec; ++m)
+        if ((rc = check_cell(c, rec + 3 * m))) return rc;
+    return sample_launch(c, (const z128*)u, n_rhs, rec, n_rec, (z128*)out);
+}
+
+int ls_synthesize(ls_ctx* c, const void* spectra, const int* k, int n_freq, int n_trace, int nt, double dt, double fp,
+                  double ts, double* traces) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if (!spectra || !k || !traces) return fail(LS_ERR_ARG, "null argument");
+    if (n_freq < 1 || n_trace < 1 || nt < 2) return fail(LS_ERR_ARG, "n_freq, n_trace >= 1 and nt >= 2 required");
+    if (!(dt > 0) || !std::isfinite(dt) || !std::isfinite(fp) || !std::isfinite(ts))
+        return fail(LS_ERR_ARG, "dt must be positive; dt, fp, ts finite");
+    for (int q = 0; q < n_freq; ++q)
+        if (k[q] < 0 || 2 * k[q] > nt) return fail(LS_ERR_ARG, "frequency index outside [0, nt/2]");
+    return synthesize_launch(c, (const z128*)spectra, k, n_freq, n_trace, nt, dt, fp, ts, traces);
 }
 
 int ls_strain(ls_ctx* c, const void* u, void* eps, int n_rhs) {

@@ -125,6 +125,8 @@ struct Ctx {
     double* partials = nullptr;  // reduction partials [max_rhs][kRedSlots][kRedBlocks]
     double* state = nullptr;     // BiCGSTAB scalars per right-hand side [max_rhs][kStateLen]
     void* stage = nullptr;       // small host/device staging area (8 KB)
+    int* ints = nullptr;          // device staging for receiver lists and frequency indices (grown on demand)
+    int ints_cap = 0;
     z128 *batch_b = nullptr, *batch_x = nullptr;  // [max_rhs][3][n] right-hand sides / solutions of ls_solve_batch (allocated on its first use)
     double* red = nullptr;       // reduction results (device)
     double* red_host = nullptr;  // pinned host mirror
@@ -163,6 +165,9 @@ int to_work(Ctx* c, const cpx<T>* f, cpx<T>* work, int nrhs);
 int grad_contrast_launch(Ctx* c, int i_omega, const z128* u, const z128* mu, int nrhs, double* g21, double* grho);
 int fold_background(Ctx* c, const double* dc_in, const double* drho_in, const double fold21[21]);
 int conj_launch(Ctx* c, z128* a, long long m);
+int sample_launch(Ctx* c, const z128* u, int nrhs, const int* rec_host, int nrec, z128* out);
+int synthesize_launch(Ctx* c, const z128* U, const int* k_host, int nf, int ntr, int nt, double dt, double fp,
+                      double ts, double* traces);
 int grad_moment_launch(Ctx* c, int i_omega, const z128* mu, int nrhs, const int* src, const double* t0,
                        double* gM);
 int strain_launch(Ctx* c, const z128* u, z128* eps, int nrhs);

@@ -7,9 +7,9 @@ loading fails loudly (there is no CPU fallback).
 The module-level functions carry the C names (``ls_setup``, ``ls_apply``, ``ls_apply_c64``,
 ``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_moment``, ``ls_solve_force``,
 ``ls_solve_batch``, ``ls_strain``, ``ls_apply_T``, ``ls_convolve``, ``ls_solve_T``,
-``ls_grad_contrast``, ``ls_grad``, ``ls_profile``, ``ls_profile_read``, ``ls_device_bytes``,
-``ls_kernel_variants``, ``ls_destroy``); ``Context`` wraps them for convenience, and
-``solve_batch`` wraps ``ls_solve_batch`` over several contexts.
+``ls_grad_contrast``, ``ls_grad``, ``ls_sample``, ``ls_synthesize``, ``ls_profile``,
+``ls_profile_read``, ``ls_device_bytes``, ``ls_kernel_variants``, ``ls_destroy``); ``Context`` wraps
+them for convenience, and ``solve_batch`` wraps ``ls_solve_batch`` over several contexts.
 """
 
 import ctypes
@@ -41,7 +41,7 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
 
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
             "ls_solve_moment", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve",
-            "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch",
+            "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch", "ls_sample", "ls_synthesize",
             "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_last_error")
 
 
@@ -110,6 +110,8 @@ def load():
         "ls_grad_contrast": (I, [P, I, P, P, I, P, P]),
         "ls_grad": (I, [P, I, P, P, I, ip, dp, P, P, dp]),
         "ls_solve_batch": (I, [ctypes.POINTER(P), I, ctypes.POINTER(Job), I, D, I, I, ctypes.POINTER(Info)]),
+        "ls_sample": (I, [P, P, I, ip, I, P]),
+        "ls_synthesize": (I, [P, P, ip, I, I, I, D, D, D, P]),
         "ls_solve_force": (I, [P, I, dp, ip, D, I, I, P, ctypes.POINTER(Info)]),
         "ls_profile": (I, [P, I]),
         "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, I]),
@@ -291,6 +293,22 @@ def ls_solve_batch(ctxs, jobs, tol, maxit, precision, raise_on_error=True):
     if raise_on_error:
         _check(code)
     return code, [infos[i].as_dict() for i in range(len(jobs))]
+
+
+def _ints(a, shape):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(shape))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def ls_sample(ctx, u, n_rhs, rec, out):
+    r, rp = _ints(rec, (-1, 3))
+    return _check(load().ls_sample(ctx, _ptr(u), int(n_rhs), rp, len(r), _ptr(out)))
+
+
+def ls_synthesize(ctx, spectra, k, n_trace, nt, dt, fp, ts, traces):
+    kk, kp = _ints(k, (-1,))
+    return _check(load().ls_synthesize(ctx, _ptr(spectra), kp, len(kk), int(n_trace), int(nt), float(dt),
+                                       float(fp), float(ts), _ptr(traces)))
 
 
 def ls_profile(ctx, enable):
@@ -499,6 +517,25 @@ class Context:
             self._check(g_drho, self.field_shape[1:], torch.float64, "g_drho")
         gM = ls_grad(self.handle, i_omega, u, lam_bar, nrhs, g_dC, g_drho, src=src, t0=t0)
         return g_dC, g_drho, gM
+
+    def sample(self, u, receivers):
+        """Receiver samples [n_rhs, n_rec, 3] (complex128, on the device) of fields u at cells [n_rec, 3]."""
+        u, nrhs = self._field(u, self.torch.complex128)
+        nrec = int(np.asarray(receivers).reshape(-1, 3).shape[0])
+        out = self.torch.empty((nrhs, nrec, 3), dtype=self.torch.complex128, device=self.device)
+        ls_sample(self.handle, u, nrhs, receivers, out)
+        return out
+
+    def synthesize(self, spectra, k, nt, dt, fp=0.0, ts=0.0):
+        """Traces [n_trace, nt] (float64, on the device) from one-sided spectra [n_freq, n_trace] at the
+        frequency indices k (w_k = 2 pi k / (nt dt)), times the Ricker wavelet (fp, ts) when fp > 0."""
+        torch = self.torch
+        spectra = torch.as_tensor(spectra, device=self.device).to(torch.complex128).resolve_conj().contiguous()
+        if spectra.dim() != 2 or spectra.shape[0] != len(np.atleast_1d(k)):
+            raise ValueError("spectra must be [n_freq, n_trace] with one row per frequency index")
+        traces = torch.empty((spectra.shape[1], int(nt)), dtype=torch.float64, device=self.device)
+        ls_synthesize(self.handle, spectra, k, spectra.shape[1], nt, dt, fp, ts, traces)
+        return traces
 
     def strain(self, u):
         u, nrhs = self._field(u, self.torch.complex128)
