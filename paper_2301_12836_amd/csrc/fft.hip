@@ -328,7 +328,7 @@ __device__ __forceinline__ void fold_index(int k, int L, int& kf, bool& flipped)
 // block order (XCD-aware): right-hand side fastest, then x tiles and y rows in mirror pairs, so the
 // blocks that read the same octant rows of G^ run together on one XCD.  The data occupy z < n3 <= L/2.
 template <typename T, int L, int TX>
-__global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
+__global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
                                                                     int n3, const cpx<T>* __restrict__ ghat,
                                                                     const cpx<T>* __restrict__ tw, long long nb_real) {
