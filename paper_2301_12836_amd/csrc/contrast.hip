@@ -193,9 +193,8 @@ __device__ __forceinline__ cpx<T> w3(const W3<T>& w, cpx<T> fm, cpx<T> f0, cpx<T
 // take the halo rows below and above the column and the next 2*BY the halo columns left and right,
 // and compute only the tau components that the divergence reads there (Voigt 22, 23, 12 across a y
 // face; 11, 13, 12 across an x face).  With BX = 32 every wave has one role, so each step is one
-// tau pass per wave.  The z neighbours of tau at the owned cells stay in registers.
-// Step k: store the prefetched plane u(k+2), start loading u(k+3) and the dC and drho of the next
-// step, tau(k+1), then f(k).  Each u plane is read from HBM once per chunk (plus the xy halo, served
+// tau pass per wave.  The z neighbours of tau at the owned cells stay in registers, so step k
+// computes tau(k+1) and f(k) between the same two barriers (details at the loop).  Each u plane is read from HBM once per chunk (plus the xy halo, served
 // mostly from L2), each dC once per chunk and right-hand side (right-hand sides are the fastest
 // logical block index, so the blocks of one column share dC through one L2), and f is written once
 // as full 128-byte rows.  Derivatives use per-lane weights (no divergent branches at the model
@@ -301,7 +300,9 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     };
     // tau on plane q at this thread's cell, from u planes q-1, q, q+1: rows I of dC eps for which
     // the mask bit I is set
-    auto tau_cell = [&](int q, auto rows) __attribute__((always_inline)) {
+    // tau on plane q at this thread's cell, from u planes q-1, q, q+1: rows I of dC eps for which the
+    // mask bit I is set; the owned cell also returns its z components (Voigt 33, 23, 13) in zc
+    auto tau_cell = [&](int q, auto rows, cpx<T>* zc) __attribute__((always_inline)) {
         constexpr int mask = decltype(rows)::value;
         const cpx<T>* um = us + ((q - 1) & 3) * 3 * UP;
         const cpx<T>* u0 = us + (q & 3) * 3 * UP;
@@ -334,107 +335,107 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
 #pragma unroll
             for (int J = 0; J < 6; ++J) acc = acc + C[packed(I, J)] * eps[J];
             s[I * SP] = acc;
+            if constexpr (mask == 0x3f) {
+                if (I >= 2 && I <= 4) zc[I - 2] = acc;
+            }
         }
     };
-    auto tau_plane = [&](int q) __attribute__((always_inline)) {
+    auto tau_plane = [&](int q, cpx<T>* zc) __attribute__((always_inline)) {
         if (q < 0 || q >= N3 || !cell) return;  // never read with a nonzero weight
         if (role == 0)
-            tau_cell(q, std::integral_constant<int, 0x3f>{});
+            tau_cell(q, std::integral_constant<int, 0x3f>{}, zc);
         else if (role == 1)
-            tau_cell(q, std::integral_constant<int, (1 << 1) | (1 << 3) | (1 << 5)>{});
+            tau_cell(q, std::integral_constant<int, (1 << 1) | (1 << 3) | (1 << 5)>{}, zc);
         else
-            tau_cell(q, std::integral_constant<int, (1 << 0) | (1 << 4) | (1 << 5)>{});
+            tau_cell(q, std::integral_constant<int, (1 << 0) | (1 << 4) | (1 << 5)>{}, zc);
     };
 
-    // prologue: zero tau planes, u planes z0-2 .. z0+1, tau planes z0-1 and z0
+    // prologue: zero tau planes; u planes z0-2 .. z0+2; tau planes z0-1 and z0 (the owned cell's z
+    // components of tau in registers: tprev, tcur, tnext for planes k-1, k, k+1)
     for (int e = t; e < 2 * 6 * SP; e += NT) ts[e] = cpx<T>{T(0), T(0)};
     for (int q = z0 - 2; q <= z0 + 1; ++q) {
         load_plane(q);
         store_plane(q);
     }
     __syncthreads();
+    cpx<T> tprev[3] = {}, tcur[3] = {}, tnext[3] = {};
     load_C(C, z0 - 1);
-    tau_plane(z0 - 1);
+    tau_plane(z0 - 1, tprev);
     load_C(C, z0);
-    tau_plane(z0);
-    load_C(C, z0 + 1);
+    tau_plane(z0, tcur);
+    __syncthreads();  // tau(z0-1) has read u(z0-2), whose ring slot u(z0+2) takes
     load_plane(z0 + 2);
+    store_plane(z0 + 2);
+    if (z0 + 3 <= zend + 1) load_plane(z0 + 3);
+    load_C(C, z0 + 1);
     T dro = (drho + (long long)z0 * plane)[cell_xy], dron = T(0);
     __syncthreads();
     const int po = (ly + 1) * SX + (lx + 1);
-    cpx<T> tprev[3] = {};  // tau_{3,4,5} (Voigt 33, 23, 13) of the owned cell one plane below
-    if (own && z0 >= 1) {
-        const cpx<T>* s = ts + ((z0 - 1) & 1) * 6 * SP + po;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) tprev[c] = s[(2 + c) * SP];
-    }
 
-    // Every load for step k+1 is issued at the top of step k, so that each has a whole step to land
-    // (the wait counter retires loads in order, so late loads would hold up earlier consumers).
+    // One barrier per step: step k computes tau(k+1) into one tau plane and f(k) from the other, and
+    // stores u(k+3) into the ring slot of u(k-1), which nothing reads in this step.  The dC and drho of
+    // the next step are requested at the top of the step and the next u plane right after the store,
+    // so each load has about a whole step to land.
     for (int k = z0; k < zend; ++k) {
         const bool more = k + 1 < zend;
-        store_plane(k + 2);
         if (more) {
-            load_plane(k + 3);
             if constexpr (DB) load_C(Cn, k + 2);
             dron = (drho + (long long)(k + 1) * plane)[cell_xy];
         }
-        __syncthreads();
-        tau_plane(k + 1);
+        tau_plane(k + 1, tnext);
         if constexpr (!DB) {
             if (more) load_C(C, k + 2);
         }
-        __syncthreads();
+        if (own) {
+            const cpx<T>* s0 = ts + (k & 1) * 6 * SP + po;
+            const W3<T> tz = dt_weights(k, N3, inv_h);
+            auto tdx = [&](int I) __attribute__((always_inline)) {
+                const cpx<T>* v = s0 + I * SP;
+                return w3(txw, v[-1], v[0], v[1]);
+            };
+            auto tdy = [&](int I) __attribute__((always_inline)) {
+                const cpx<T>* v = s0 + I * SP;
+                return w3(tyw, v[-SX], v[0], v[SX]);
+            };
+            // tnext holds stale finite values on the last plane, where its weight is 0
+            const cpx<T> f0 = tdx(0) + tdy(5) + w3(tz, tprev[2], tcur[2], tnext[2]);
+            const cpx<T> f1 = tdx(5) + tdy(1) + w3(tz, tprev[1], tcur[1], tnext[1]);
+            const cpx<T> f2 = tdx(4) + tdy(3) + w3(tz, tprev[0], tcur[0], tnext[0]);
+            const long long p = (long long)k * plane + cell_xy;
+            const cpx<T>* uk = us + (k & 3) * 3 * UP + (ly + 2) * UX + (lx + 2);
+            const T wr = w2 * dro;
+            const cpx<T> g0 = wr * uk[0] - f0, g1 = wr * uk[UP] - f1, g2 = wr * uk[2 * UP] - f2;
+            if constexpr (OUT == 0) {
+                const long long cpitch = (long long)N3 * L2 * L1;
+                cpx<T>* w_ = out + (long long)rhs * 3 * cpitch + ((long long)k * L2 + gy) * L1 + gx;
+                w_[0] = g0;
+                w_[cpitch] = g1;
+                w_[2 * cpitch] = g2;
+            } else {
+                const cpx<T>* yr = y + (long long)rhs * 3 * n;
+                cpx<T>* o_ = out + (long long)rhs * 3 * n;
+                o_[p] = yr[p] - g0;
+                o_[n + p] = yr[n + p] - g1;
+                o_[2 * n + p] = yr[2 * n + p] - g2;
+            }
+        }
+        if (k + 3 <= zend + 1) {
+            store_plane(k + 3);
+            if (k + 4 <= zend + 1) load_plane(k + 4);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            tprev[c] = tcur[c];
+            tcur[c] = tnext[c];
+        }
+        dro = dron;
         if constexpr (DB) {
             if (more) {
 #pragma unroll
                 for (int qq = 0; qq < 21; ++qq) C[qq] = Cn[qq];
             }
         }
-        if (!own) {
-            dro = dron;
-            continue;
-        }
-        const cpx<T>* s0 = ts + (k & 1) * 6 * SP + po;
-        const cpx<T>* s1 = ts + ((k + 1) & 1) * 6 * SP + po;
-        const W3<T> tz = dt_weights(k, N3, inv_h);
-        auto tdx = [&](int I) __attribute__((always_inline)) {
-            const cpx<T>* v = s0 + I * SP;
-            return w3(txw, v[-1], v[0], v[1]);
-        };
-        auto tdy = [&](int I) __attribute__((always_inline)) {
-            const cpx<T>* v = s0 + I * SP;
-            return w3(tyw, v[-SX], v[0], v[SX]);
-        };
-        cpx<T> tcur[3], tnext[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            tcur[c] = s0[(2 + c) * SP];
-            tnext[c] = s1[(2 + c) * SP];  // weight 0 on the last plane
-        }
-        const cpx<T> f0 = tdx(0) + tdy(5) + w3(tz, tprev[2], tcur[2], tnext[2]);
-        const cpx<T> f1 = tdx(5) + tdy(1) + w3(tz, tprev[1], tcur[1], tnext[1]);
-        const cpx<T> f2 = tdx(4) + tdy(3) + w3(tz, tprev[0], tcur[0], tnext[0]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) tprev[c] = tcur[c];
-        const long long p = (long long)k * plane + cell_xy;
-        const cpx<T>* uk = us + (k & 3) * 3 * UP + (ly + 2) * UX + (lx + 2);
-        const T wr = w2 * dro;
-        dro = dron;
-        const cpx<T> g0 = wr * uk[0] - f0, g1 = wr * uk[UP] - f1, g2 = wr * uk[2 * UP] - f2;
-        if constexpr (OUT == 0) {
-            const long long cpitch = (long long)N3 * L2 * L1;
-            cpx<T>* w_ = out + (long long)rhs * 3 * cpitch + ((long long)k * L2 + gy) * L1 + gx;
-            w_[0] = g0;
-            w_[cpitch] = g1;
-            w_[2 * cpitch] = g2;
-        } else {
-            const cpx<T>* yr = y + (long long)rhs * 3 * n;
-            cpx<T>* o_ = out + (long long)rhs * 3 * n;
-            o_[p] = yr[p] - g0;
-            o_[n + p] = yr[n + p] - g1;
-            o_[2 * n + p] = yr[2 * n + p] - g2;
-        }
+        __syncthreads();
     }
 }
 
