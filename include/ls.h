@@ -243,6 +243,13 @@ int ls_grad_contrast(ls_ctx* ctx, int i_omega, const void* u, const void* mu, in
 int ls_grad(ls_ctx* ctx, int i_omega, const void* u, const void* lam_bar, int n_rhs, const int* src,
             const double* t0, double* g_dC, double* g_drho, double* g_M);
 
+/* Convergence record of the last ls_solve / ls_solve_moment / ls_solve_force / ls_solve_T on the context:
+ * the relative residual ||r|| / ||b|| after each BiCGSTAB iteration of right-hand side rhs (the
+ * recursive residual; with LS_PREC_MIXED, each inner iteration's residual scaled by the outer residual
+ * it started from, so the values refer to the original system).  Copies up to max_len values into the
+ * host array hist and returns how many the record holds (>= 0), or a negative LS_ERR_* code. */
+int ls_residual_history(ls_ctx* ctx, int rhs, double* hist, int max_len);
+
 /* Per-kernel timing of the library's own launches.  ls_profile(ctx, 1) starts recording a
  * HIP event pair around every kernel launch on the context's stream (at most a fixed number
  * of launches; later ones are not recorded); ls_profile(ctx, 0) stops.  ls_profile_read

@@ -697,6 +697,16 @@ int ls_strain(ls_ctx* c, const void* u, void* eps, int n_rhs) {
     return strain_launch(c, (const z128*)u, (z128*)eps, n_rhs);
 }
 
+int ls_residual_history(ls_ctx* c, int rhs, double* hist, int max_len) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if (rhs < 0 || rhs >= (int)c->history.size()) return fail(LS_ERR_ARG, "no such right-hand side in the last solve");
+    if (max_len < 0 || (max_len > 0 && !hist)) return fail(LS_ERR_ARG, "bad history buffer");
+    const auto& h = c->history[rhs];
+    for (int i = 0; i < max_len && i < (int)h.size(); ++i) hist[i] = h[i];
+    return (int)h.size();
+}
+
 int ls_profile(ls_ctx* c, int enable) {
     int rc;
     if ((rc = check_ctx(c))) return rc;

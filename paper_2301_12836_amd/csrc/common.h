@@ -127,6 +127,7 @@ struct Ctx {
     void* stage = nullptr;       // small host/device staging area (8 KB)
     int* ints = nullptr;          // device staging for receiver lists and frequency indices (grown on demand)
     int ints_cap = 0;
+    std::vector<std::vector<double>> history;  // per right-hand side: relative residual after each iteration of the last solve
     z128 *batch_b = nullptr, *batch_x = nullptr;  // [max_rhs][3][n] right-hand sides / solutions of ls_solve_batch (allocated on its first use)
     double* red = nullptr;       // reduction results (device)
     double* red_host = nullptr;  // pinned host mirror

@@ -407,7 +407,8 @@ int finalize(Ctx* c, int phase, int nslots, int nrhs, double tol2 = 0.0, double*
 // Generic BiCGSTAB.  T: vector precision, X: iterate precision (x is cpx<X>), ApplyFn(in, out).
 template <typename T, typename X, typename ApplyFn>
 int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, cpx<T>* rhat, cpx<T>* p, cpx<T>* v,
-             cpx<T>* s, cpx<T>* t, int nrhs, double tol, int maxit, ApplyFn apply, std::vector<int>& iters) {
+             cpx<T>* s, cpx<T>* t, int nrhs, double tol, int maxit, ApplyFn apply, std::vector<int>& iters,
+             const double* hscale = nullptr) {
     const long long m = (long long)c->field_elems();
     const dim3 g = vgrid(nrhs);
     hipLaunchKernelGGL((k_init<T>), g, dim3(kThreads), 0, c->stream, b, ax0, r, rhat, p, v, m, c->partials);
@@ -473,7 +474,7 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
     // residual).  FP64 solves run to tol or maxit.
     constexpr int kStall = 30;
     std::vector<double> best(nrhs, std::numeric_limits<double>::infinity());
-    std::vector<int> since(nrhs, 0);
+    std::vector<int> since(nrhs, 0), last_it(nrhs, 0);
     static const double zero = 0.0;
     for (int it = 0; it < maxit; ++it) {
         if (guard.exec) {
@@ -487,6 +488,11 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
         bool any = false;
         for (int q = 0; q < nrhs; ++q) {
             const double* sq = &c->red_host[q * kStateLen];
+            // relative residual of each completed iteration (scaled to the caller's system)
+            if ((int)sq[S_ITERS] > last_it[q] && sq[S_BNORM2] > 0.0 && (size_t)q < c->history.size()) {
+                last_it[q] = (int)sq[S_ITERS];
+                c->history[q].push_back(std::sqrt(sq[S_RNORM2] / sq[S_BNORM2]) * (hscale ? hscale[q] : 1.0));
+            }
             if (sq[S_ACTIVE] == 0.0) continue;
             if (sizeof(T) == 4) {
                 if (sq[S_RNORM2] < 0.81 * best[q]) {  // 10 % on the norm
@@ -538,6 +544,7 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
     const long long m = (long long)c->field_elems();
     std::vector<ls_info> inf(nrhs);
     for (auto& q : inf) q = ls_info{0, 0, 0, LS_OK, 0.0, 0.0};
+    c->history.assign(nrhs, std::vector<double>());
     // x = x0 or 0
     if (x0) {
         hipLaunchKernelGGL(k_copy, vgrid(nrhs), dim3(kThreads), 0, c->stream, x0, u_out, m);
@@ -549,22 +556,37 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
     std::vector<int> iters;
     int rc = LS_OK;
     if (precision == LS_PREC_C128) {
-        const z128* ax0 = nullptr;
-        if (x0) {
-            if ((rc = op_apply<double>(c, i_omega, u_out, c->t, nrhs, transposed))) return rc;
-            ax0 = c->t;
-        }
         auto apply = [&](const z128* in, z128* out) { return op_apply<double>(c, i_omega, in, out, nrhs, transposed); };
-        rc = bicgstab<double, double>(c, b, u_out, ax0, c->r, c->rhat, c->p, c->v, c->s, c->t, nrhs, tol, maxit, apply,
-                                      iters);
-        if (rc) return rc;
-        std::vector<double> st(c->red_host, c->red_host + (size_t)nrhs * kStateLen);
+        // A breakdown (rho = 0 or rhat^H v = 0) restarts once from the current iterate, which re-seeds the
+        // shadow residual with the current residual; systems already within tol take no further iteration.
+        std::vector<double> st;
+        std::vector<int> total(nrhs, 0), extra(nrhs, 0);
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            const z128* ax0 = nullptr;
+            if (x0 || attempt > 0) {
+                if ((rc = op_apply<double>(c, i_omega, u_out, c->t, nrhs, transposed))) return rc;
+                ax0 = c->t;
+                for (int q = 0; q < nrhs; ++q) extra[q] += 1;
+            }
+            rc = bicgstab<double, double>(c, b, u_out, ax0, c->r, c->rhat, c->p, c->v, c->s, c->t, nrhs, tol, maxit,
+                                          apply, iters);
+            if (rc) return rc;
+            st.assign(c->red_host, c->red_host + (size_t)nrhs * kStateLen);
+            bool broke = false;
+            for (int q = 0; q < nrhs; ++q) {
+                const double* sq = &st[(size_t)q * kStateLen];
+                const bool half = sq[S_DONE] == 1.0 && sq[S_SNORM2] == sq[S_RNORM2];
+                total[q] += iters[q];
+                extra[q] += 2 * iters[q] - (half ? 1 : 0);
+                broke = broke || sq[S_FLAG] == 2.0;
+            }
+            if (!broke) break;
+        }
         if ((rc = true_residual(c, i_omega, b, u_out, c->v, nullptr, nrhs, rel, nrm, transposed))) return rc;
         for (int q = 0; q < nrhs; ++q) {
             const double* sq = &st[(size_t)q * kStateLen];
-            inf[q].iters = iters[q];
-            const bool half = sq[S_DONE] == 1.0 && sq[S_SNORM2] == sq[S_RNORM2];
-            inf[q].matvecs = 2 * iters[q] - (half ? 1 : 0) + 1 + (x0 ? 1 : 0);
+            inf[q].iters = total[q];
+            inf[q].matvecs = extra[q] + 1;
             inf[q].rel_res = sq[S_BNORM2] > 0 ? std::sqrt(sq[S_RNORM2] / sq[S_BNORM2]) : 0.0;
             inf[q].rel_res_true = rel[q];
             if (sq[S_FLAG] == 3.0 || !std::isfinite(rel[q]))
@@ -621,7 +643,7 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 return op_apply<float>(c, i_omega, in, out, nrhs, transposed);
             };
             rc = bicgstab<float, float>(c, c->b32, c->x32, nullptr, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32,
-                                        nrhs, eta, maxit, apply32, iters);
+                                        nrhs, eta, maxit, apply32, iters, rel.data());
             if (rc) return rc;
             for (int q = 0; q < nrhs; ++q) {
                 if (!active[q]) continue;

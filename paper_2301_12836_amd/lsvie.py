@@ -7,7 +7,7 @@ loading fails loudly (there is no CPU fallback).
 The module-level functions carry the C names (``ls_setup``, ``ls_apply``, ``ls_apply_c64``,
 ``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_moment``, ``ls_solve_force``,
 ``ls_solve_batch``, ``ls_strain``, ``ls_apply_T``, ``ls_convolve``, ``ls_solve_T``,
-``ls_grad_contrast``, ``ls_grad``, ``ls_sample``, ``ls_synthesize``, ``ls_profile``,
+``ls_grad_contrast``, ``ls_grad``, ``ls_sample``, ``ls_synthesize``, ``ls_residual_history``, ``ls_profile``,
 ``ls_profile_read``, ``ls_device_bytes``, ``ls_kernel_variants``, ``ls_destroy``); ``Context`` wraps
 them for convenience, and ``solve_batch`` wraps ``ls_solve_batch`` over several contexts.
 """
@@ -41,7 +41,7 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
 
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
             "ls_solve_moment", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve",
-            "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch", "ls_sample", "ls_synthesize",
+            "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch", "ls_sample", "ls_synthesize", "ls_residual_history",
             "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_last_error")
 
 
@@ -111,6 +111,7 @@ def load():
         "ls_grad": (I, [P, I, P, P, I, ip, dp, P, P, dp]),
         "ls_solve_batch": (I, [ctypes.POINTER(P), I, ctypes.POINTER(Job), I, D, I, I, ctypes.POINTER(Info)]),
         "ls_sample": (I, [P, P, I, ip, I, P]),
+        "ls_residual_history": (I, [P, I, dp, I]),
         "ls_synthesize": (I, [P, P, ip, I, I, I, D, D, D, P]),
         "ls_solve_force": (I, [P, I, dp, ip, D, I, I, P, ctypes.POINTER(Info)]),
         "ls_profile": (I, [P, I]),
@@ -309,6 +310,18 @@ def ls_synthesize(ctx, spectra, k, n_trace, nt, dt, fp, ts, traces):
     kk, kp = _ints(k, (-1,))
     return _check(load().ls_synthesize(ctx, _ptr(spectra), kp, len(kk), int(n_trace), int(nt), float(dt),
                                        float(fp), float(ts), _ptr(traces)))
+
+
+def ls_residual_history(ctx, rhs):
+    """numpy array of the relative residual after each iteration of right-hand side rhs in the last solve."""
+    lib = load()
+    n = lib.ls_residual_history(ctx, int(rhs), None, 0)
+    if n < 0:
+        _check(n)
+    out = np.zeros(n, dtype=np.float64)
+    if n:
+        _check(min(0, lib.ls_residual_history(ctx, int(rhs), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n)))
+    return out
 
 
 def ls_profile(ctx, enable):
@@ -542,6 +555,9 @@ class Context:
         eps = self.torch.empty(u.shape[:-4] + (6,) + self.field_shape[1:], dtype=u.dtype, device=self.device)
         ls_strain(self.handle, u, eps, nrhs)
         return eps
+
+    def residual_history(self, rhs=0):
+        return ls_residual_history(self.handle, rhs)
 
     def profile(self, enable=True):
         ls_profile(self.handle, enable)

@@ -313,3 +313,41 @@ def test_absorbing_taper_apply_and_gradient_weight():
     with pytest.raises(lsvie.LsError) as e:
         lsvie.context_from_model(m, omegas=[W15], taper=6)
     assert e.value.code == lsvie.LS_ERR_ARG
+
+
+def test_residual_history_matches_textbook_bicgstab():
+    """The recorded residual after each iteration equals the oracle's textbook BiCGSTAB on the same system
+    (same iterates in exact arithmetic: x0 = 0, shadow residual r0) while rounding is small, and the
+    mixed-precision record (inner residuals scaled to the original system) ends below tol."""
+    from oracle import solve
+    m = models.random_medium((8, 7, 6), seed=12, rel=0.1, aniso_background=True)
+    ctx, (P,) = ctx_and_problem(m, omegas=[W15], precision="mixed")
+    b = ctx.rhs_moment(models.EXPLOSION, (4, 3, 3))
+    x, infos = ctx.solve(b, tol=1e-10, precision="c128")
+    h = ctx.residual_history(0)
+    _, hist, _ = solve.bicgstab(P.apply_fft, to_np(b), 1e-10)
+    print("iterations", len(h), len(hist) - 1, "first", h[:4], hist[1:5], flush=True)
+    assert len(h) == infos[0]["iters"] and abs(len(h) - (len(hist) - 1)) <= 1
+    for i in range(min(5, len(h))):
+        assert abs(h[i] - hist[i + 1]) <= 1e-8 * hist[i + 1]
+    xm, im = ctx.solve(b, tol=1e-6, precision="mixed")
+    hm = ctx.residual_history(0)
+    assert len(hm) == im[0]["iters"] and hm[-1] < 1e-6 and hm[0] < 1.0
+    with pytest.raises(lsvie.LsError):
+        ctx.residual_history(1)
+    ctx.close()
+
+
+def test_nonfinite_contrast_is_reported():
+    m = models.random_medium((6, 6, 6), seed=2)
+    dc = m.dc21.copy()
+    dc[0, 3, 3, 3] = np.nan
+    ctx = lsvie.Context(m.shape, m.h, m.C0, m.rho0, dc, m.drho, [W15], precision="mixed")
+    b = ctx.rhs_moment(models.EXPLOSION, (2, 2, 2))
+    for prec in ("c128", "mixed"):
+        _, infos = ctx.solve(b, tol=1e-8, precision=prec, raise_on_error=False)
+        assert infos[0]["status"] == lsvie.LS_ERR_NONFINITE, (prec, infos)
+    with pytest.raises(lsvie.LsError) as e:
+        ctx.solve(b, tol=1e-8, precision="c128")
+    assert e.value.code == lsvie.LS_ERR_NONFINITE
+    ctx.close()
