@@ -127,6 +127,27 @@ def double_couple(strike, dip, rake, m0=1.0):
     return m0 * np.array([m11, m22, m33, m23, m13, m12])
 
 
+def fault_vectors(strike, dip, rake):
+    """Unit fault normal nu and slip direction d of Aki and Richards (x north, y east, z down)."""
+    f, dl, l = np.deg2rad([strike, dip, rake])
+    nu = np.array([-np.sin(dl) * np.sin(f), np.sin(dl) * np.cos(f), -np.cos(dl)])
+    d = np.array([np.cos(l) * np.cos(f) + np.cos(dl) * np.sin(l) * np.sin(f),
+                  np.cos(l) * np.sin(f) - np.cos(dl) * np.sin(l) * np.cos(f),
+                  -np.sin(l) * np.sin(dl)])
+    return nu, d
+
+
+def double_couple_aniso(C, strike, dip, rake, potency=1.0):
+    """Moment tensor of a shear dislocation (slip x area = potency) in a medium of stiffness C (6x6 Voigt):
+    M = potency C : sym(nu (x) d), the double-couple source of an anisotropic medium (the paper's VTI
+    example takes its source this way).  For isotropic C it is mu potency times the Aki-Richards double
+    couple; in anisotropic media it has non-double-couple parts.  Voigt (11,22,33,23,13,12)."""
+    nu, d = fault_vectors(strike, dip, rake)
+    e = np.array([nu[0] * d[0], nu[1] * d[1], nu[2] * d[2], nu[1] * d[2] + nu[2] * d[1],
+                  nu[0] * d[2] + nu[2] * d[0], nu[0] * d[1] + nu[1] * d[0]])   # engineering Voigt strain
+    return potency * (np.asarray(C, dtype=np.float64) @ e)
+
+
 EXPLOSION = np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0])
 
 

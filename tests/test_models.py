@@ -48,3 +48,19 @@ def test_random_fields_are_normalised():
     g = models.gaussian_random_fields(np.random.default_rng(0), 2, 32, 8.0, 40.0)
     assert np.allclose(g.mean(axis=(1, 2, 3)), 0, atol=1e-12)
     assert np.allclose(g.std(axis=(1, 2, 3)), 1, atol=1e-12)
+
+
+def test_anisotropic_double_couple():
+    """C : sym(nu x d) reduces to mu x potency x the Aki-Richards double couple for isotropic C (the fault
+    normal and slip are orthonormal, so the trace term vanishes); in a VTI medium it is no longer
+    trace-free for an inclined fault."""
+    for sdr in ((30, 60, 90), (0, 90, 0), (120, 35, -45)):
+        nu, d = models.fault_vectors(*sdr)
+        assert np.isclose(nu @ nu, 1) and np.isclose(d @ d, 1) and abs(nu @ d) < 1e-14
+        Ciso = models.iso_C(3000.0, 1700.0, 2400.0)
+        mu = Ciso[3, 3]
+        M = models.double_couple_aniso(Ciso, *sdr, potency=2.0)
+        assert np.allclose(M, models.double_couple(*sdr, m0=2.0 * mu), rtol=1e-12, atol=1e-3)
+    Cvti = models.vti_from_thomsen(**models.VTI_CFG2)
+    M = models.double_couple_aniso(Cvti, 30, 60, 90)
+    assert abs(M[0] + M[1] + M[2]) > 1e-3 * np.abs(M).max()
