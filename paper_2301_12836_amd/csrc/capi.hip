@@ -352,7 +352,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
         if (c->mixed) A((void**)&c->ghat32[i], 6 * oct * sizeof(z64));
     }
     A(&c->work, (size_t)c->max_rhs * 3 * c->n3 * c->L2 * c->L1 * sizeof(z128));
-    A(&c->tau, (size_t)c->max_rhs * 6 * n * sizeof(z128));
+    if (!use_fused_contrast()) A(&c->tau, (size_t)c->max_rhs * 6 * n * sizeof(z128));  // split contrast only
     z128** v128[] = {&c->r, &c->rhat, &c->p, &c->v, &c->s, &c->t};
     for (auto pp : v128) A((void**)pp, fe * sizeof(z128));
     A((void**)&c->bd, 3 * n * sizeof(z128));

@@ -114,7 +114,7 @@ struct Ctx {
 
     // workspaces
     void* work = nullptr;       // padded FFT buffer [max_rhs][3][N3][L2][L1] (c128 size)
-    void* tau = nullptr;        // Voigt stress scratch [max_rhs][6][ncell] (c128 size)
+    void* tau = nullptr;        // Voigt stress scratch [max_rhs][6][ncell] (c128 size), split contrast only
     // Krylov vectors, c128 [max_rhs][3][ncell] each
     z128 *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
     z128 *xd = nullptr, *bd = nullptr;           // FP64 iterate / rhs copies for refinement
@@ -165,6 +165,7 @@ template <typename T>
 int to_work(Ctx* c, const cpx<T>* f, cpx<T>* work, int nrhs);
 int grad_contrast_launch(Ctx* c, int i_omega, const z128* u, const z128* mu, int nrhs, double* g21, double* grho);
 int fold_background(Ctx* c, const double* dc_in, const double* drho_in, const double fold21[21]);
+bool use_fused_contrast();  // false under LS_CONTRAST=split (the two-kernel contrast, which needs tau)
 int conj_launch(Ctx* c, z128* a, long long m);
 int sample_launch(Ctx* c, const z128* u, int nrhs, const int* rec_host, int nrec, z128* out);
 int synthesize_launch(Ctx* c, const z128* U, const int* k_host, int nf, int ntr, int nt, double dt, double fp,
