@@ -79,3 +79,21 @@ def test_output_buffers_are_checked_before_the_library_writes():
     for t in bad:
         with pytest.raises(ValueError):
             lsvie.check_buffer(t, shape, torch.complex128, dev)
+
+
+def test_header_is_plain_c():
+    """The boundary is a C ABI: the header compiles as C99 (and as C++) with no HIP or torch types."""
+    import shutil
+    import subprocess
+    import tempfile
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    src = '#include "ls.h"\nint main(void) { ls_options o = {0}; ls_info i = {0}; ls_job j = {0};\n' \
+          '  (void)o; (void)i; (void)j; return LS_OK; }\n'
+    with tempfile.TemporaryDirectory() as d:
+        for lang, comp, std in (("c", "gcc", "-std=c99"), ("c++", "g++", "-std=c++17")):
+            f = os.path.join(d, "t." + ("c" if lang == "c" else "cpp"))
+            open(f, "w").write(src)
+            r = subprocess.run([comp, std, "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.join(ROOT, "include"), f],
+                               capture_output=True, text=True)
+            assert r.returncode == 0, r.stderr
