@@ -17,13 +17,15 @@ Discretisation (the readings are listed with each function):
   M at cell s (Eq 13-16, Aki-Richards sign) is b = e^{i w t0} Gconv E^T (M delta_s) / h^3.
 * background: if C0 is not isotropic, the isotropic reference takes
   c11 = C33, c44 = (C44 + C55)/2 (the rule of the paper's Model 1) and C0 - C_iso
-  is added to the contrast of every cell.
+  is added to the contrast of every cell.  Mode 'aniso' instead convolves with the
+  Green's tensor of C0 itself (``green_aniso``) and adds nothing to the contrast.
 """
 
 import numpy as np
 import scipy.sparse as sp
 
 from . import green as _green
+from . import green_aniso as _green_aniso
 
 # Voigt index J -> tensor pair (0-based x, y, z): 11, 22, 33, 23, 13, 12 (Eq 17)
 VOIGT_PAIRS = ((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))
@@ -225,15 +227,24 @@ def contrast_apply(u, h, dc21_total, drho, omega):
 # Green's table and convolution
 
 
-def green_tensor(d, omega, alpha, beta, rho, mode):
+def green_tensor(d, omega, alpha, beta, rho, mode, C0=None):
     if mode == 'exact':
         return _green.green_exact(d, omega, alpha, beta, rho)
     if mode == 'paper_sum':
         return _green.green_paper_sum(d, omega, alpha, beta, rho)
+    if mode == 'aniso':
+        return _green_aniso.green_aniso(d, omega, C0, rho)
     raise ValueError(mode)
 
 
-def green_table(shape, h, omega, alpha, beta, rho, mode='exact'):
+def self_matrix(h, omega, alpha, beta, rho, mode, C0=None):
+    """The r = 0 table entry (a 3x3 matrix): the integral of G over the sphere of volume h^3."""
+    if mode == 'aniso':
+        return _green_aniso.green_aniso_self_term(h, omega, C0, rho)
+    return _green.green_self_term(h, omega, alpha, beta, rho) * np.eye(3)
+
+
+def green_table(shape, h, omega, alpha, beta, rho, mode='exact', C0=None):
     """T[3, 3, 2N3-1, 2N2-1, 2N1-1]: T at offset (dx, dy, dz) stored at [..., dz+N3-1, dy+N2-1, dx+N1-1]."""
     n1, n2, n3 = shape
     oz, oy, ox = np.meshgrid(np.arange(-(n3 - 1), n3), np.arange(-(n2 - 1), n2),
@@ -241,8 +252,16 @@ def green_table(shape, h, omega, alpha, beta, rho, mode='exact'):
     d = np.stack([ox, oy, oz], axis=-1).astype(np.float64) * h
     zero = (ox == 0) & (oy == 0) & (oz == 0)
     d[zero] = 1.0  # placeholder, overwritten below
-    G = green_tensor(d, omega, alpha, beta, rho, mode) * h**3
-    G[zero] = _green.green_self_term(h, omega, alpha, beta, rho) * np.eye(3)
+    if mode == 'aniso':
+        # G(-x) = G(x) for every homogeneous medium (Gamma(n) is even in n): evaluate the half of the
+        # offsets that comes first in (dz, dy, dx) order, then mirror it through the origin
+        half = (oz > 0) | ((oz == 0) & (oy > 0)) | ((oz == 0) & (oy == 0) & (ox > 0))
+        G = np.zeros(d.shape[:-1] + (3, 3), dtype=complex)
+        G[half] = green_tensor(d[half], omega, alpha, beta, rho, mode, C0) * h**3
+        G = G + G[::-1, ::-1, ::-1]
+    else:
+        G = green_tensor(d, omega, alpha, beta, rho, mode) * h**3
+    G[zero] = self_matrix(h, omega, alpha, beta, rho, mode, C0)
     return np.moveaxis(G, (-2, -1), (0, 1))
 
 
@@ -262,18 +281,18 @@ def dense_green(shape, T):
     return blk.transpose(0, 2, 1, 3).reshape(3 * n, 3 * n)
 
 
-def convolve_at(f, shape, h, omega, alpha, beta, rho, cells, mode='exact'):
+def convolve_at(f, shape, h, omega, alpha, beta, rho, cells, mode='exact', C0=None):
     """(Gconv f) at the listed cells by direct O(n) sums per cell; f [3, N3, N2, N1]; cells [m, 3] (x,y,z)."""
     P = cell_coords(shape)
     fv = f.reshape(3, -1)
     out = np.zeros((len(cells), 3), dtype=complex)
-    self_val = _green.green_self_term(h, omega, alpha, beta, rho)
+    self_val = self_matrix(h, omega, alpha, beta, rho, mode, C0)
     for t, c in enumerate(np.asarray(cells)):
         d = (c[None, :] - P).astype(np.float64) * h
         here = np.all(d == 0.0, axis=1)
         d[here] = 1.0
-        G = green_tensor(d, omega, alpha, beta, rho, mode) * h**3
-        G[here] = self_val * np.eye(3)
+        G = green_tensor(d, omega, alpha, beta, rho, mode, C0) * h**3
+        G[here] = self_val
         out[t] = np.einsum('qij,jq->i', G, fv)
     return out
 
@@ -307,9 +326,13 @@ class Problem:
         self.omega = omega
         self.rho0 = float(rho0)
         self.alpha, self.beta, self.c_iso = iso_reference(C0, rho0)
+        self.C0 = np.asarray(C0, dtype=np.float64)
         n3, n2, n1 = self.shape[2], self.shape[1], self.shape[0]
         w = taper_weights(self.shape, taper)   # the absorbing layer weights the total contrast (Eq 25)
-        self.dc21 = total_contrast21(C0, rho0, np.asarray(dc21).reshape(21, n3, n2, n1)) * w[None]
+        dc21 = np.asarray(dc21, dtype=np.float64).reshape(21, n3, n2, n1)
+        if mode != 'aniso':
+            dc21 = total_contrast21(C0, rho0, dc21)
+        self.dc21 = dc21 * w[None]
         self.drho = np.asarray(drho, dtype=np.float64).reshape(n3, n2, n1) * w
         self.mode = mode
         self._T = None
@@ -324,7 +347,8 @@ class Problem:
 
     def table(self):
         if self._T is None:
-            self._T = green_table(self.shape, self.h, self.omega, self.alpha, self.beta, self.rho0, self.mode)
+            self._T = green_table(self.shape, self.h, self.omega, self.alpha, self.beta, self.rho0, self.mode,
+                                  self.C0)
         return self._T
 
     def B(self):
@@ -348,7 +372,8 @@ class Problem:
             v = (dense_green(self.shape, self.table()) @ f.reshape(-1)).reshape(u.shape)
             return u - v
         cells = np.asarray(cells)
-        v = convolve_at(f, self.shape, self.h, self.omega, self.alpha, self.beta, self.rho0, cells, self.mode)
+        v = convolve_at(f, self.shape, self.h, self.omega, self.alpha, self.beta, self.rho0, cells, self.mode,
+                        self.C0)
         return u[:, cells[:, 2], cells[:, 1], cells[:, 0]].T - v
 
     def moment_source(self, M, src):
@@ -359,17 +384,21 @@ class Problem:
         return strain_adjoint_apply(tau, self.h) / self.h**3
 
     def convolve_point_sources(self, f):
-        """Gconv f for a force density f with few non-zero cells, by direct closed-form sums over all cells."""
+        """Gconv f for a force density f with few non-zero cells, by direct closed-form sums over all cells.
+
+        The anisotropic tensor has no closed form; mode 'aniso' convolves with the sampled table instead."""
+        if self.mode == 'aniso':
+            return convolve_fft(f, self.table())
         P = cell_coords(self.shape)
         out = np.zeros((self.n, 3), dtype=complex)
-        self_val = _green.green_self_term(self.h, self.omega, self.alpha, self.beta, self.rho0)
+        self_val = self_matrix(self.h, self.omega, self.alpha, self.beta, self.rho0, self.mode, self.C0)
         fv = f.reshape(3, -1)
         for q in np.flatnonzero(np.any(fv != 0, axis=0)):
             d = (P - P[q][None, :]).astype(np.float64) * self.h
             here = np.all(d == 0.0, axis=1)
             d[here] = 1.0
-            G = green_tensor(d, self.omega, self.alpha, self.beta, self.rho0, self.mode) * self.h**3
-            G[here] = self_val * np.eye(3)
+            G = green_tensor(d, self.omega, self.alpha, self.beta, self.rho0, self.mode, self.C0) * self.h**3
+            G[here] = self_val
             out += G @ fv[:, q]
         return out.T.reshape(self.field_shape)
 
