@@ -52,7 +52,7 @@ enum {
 };
 
 enum { LS_PREC_C128 = 0, LS_PREC_MIXED = 1 };
-enum { LS_GREEN_EXACT = 0, LS_GREEN_PAPER_SUM = 1 };
+enum { LS_GREEN_EXACT = 0, LS_GREEN_PAPER_SUM = 1, LS_GREEN_ANISO = 2 };
 
 typedef struct {
     int n[3];       /* N1, N2, N3 */
@@ -62,7 +62,9 @@ typedef struct {
 typedef struct {
     int precision;  /* LS_PREC_C128: FP64 operator only; LS_PREC_MIXED: also the FP32 operator */
     int green_mode; /* LS_GREEN_EXACT (default): the closed-form solution of Eq 7;
-                       LS_GREEN_PAPER_SUM: the near-field A.4 plus far-field A.5 tensors   */
+                       LS_GREEN_PAPER_SUM: the near-field A.4 plus far-field A.5 tensors;
+                       LS_GREEN_ANISO: the solution of Eq 7 for the anisotropic C0 itself
+                       (see below)                                                          */
     int max_rhs;    /* largest batch of right-hand sides one call may carry (>= 1)         */
     int flags;      /* LS_FLAG_* bits (0: defaults)                                          */
     int taper;      /* absorbing boundary layer thickness in cells (0: off); see below        */
@@ -75,6 +77,22 @@ typedef struct {
  * centre through it leaves the box (the faces lie half a cell outside the outer cell centres), N_a the
  * number of cells along the axis of the face it crosses.  Gradients (ls_grad_contrast, ls_grad) are
  * taken with respect to the input contrast, so they carry the same weight.  0 <= d <= min(N)/2. */
+
+/* ls_options.green_mode = LS_GREEN_ANISO convolves with the Green's tensor of the background C0 itself
+ * instead of folding C0 into an isotropic reference plus contrast (the paper's method admits an arbitrary
+ * background, Eq 2-3, 7; Appendix A writes out only the isotropic tensor).  The tensor is evaluated from
+ * its plane-wave (unit-sphere) representation: with Gamma(n) the Christoffel matrix, lambda_m, P_m its
+ * eigenvalues and eigenprojectors and k_m = w sqrt(rho0 / lambda_m),
+ *     G(x) = 1/(8 pi^2 r) int_{n.x = 0} Gamma(n)^{-1} dphi
+ *          + i/(8 pi^2) int_{n.x > 0} sum_m P_m k_m / lambda_m e^{i k_m n.x} dS(n),
+ * and the zero-offset cell takes the integral over the sphere of volume h^3,
+ *     1/(4 pi) int sum_m P_m I(k_m) / lambda_m dS,  I(k) = int_0^R r e^{i k r} dr,  R = (3/(4 pi))^{1/3} h
+ * (for an isotropic C0 both equal the LS_GREEN_EXACT table).  Requirements, checked at set-up
+ * (LS_ERR_ARG otherwise): C0 has the three coordinate mirror planes (orthorhombic, VTI or isotropic in
+ * the grid axes: C14..C16, C24..C26, C34..C36, C45, C46, C56 zero), is positive definite, its quasi-P
+ * eigenvalue stays at least 5 % above the quasi-S ones in every direction, and the largest phase
+ * w r / v_min over the grid is at most 1600 rad.  Nothing is folded into the contrast.  The table is
+ * computed once per frequency at set-up (FP64 quadrature on the device, seconds at 256^3). */
 
 /* ls_options.flags:
  *   LS_FLAG_NO_GRAPH  run every BiCGSTAB iteration as separate launches instead of replaying one
@@ -96,9 +114,9 @@ typedef struct ls_ctx ls_ctx;
 
 /* Build a context for one grid and medium at n_omega angular frequencies (Eq 1-3, 7, 21).
  *   C0[36]  host, row-major 6x6 background stiffness (must be symmetric).  If it is not
- *           isotropic, the isotropic reference c11 = C33, c44 = (C44 + C55)/2 is used (the
- *           rule of the paper's Model 1) and C0 minus that reference is added to every
- *           cell's contrast.
+ *           isotropic and green_mode is not LS_GREEN_ANISO, the isotropic reference c11 = C33,
+ *           c44 = (C44 + C55)/2 is used (the rule of the paper's Model 1) and C0 minus that
+ *           reference is added to every cell's contrast.
  *   rho0    background density.
  *   dC      device, [21][N3][N2][N1] doubles (see conventions); drho device, [N3][N2][N1].
  *           Both are copied; the caller may free them after the call returns.

@@ -95,10 +95,11 @@ static void release(Ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
                     c->xd, c->bd, c->gs, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
-                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints};
+                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto q : c->ghat) (void)hipFree(q);
+    for (auto q : c->greal) (void)hipFree(q);
     for (auto q : c->ghat32) (void)hipFree(q);
     for (auto q : c->tw128) (void)hipFree(q);
     for (auto q : c->tw64) (void)hipFree(q);
@@ -269,7 +270,16 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, 0, 0, {0, 0, 0}};
     if (opt) o = *opt;
     if (o.precision != LS_PREC_C128 && o.precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
-    if (o.green_mode != LS_GREEN_EXACT && o.green_mode != LS_GREEN_PAPER_SUM) return fail(LS_ERR_ARG, "bad green_mode");
+    if (o.green_mode != LS_GREEN_EXACT && o.green_mode != LS_GREEN_PAPER_SUM && o.green_mode != LS_GREEN_ANISO)
+        return fail(LS_ERR_ARG, "bad green_mode");
+    if (o.green_mode == LS_GREEN_ANISO) {
+        // the three coordinate mirror planes: no coupling of normal and shear strains or of different shears
+        for (int I = 0; I < 6; ++I)
+            for (int J = I + 1; J < 6; ++J)
+                if ((J >= 3) && std::fabs(C0[I * 6 + J]) > 1e-12 * cmax)
+                    return fail(LS_ERR_ARG, "LS_GREEN_ANISO needs a background with the three coordinate mirror "
+                                            "planes (C14..C16, C24..C26, C34..C36, C45, C46, C56 zero)");
+    }
     if (o.max_rhs < 1 || o.max_rhs > 64) return fail(LS_ERR_ARG, "max_rhs must be in [1, 64]");
     if (o.taper < 0 || 2 * o.taper > std::min(grid->n[0], std::min(grid->n[1], grid->n[2])))
         return fail(LS_ERR_ARG, "taper must be in [0, min(N)/2]");
@@ -290,7 +300,8 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     for (int I = 3; I < 6; ++I) Ciso[I * 6 + I] = c44;
     double fold21[21];
     for (int I = 0, q = 0; I < 6; ++I)
-        for (int J = I; J < 6; ++J, ++q) fold21[q] = C0[I * 6 + J] - Ciso[I * 6 + J];
+        for (int J = I; J < 6; ++J, ++q)
+            fold21[q] = o.green_mode == LS_GREEN_ANISO ? 0.0 : C0[I * 6 + J] - Ciso[I * 6 + J];
 
     Ctx* c = new (std::nothrow) ls_ctx();
     if (!c) return fail(LS_ERR_OOM, "host allocation failed");
@@ -306,6 +317,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     c->green_mode = o.green_mode;
     c->max_rhs = o.max_rhs;
     c->rho0 = rho0;
+    std::copy(C0, C0 + 36, c->C0);
     c->alpha = std::sqrt(c11 / rho0);
     c->beta = std::sqrt(c44 / rho0);
     c->omega.assign(omega, omega + n_omega);
@@ -350,6 +362,10 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     for (int i = 0; i < n_omega; ++i) {
         A((void**)&c->ghat[i], 6 * oct * sizeof(z128));
         if (c->mixed) A((void**)&c->ghat32[i], 6 * oct * sizeof(z64));
+    }
+    if (c->green_mode == LS_GREEN_ANISO) {
+        c->greal.assign(n_omega, nullptr);
+        for (int i = 0; i < n_omega; ++i) A((void**)&c->greal[i], 6 * n * sizeof(z128));
     }
     A(&c->work, (size_t)c->max_rhs * 3 * c->n3 * c->L2 * c->L1 * sizeof(z128));
     if (!use_fused_contrast()) A(&c->tau, (size_t)c->max_rhs * 6 * n * sizeof(z128));  // split contrast only

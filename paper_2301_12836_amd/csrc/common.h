@@ -83,7 +83,8 @@ struct Ctx {
     int green_mode = LS_GREEN_EXACT;
     int max_rhs = 1;
     double rho0 = 0, alpha = 0, beta = 0;
-    double fold21[21] = {0};      // C0 - C_iso, packed, added to every cell's contrast
+    double fold21[21] = {0};      // C0 - C_iso, packed, added to every cell's contrast (zero for LS_GREEN_ANISO)
+    double C0[36] = {0};          // background stiffness as given
     std::vector<double> omega;
     hipStream_t stream = nullptr;
     hipStream_t own_stream = nullptr;  // created when the caller passes the null stream (a blocking stream,
@@ -105,7 +106,9 @@ struct Ctx {
     // k-space Green's tables per frequency: octant [L3/2+1][L2/2+1][L1/2+1][6], already scaled by
     // 1/(L1 L2 L3) so the inverse FFT needs no normalisation
     std::vector<z128*> ghat;
+    std::vector<z128*> greal;     // LS_GREEN_ANISO: h^3 G at the offsets of one octant, [N3][N2][N1][6] per frequency
     std::vector<z64*> ghat32;
+    double* gl_nodes = nullptr;   // LS_GREEN_ANISO: Gauss-Legendre nodes and weights on [0, 1] (device)
 
     // twiddle tables e^{-2 pi i m / L}, m < L, per distinct length
     std::vector<int> tw_len;

@@ -31,6 +31,8 @@ LS_PREC_C128 = 0
 LS_PREC_MIXED = 1
 LS_GREEN_EXACT = 0
 LS_GREEN_PAPER_SUM = 1
+LS_GREEN_ANISO = 2
+GREEN_MODES = {"exact": LS_GREEN_EXACT, "paper_sum": LS_GREEN_PAPER_SUM, "aniso": LS_GREEN_ANISO}
 LS_FLAG_NO_GRAPH = 1
 LS_FLAG_AUTOTUNE = 2
 PASS_NAMES = ("x_fwd", "y_fwd", "z_green", "y_inv", "x_inv")
@@ -379,7 +381,7 @@ class Context:
         self.stream = torch.cuda.current_stream(self.device)
         self.handle = ls_setup(self.shape, h, C0, rho0, dc, dr, self.omegas,
                                LS_PREC_MIXED if self.mixed else LS_PREC_C128,
-                               LS_GREEN_PAPER_SUM if green_mode == "paper_sum" else LS_GREEN_EXACT, max_rhs,
+                               GREEN_MODES[green_mode], max_rhs,
                                self.stream.cuda_stream,
                                (0 if graphs else LS_FLAG_NO_GRAPH) | (LS_FLAG_AUTOTUNE if autotune else 0),
                                int(taper))
