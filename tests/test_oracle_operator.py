@@ -284,3 +284,26 @@ def test_taper_weights_geometry():
     # the corner cell's ray leaves through the corner: l = sqrt(3) / 2
     assert np.isclose(w2[0, 0, 0], 1.0 - np.exp(-0.75 / 9.0))
     assert np.all(op.taper_weights(shape, 0) == 1.0)
+
+
+def test_bicgstab_l_with_one_step_is_bicgstab():
+    """BiCGSTAB(1) and the textbook Bi-CGSTAB are the same method: equal residual histories."""
+    P = small_problem((6, 5, 7), 31, rel=0.3)
+    b = P.rhs_moment(models.EXPLOSION, (2, 2, 3))
+    _, h1, n1 = solve.bicgstab(P.apply_fft, b, 1e-11)
+    _, hl, nl = solve.bicgstab_l(P.apply_fft, b, 1e-11, 1)
+    assert len(h1) == len(hl) and nl == n1
+    # rounding differences grow along the iteration; the first dozen steps agree to 1e-9
+    assert np.allclose(hl[:12], h1[:12], rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("ell", [2, 3, 4])
+def test_bicgstab_l_reaches_lu_solution(ell):
+    P = small_problem((6, 5, 7), 31, rel=0.3)
+    b = P.rhs_moment(models.EXPLOSION, (2, 2, 3))
+    x_lu = solve.solve_dense(P.dense_A(), b)
+    x, hist, nmv = solve.bicgstab_l(P.apply_fft, b, 1e-12, ell)
+    assert hist[-1] <= 1e-12
+    # the recursively updated residual is the true one
+    assert abs(solve.relative_residual(P.apply_fft, x, b) - hist[-1]) < 1e-12
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-10
