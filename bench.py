@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--compare-c128", action="store_true",
                     help="also time the same 48 systems as sequential single-source plain c128 solves")
+    ap.add_argument("--bicgstab-l", type=int, default=1,
+                    help="Krylov method: 1 Bi-CGSTAB (the paper's), 2..4 BiCGSTAB(l)")
     ap.add_argument("--mode", choices=["bench", "apply-profile"], default="bench",
                     help="apply-profile: only a few batched applies plus a copy of known size, for counter runs")
     args = ap.parse_args()
@@ -205,7 +207,7 @@ def main():
     nrhs = len(model.sources)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx = lsvie.context_from_model(model, precision="mixed", max_rhs=nrhs)
+    ctx = lsvie.context_from_model(model, precision="mixed", max_rhs=nrhs, bicgstab_l=args.bicgstab_l)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"context set up in {setup_s:.2f} s ({ctx.device_bytes / 2**30:.2f} GiB on the device)")
@@ -317,7 +319,7 @@ def main():
         "vs_baseline": None, "dtype": "c64/f64", "data": "synthetic",
         "config": {"workload": f"{n}^3 h=8 m TTI + Gaussian random fields, 6 moment tensors x 8 frequencies "
                                f"5-40 Hz, batched mixed-precision BiCGSTAB to rel res 1e-6",
-                   "grid": n, "rhs": nrhs * len(model.omegas), "tol": model.tol},
+                   "grid": n, "rhs": nrhs * len(model.omegas), "tol": model.tol, "bicgstab_l": args.bicgstab_l},
         "time_to_solve_s": round(ms_per_step / 1e3, 3),
         "setup_s": round(setup_s, 3),
         "iterations_per_frequency": [max(i) for i in its],

@@ -68,8 +68,17 @@ typedef struct {
     int max_rhs;    /* largest batch of right-hand sides one call may carry (>= 1)         */
     int flags;      /* LS_FLAG_* bits (0: defaults)                                          */
     int taper;      /* absorbing boundary layer thickness in cells (0: off); see below        */
-    int reserved[3];
+    int bicgstab_l; /* Krylov method: 1 (or 0) Bi-CGSTAB, the paper's solver; 2..4 BiCGSTAB(l)  */
+    int reserved[2];
 } ls_options;
+
+/* ls_options.bicgstab_l = l > 1 solves with BiCGSTAB(l) (Sleijpen and Fokkema 1993): l Bi-CG steps, then a
+ * minimal-residual polynomial of degree l over the residuals those steps produced.  l = 1 is Bi-CGSTAB.  At
+ * high frequency, where Bi-CGSTAB stagnates (its degree-one minimal-residual steps cannot follow a
+ * spectrum spread around the origin), l = 4 often converges at about the same work per matvec.  The
+ * cycle's scalars are formed on the host (one round trip per inner product), so these solves are not
+ * captured in graphs.  Costs 2 l + 3 field vectors per right-hand side (and as many FP32 ones for
+ * mixed precision) instead of 6, allocated at set-up.  ls_info.iters counts Bi-CG steps (2 matvecs each). */
 
 /* ls_options.taper = d > 0 weights the total contrast (input plus background fold) of every cell within
  * d cells of a face by 1 - exp(-l^2 / (N_a h^2)) (the absorbing boundary of Eq 23-25), at set-up and

@@ -95,11 +95,13 @@ static void release(Ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
                     c->xd, c->bd, c->gs, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
-                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes};
+                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes, c->gpart};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto q : c->ghat) (void)hipFree(q);
     for (auto q : c->greal) (void)hipFree(q);
+    for (auto q : c->kry128) (void)hipFree(q);
+    for (auto q : c->kry64) (void)hipFree(q);
     for (auto q : c->ghat32) (void)hipFree(q);
     for (auto q : c->tw128) (void)hipFree(q);
     for (auto q : c->tw64) (void)hipFree(q);
@@ -267,8 +269,10 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
         for (int J = 0; J < I; ++J)
             if (std::fabs(C0[I * 6 + J] - C0[J * 6 + I]) > 1e-12 * cmax)
                 return fail(LS_ERR_ARG, "background stiffness must be symmetric");
-    ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, 0, 0, {0, 0, 0}};
+    ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, 0, 0, 1, {0, 0}};
     if (opt) o = *opt;
+    if (o.bicgstab_l == 0) o.bicgstab_l = 1;
+    if (o.bicgstab_l < 1 || o.bicgstab_l > 4) return fail(LS_ERR_ARG, "bicgstab_l must be in [1, 4] (0 means 1)");
     if (o.precision != LS_PREC_C128 && o.precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
     if (o.green_mode != LS_GREEN_EXACT && o.green_mode != LS_GREEN_PAPER_SUM && o.green_mode != LS_GREEN_ANISO)
         return fail(LS_ERR_ARG, "bad green_mode");
@@ -324,6 +328,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     c->stream = (hipStream_t)stream;
     c->flags = o.flags;
     c->taper = o.taper;
+    c->bicgstab_l = o.bicgstab_l;
     {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess) {
@@ -381,6 +386,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     A((void**)&c->state, (size_t)c->max_rhs * kStateLen * sizeof(double));
     A((void**)&c->red, 4 * kRedBlocks * sizeof(double));
     A(&c->stage, 8192);
+    if (rc == LS_OK && c->bicgstab_l > 1) rc = krylov_setup(c);
     if (rc == LS_OK) {
         const size_t hb = std::max<size_t>(4 * kRedBlocks, (size_t)c->max_rhs * kStateLen) * sizeof(double);
         if (hipHostMalloc((void**)&c->red_host, hb, hipHostMallocDefault) != hipSuccess) {

@@ -132,6 +132,9 @@ struct Ctx {
     int ints_cap = 0;
     std::vector<std::vector<double>> history;  // per right-hand side: relative residual after each iteration of the last solve
     z128 *batch_b = nullptr, *batch_x = nullptr;  // [max_rhs][3][n] right-hand sides / solutions of ls_solve_batch (allocated on its first use)
+    int bicgstab_l = 1;          // Krylov method: 1 Bi-CGSTAB (graph-captured), 2..4 BiCGSTAB(l)
+    double* gpart = nullptr;     // BiCGSTAB(l) reduction partials [max_rhs][slots][kRedBlocks]
+    std::vector<void*> kry128, kry64;  // BiCGSTAB(l) vectors beyond the six of Bi-CGSTAB, per precision
     double* red = nullptr;       // reduction results (device)
     double* red_host = nullptr;  // pinned host mirror
     long long bytes = 0;
@@ -191,6 +194,7 @@ template <typename T>
 int convolve_op(Ctx* c, int i_omega, const cpx<T>* f, cpx<T>* out, int nrhs);
 
 // solver (BiCGSTAB, mixed-precision refinement); see solver.hip
+int krylov_setup(Ctx* c);  // allocates what BiCGSTAB(l) needs beyond Bi-CGSTAB (called by ls_setup)
 int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int maxit, int precision,
                   const z128* x0, z128* u_out, ls_info* info, bool transposed = false);
 

@@ -10,8 +10,9 @@
 // the right-hand side's scalars and its active flag, so an iteration is a fixed sequence of
 // stream-ordered launches; the host only reads the flags to decide when to stop.  Reductions
 // use a fixed number of blocks and a fixed tree, so results are bitwise reproducible.
+#include <algorithm>
 #include <cmath>
-
+#include <complex>
 #include <limits>
 
 #include "common.h"
@@ -404,6 +405,11 @@ int finalize(Ctx* c, int phase, int nslots, int nrhs, double tol2 = 0.0, double*
     return LS_OK;
 }
 
+// Iterations without a 10 % gain on the best residual norm after which an FP32 inner solve stops:
+// 30 once the residual is within 1e-4 of the inner right-hand side (FP32's attainable accuracy is
+// near), 300 above that, where hard systems (high frequency, many wavelengths) cross long plateaus.
+inline int stall_window(double r2, double b2) { return r2 < 1e-8 * b2 ? 30 : 300; }
+
 // Generic BiCGSTAB.  T: vector precision, X: iterate precision (x is cpx<X>), ApplyFn(in, out).
 template <typename T, typename X, typename ApplyFn>
 int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, cpx<T>* rhat, cpx<T>* p, cpx<T>* v,
@@ -470,9 +476,8 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
         }
     }
     // FP32 inner solves stop a right-hand side whose residual has not improved on its best by 10 % for
-    // kStall iterations (its attainable accuracy is reached; the FP64 refinement restarts from the true
+    // a stall window of iterations (see stall_window; the FP64 refinement restarts from the true
     // residual).  FP64 solves run to tol or maxit.
-    constexpr int kStall = 30;
     std::vector<double> best(nrhs, std::numeric_limits<double>::infinity());
     std::vector<int> since(nrhs, 0), last_it(nrhs, 0);
     static const double zero = 0.0;
@@ -498,7 +503,7 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
                 if (sq[S_RNORM2] < 0.81 * best[q]) {  // 10 % on the norm
                     best[q] = sq[S_RNORM2];
                     since[q] = 0;
-                } else if (++since[q] >= kStall) {
+                } else if (++since[q] >= stall_window(sq[S_RNORM2], sq[S_BNORM2])) {
                     LS_HIP(hipMemcpyAsync(c->state + q * kStateLen + S_ACTIVE, &zero, sizeof(double),
                                           hipMemcpyHostToDevice, c->stream));
                     continue;
@@ -512,6 +517,460 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
     LS_HIP(hipStreamSynchronize(c->stream));
     iters.resize(nrhs);
     for (int q = 0; q < nrhs; ++q) iters[q] = (int)c->red_host[q * kStateLen + S_ITERS];
+    return LS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// BiCGSTAB(l) (Sleijpen and Fokkema): l Bi-CG steps, then the minimal-residual polynomial of degree l
+// over the residuals r_0 .. r_l the steps built (r_j = A r_{j-1}).  Per right-hand side:
+//   Bi-CG step j:  rho1 = r^H r_j;  beta = alpha rho1 / rho0;  rho0 = rho1;  u_i = r_i - beta u_i (i <= j);
+//                  u_{j+1} = A u_j;  alpha = rho0 / (r^H u_{j+1});  r_i -= alpha u_{i+1} (i <= j);
+//                  x += alpha u_0;  r_{j+1} = A r_j
+//   MR part:       gamma = argmin ||r_0 - sum_{j>=1} gamma_j r_j||, from the Gram matrix Z = R^H R
+//                  (normal equations, Cholesky on the host);  r_0 -= sum gamma_j r_j;
+//                  u_0 -= sum gamma_j u_j;  x += sum gamma_j r_{j-1};  omega = gamma_l;  next rho0 = -omega rho0.
+// The scalars of the cycle are computed on the host from deterministic device reductions (fixed
+// block count and order), one round trip per inner product, so the iteration is not captured in a
+// graph; a cycle costs 2 l matvecs and 2 l + 1 round trips.  l = 1 uses the graph-captured Bi-CGSTAB.
+
+constexpr int kMaxL = 4;
+constexpr int kGramSlots = (kMaxL + 1) * (kMaxL + 2);  // re, im of the upper triangle of Z
+constexpr int kCoef = 12;                              // per right-hand side: up to l complex + active flag
+
+template <typename T>
+struct VecSet {
+    cpx<T>* v[kMaxL + 1];
+};
+
+// nq per-thread values summed over the block in a fixed order (wavefront shuffles, then the four
+// wavefronts in order) into gp[(rr kGramSlots + q) kRedBlocks + block]
+template <int NQ>
+__device__ __forceinline__ void block_partials(const double (&a)[NQ], int nq, double* gp, int rr) {
+    __shared__ double sh[kThreads / 64][NQ];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (q >= nq) break;
+        double v = a[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) sh[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        double v = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) v += sh[w][threadIdx.x];
+        gp[((long long)rr * kGramSlots + threadIdx.x) * kRedBlocks + blockIdx.x] = v;
+    }
+}
+
+// (a^H b, ||b||^2) per right-hand side
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot_l(const cpx<T>* __restrict__ a, const cpx<T>* __restrict__ b,
+                                                    long long m, const double* __restrict__ coef, double* gp) {
+    const int rr = blockIdx.y;
+    if (coef[rr * kCoef + kCoef - 1] == 0.0) return;
+    const long long off = (long long)rr * m;
+    double acc[3] = {0.0, 0.0, 0.0};
+    LS_FOR_ELEMS(m) {
+        const cpx<double> av = wide(a[off + e]), bv = wide(b[off + e]);
+        acc[0] += av.x * bv.x + av.y * bv.y;
+        acc[1] += av.x * bv.y - av.y * bv.x;
+        acc[2] += bv.x * bv.x + bv.y * bv.y;
+    }
+    block_partials<3>(acc, 3, gp, rr);
+}
+
+// u_i = r_i - beta u_i, i <= j
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bicg_u(VecSet<T> R, VecSet<T> U, int j, long long m,
+                                                     const double* __restrict__ coef) {
+    const int rr = blockIdx.y;
+    const double* cf = coef + rr * kCoef;
+    if (cf[kCoef - 1] == 0.0) return;
+    const cpx<T> beta = {(T)cf[0], (T)cf[1]};
+    const long long off = (long long)rr * m;
+    LS_FOR_ELEMS(m) {
+        for (int i = 0; i <= j; ++i) U.v[i][off + e] = R.v[i][off + e] - beta * U.v[i][off + e];
+    }
+}
+
+// r_i -= alpha u_{i+1} (i <= j), x += alpha u_0; partials ||r_0||^2
+template <typename T, typename X>
+__global__ __launch_bounds__(kThreads) void k_bicg_r(VecSet<T> R, VecSet<T> U, int j, cpx<X>* __restrict__ x,
+                                                     long long m, const double* __restrict__ coef, double* gp) {
+    const int rr = blockIdx.y;
+    const double* cf = coef + rr * kCoef;
+    if (cf[kCoef - 1] == 0.0) return;
+    const cpx<T> alpha = {(T)cf[0], (T)cf[1]};
+    const cpx<X> alx = {(X)cf[0], (X)cf[1]};
+    const long long off = (long long)rr * m;
+    double acc[1] = {0.0};
+    LS_FOR_ELEMS(m) {
+        for (int i = 0; i <= j; ++i) {
+            const cpx<T> v = R.v[i][off + e] - alpha * U.v[i + 1][off + e];
+            R.v[i][off + e] = v;
+            if (i == 0) acc[0] += (double)v.x * v.x + (double)v.y * v.y;
+        }
+        const cpx<T> u0 = U.v[0][off + e];
+        x[off + e] = x[off + e] + alx * cpx<X>{(X)u0.x, (X)u0.y};
+    }
+    block_partials<1>(acc, 1, gp, rr);
+}
+
+// Z_ab = r_a^H r_b, a <= b <= L (row by row), as (re, im) pairs
+template <typename T, int L>
+__global__ __launch_bounds__(kThreads) void k_gram(VecSet<T> R, long long m, const double* __restrict__ coef,
+                                                   double* gp) {
+    const int rr = blockIdx.y;
+    if (coef[rr * kCoef + kCoef - 1] == 0.0) return;
+    constexpr int NQ = (L + 1) * (L + 2);
+    const long long off = (long long)rr * m;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    LS_FOR_ELEMS(m) {
+        cpx<double> v[L + 1];
+#pragma unroll
+        for (int a = 0; a <= L; ++a) v[a] = wide(R.v[a][off + e]);
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a <= L; ++a)
+#pragma unroll
+            for (int b = a; b <= L; ++b, q += 2) {
+                acc[q] += v[a].x * v[b].x + v[a].y * v[b].y;
+                acc[q + 1] += v[a].x * v[b].y - v[a].y * v[b].x;
+            }
+    }
+    block_partials<NQ>(acc, NQ, gp, rr);
+}
+
+// r_0 -= sum_j g_j r_j;  u_0 -= sum_j g_j u_j;  x += sum_j g_j r_{j-1}   (j = 1..L)
+template <typename T, typename X, int L>
+__global__ __launch_bounds__(kThreads) void k_mr(VecSet<T> R, VecSet<T> U, cpx<X>* __restrict__ x, long long m,
+                                                 const double* __restrict__ coef) {
+    const int rr = blockIdx.y;
+    const double* cf = coef + rr * kCoef;
+    if (cf[kCoef - 1] == 0.0) return;
+    cpx<T> g[L + 1];
+#pragma unroll
+    for (int j = 1; j <= L; ++j) g[j] = {(T)cf[2 * (j - 1)], (T)cf[2 * (j - 1) + 1]};
+    const long long off = (long long)rr * m;
+    LS_FOR_ELEMS(m) {
+        cpx<T> rv[L + 1];
+#pragma unroll
+        for (int a = 0; a <= L; ++a) rv[a] = R.v[a][off + e];
+        cpx<T> r0 = rv[0], u0 = U.v[0][off + e];
+        cpx<X> dx = {(X)0, (X)0};
+#pragma unroll
+        for (int j = 1; j <= L; ++j) {
+            r0 = r0 - g[j] * rv[j];
+            u0 = u0 - g[j] * U.v[j][off + e];
+            const cpx<T> t = g[j] * rv[j - 1];
+            dx = dx + cpx<X>{(X)t.x, (X)t.y};
+        }
+        R.v[0][off + e] = r0;
+        U.v[0][off + e] = u0;
+        x[off + e] = x[off + e] + dx;
+    }
+}
+
+// sums of the first nq partial slots of each right-hand side, in a fixed order -> out[rr kGramSlots + q]
+__global__ __launch_bounds__(kThreads) void k_reduce_slots(const double* __restrict__ gp, int nq,
+                                                           double* __restrict__ out) {
+    __shared__ double sh[kThreads];
+    const int rr = blockIdx.x, tid = threadIdx.x;
+    for (int q = 0; q < nq; ++q) {
+        double a = 0.0;
+        for (int k = tid; k < kRedBlocks; k += kThreads) a += gp[((long long)rr * kGramSlots + q) * kRedBlocks + k];
+        sh[tid] = a;
+        __syncthreads();
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if (tid < w) sh[tid] += sh[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) out[rr * kGramSlots + q] = sh[0];
+        __syncthreads();
+    }
+}
+
+struct LState {
+    int iters = 0, matvecs = 0;
+    int status = 0;          // 0 running / converged, 1 not converged, 2 breakdown, 3 non-finite
+    bool active = true, done = false;
+    double bnorm2 = 0, rnorm2 = 0, best = 0;
+    int since = 0;
+    std::complex<double> rho0 = 1.0, alpha = 0.0, omega = 1.0;
+};
+
+// Solve min ||r_0 - sum_{j=1..l} g_j r_j|| from Z (upper triangle, row-major pairs): Z[1:,1:] g = Z[1:,0].
+bool mr_coefficients(const double* z, int l, std::complex<double>* g) {
+    using C = std::complex<double>;
+    // entry (a, b) of the Hermitian Gram matrix from its stored upper triangle
+    auto Z = [&](int a, int b) -> C {
+        const bool lower = a > b;
+        if (lower) std::swap(a, b);
+        int q = 0;
+        for (int i = 0; i < a; ++i) q += l + 1 - i;
+        q += b - a;
+        const C v(z[2 * q], z[2 * q + 1]);
+        return lower ? std::conj(v) : v;
+    };
+    C M[kMaxL][kMaxL], rhs[kMaxL];
+    for (int a = 0; a < l; ++a) {
+        for (int b = 0; b < l; ++b) M[a][b] = Z(a + 1, b + 1);
+        rhs[a] = Z(a + 1, 0);
+    }
+    // Cholesky M = L L^H
+    C Lm[kMaxL][kMaxL] = {};
+    for (int a = 0; a < l; ++a) {
+        for (int b = 0; b <= a; ++b) {
+            C sacc = M[a][b];
+            for (int k = 0; k < b; ++k) sacc -= Lm[a][k] * std::conj(Lm[b][k]);
+            if (a == b) {
+                if (!(sacc.real() > 0.0) || !std::isfinite(sacc.real())) return false;
+                Lm[a][a] = std::sqrt(sacc.real());
+            } else {
+                Lm[a][b] = sacc / Lm[b][b].real();
+            }
+        }
+    }
+    C y[kMaxL];
+    for (int a = 0; a < l; ++a) {
+        C sacc = rhs[a];
+        for (int k = 0; k < a; ++k) sacc -= Lm[a][k] * y[k];
+        y[a] = sacc / Lm[a][a].real();
+    }
+    for (int a = l - 1; a >= 0; --a) {
+        C sacc = y[a];
+        for (int k = a + 1; k < l; ++k) sacc -= std::conj(Lm[k][a]) * g[k + 1];
+        g[a + 1] = sacc / Lm[a][a].real();
+        if (!std::isfinite(g[a + 1].real()) || !std::isfinite(g[a + 1].imag())) return false;
+    }
+    return true;
+}
+
+template <typename T, typename X, typename ApplyFn>
+int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* const* vecs, int l, int nrhs,
+               double tol, int maxit, ApplyFn apply, std::vector<LState>& st, const double* hscale = nullptr) {
+    using Cd = std::complex<double>;
+    const long long m = (long long)c->field_elems();
+    const dim3 g = vgrid(nrhs);
+    VecSet<T> R{}, U{};
+    for (int i = 0; i <= l; ++i) {
+        R.v[i] = vecs[i];
+        U.v[i] = vecs[l + 1 + i];
+    }
+    cpx<T>* rhat = vecs[2 * l + 2];
+    double* coef = c->red + 3 * kRedBlocks;
+    double* out = c->red;
+    std::vector<double> hc((size_t)nrhs * kCoef, 0.0);
+    std::vector<int> stale(nrhs, 0);
+    st.assign(nrhs, LState());
+    // r_0 = b - A x0, rhat = r_0, u_0 = 0
+    hipLaunchKernelGGL((k_init<T>), g, dim3(kThreads), 0, c->stream, b, ax0, R.v[0], rhat, U.v[0], U.v[1], m,
+                       c->partials);
+    LS_HIP(hipGetLastError());
+    int rc = finalize(c, PH_INIT, 2, nrhs, tol * tol);
+    if (rc) return rc;
+    LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * nrhs * kStateLen, hipMemcpyDeviceToHost, c->stream));
+    LS_HIP(hipStreamSynchronize(c->stream));
+    const double tol2 = tol * tol;
+    for (int q = 0; q < nrhs; ++q) {
+        st[q].bnorm2 = c->red_host[q * kStateLen + S_BNORM2];
+        st[q].rnorm2 = c->red_host[q * kStateLen + S_RNORM2];
+        st[q].best = st[q].rnorm2;
+        if (!std::isfinite(st[q].bnorm2) || !std::isfinite(st[q].rnorm2)) {
+            st[q].status = 3;
+            st[q].active = false;
+        } else if (st[q].rnorm2 <= tol2 * st[q].bnorm2) {
+            st[q].active = false;
+            st[q].done = true;
+        }
+    }
+    // hc holds the coefficients of the active systems; the last slot carries the active flag
+    auto push = [&]() -> int {
+        for (int q = 0; q < nrhs; ++q) hc[(size_t)q * kCoef + kCoef - 1] = st[q].active ? 1.0 : 0.0;
+        LS_HIP(hipMemcpyAsync(coef, hc.data(), sizeof(double) * nrhs * kCoef, hipMemcpyHostToDevice, c->stream));
+        return LS_OK;
+    };
+    auto reduce = [&](int nq) -> int {
+        hipLaunchKernelGGL(k_reduce_slots, dim3(nrhs), dim3(kThreads), 0, c->stream, c->gpart, nq, out);
+        LS_HIP(hipGetLastError());
+        LS_HIP(hipMemcpyAsync(c->red_host, out, sizeof(double) * nrhs * kGramSlots, hipMemcpyDeviceToHost, c->stream));
+        LS_HIP(hipStreamSynchronize(c->stream));
+        return LS_OK;
+    };
+    auto any_active = [&]() {
+        for (auto& q : st)
+            if (q.active) return true;
+        return false;
+    };
+    auto record = [&](int q, double r2) {
+        st[q].rnorm2 = r2;
+        stale[q] = 0;
+        if ((size_t)q < c->history.size() && st[q].bnorm2 > 0.0)
+            c->history[q].push_back(std::sqrt(r2 / st[q].bnorm2) * (hscale ? hscale[q] : 1.0));
+    };
+    // converged, non-finite, or (FP32 inner solves) no 10 % gain on the best norm for 30 checks
+    auto check = [&](int q, double r2) {
+        if (!std::isfinite(r2)) {
+            st[q].status = 3;
+            st[q].active = false;
+        } else if (r2 <= tol2 * st[q].bnorm2) {
+            st[q].active = false;
+            st[q].done = true;
+        } else if (sizeof(T) == 4) {
+            if (r2 < 0.81 * st[q].best) {
+                st[q].best = r2;
+                st[q].since = 0;
+            } else if (++st[q].since >= stall_window(r2, st[q].bnorm2)) {
+                st[q].active = false;
+            }
+        }
+    };
+    auto halt = [&](int q, bool finite) {
+        st[q].status = finite ? 2 : 3;
+        st[q].active = false;
+    };
+    bool first = true;
+    while (any_active()) {
+        for (auto& q : st)
+            if (q.active && q.iters + l > maxit) q.active = false;
+        if (!any_active()) break;
+        for (auto& q : st)
+            if (q.active) q.rho0 = -q.omega * q.rho0;
+        for (int j = 0; j < l && any_active(); ++j) {
+            // rho1 = rhat^H r_j; at j = 0 also ||r_0||^2, the residual after the last minimal-residual update
+            if ((rc = push())) return rc;
+            hipLaunchKernelGGL((k_dot_l<T>), g, dim3(kThreads), 0, c->stream, rhat, R.v[j], m, coef, c->gpart);
+            LS_HIP(hipGetLastError());
+            if ((rc = reduce(3))) return rc;
+            for (int q = 0; q < nrhs; ++q) {
+                if (!st[q].active) continue;
+                const double* o = &c->red_host[q * kGramSlots];
+                if (j == 0 && !first) {
+                    record(q, o[2]);
+                    check(q, o[2]);
+                    if (!st[q].active) continue;
+                }
+                const Cd rho1(o[0], o[1]);
+                if (!(std::abs(st[q].rho0) > 0.0) || !(std::abs(rho1) > 0.0) || !std::isfinite(std::abs(rho1))) {
+                    halt(q, std::isfinite(std::abs(rho1)));
+                    continue;
+                }
+                const Cd beta = st[q].alpha * rho1 / st[q].rho0;
+                st[q].rho0 = rho1;
+                hc[(size_t)q * kCoef] = beta.real();
+                hc[(size_t)q * kCoef + 1] = beta.imag();
+            }
+            if (!any_active()) break;
+            // u_i = r_i - beta u_i;  u_{j+1} = A u_j
+            if ((rc = push())) return rc;
+            c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+            hipLaunchKernelGGL((k_bicg_u<T>), g, dim3(kThreads), 0, c->stream, R, U, j, m, coef);
+            c->prof.end(c->stream);
+            LS_HIP(hipGetLastError());
+            if ((rc = apply(U.v[j], U.v[j + 1]))) return rc;
+            for (auto& q : st)
+                if (q.active) q.matvecs += 1;
+            // alpha = rho0 / (rhat^H u_{j+1})
+            hipLaunchKernelGGL((k_dot_l<T>), g, dim3(kThreads), 0, c->stream, rhat, U.v[j + 1], m, coef, c->gpart);
+            LS_HIP(hipGetLastError());
+            if ((rc = reduce(3))) return rc;
+            for (int q = 0; q < nrhs; ++q) {
+                if (!st[q].active) continue;
+                const double* o = &c->red_host[q * kGramSlots];
+                const Cd gam(o[0], o[1]);
+                if (!(std::abs(gam) > 0.0) || !std::isfinite(std::abs(gam))) {
+                    halt(q, std::isfinite(std::abs(gam)));
+                    continue;
+                }
+                st[q].alpha = st[q].rho0 / gam;
+                hc[(size_t)q * kCoef] = st[q].alpha.real();
+                hc[(size_t)q * kCoef + 1] = st[q].alpha.imag();
+            }
+            if (!any_active()) break;
+            // r_i -= alpha u_{i+1};  x += alpha u_0;  ||r_0||^2
+            if ((rc = push())) return rc;
+            c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+            hipLaunchKernelGGL((k_bicg_r<T, X>), g, dim3(kThreads), 0, c->stream, R, U, j, x, m, coef, c->gpart);
+            c->prof.end(c->stream);
+            LS_HIP(hipGetLastError());
+            if ((rc = reduce(1))) return rc;
+            for (int q = 0; q < nrhs; ++q) {
+                if (!st[q].active) continue;
+                const double r2 = c->red_host[q * kGramSlots];
+                st[q].iters += 1;
+                check(q, r2);
+                if (j < l - 1 || !st[q].active) record(q, r2);
+            }
+            if (!any_active()) break;
+            // r_{j+1} = A r_j
+            if ((rc = apply(R.v[j], R.v[j + 1]))) return rc;
+            for (auto& q : st)
+                if (q.active) q.matvecs += 1;
+        }
+        if (!any_active()) break;
+        // minimal-residual part: the Gram matrix of r_0 .. r_l, the normal equations on the host
+        const int nq = (l + 1) * (l + 2);
+        if ((rc = push())) return rc;
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+        switch (l) {
+            case 2: hipLaunchKernelGGL((k_gram<T, 2>), g, dim3(kThreads), 0, c->stream, R, m, coef, c->gpart); break;
+            case 3: hipLaunchKernelGGL((k_gram<T, 3>), g, dim3(kThreads), 0, c->stream, R, m, coef, c->gpart); break;
+            default: hipLaunchKernelGGL((k_gram<T, 4>), g, dim3(kThreads), 0, c->stream, R, m, coef, c->gpart); break;
+        }
+        c->prof.end(c->stream);
+        LS_HIP(hipGetLastError());
+        if ((rc = reduce(nq))) return rc;
+        for (int q = 0; q < nrhs; ++q) {
+            if (!st[q].active) continue;
+            Cd gm[kMaxL + 1];
+            if (!mr_coefficients(&c->red_host[q * kGramSlots], l, gm)) {
+                halt(q, true);
+                continue;
+            }
+            st[q].omega = gm[l];
+            for (int j = 1; j <= l; ++j) {
+                hc[(size_t)q * kCoef + 2 * (j - 1)] = gm[j].real();
+                hc[(size_t)q * kCoef + 2 * (j - 1) + 1] = gm[j].imag();
+            }
+            stale[q] = 1;
+        }
+        if (!any_active()) break;
+        if ((rc = push())) return rc;
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+        switch (l) {
+            case 2: hipLaunchKernelGGL((k_mr<T, X, 2>), g, dim3(kThreads), 0, c->stream, R, U, x, m, coef); break;
+            case 3: hipLaunchKernelGGL((k_mr<T, X, 3>), g, dim3(kThreads), 0, c->stream, R, U, x, m, coef); break;
+            default: hipLaunchKernelGGL((k_mr<T, X, 4>), g, dim3(kThreads), 0, c->stream, R, U, x, m, coef); break;
+        }
+        c->prof.end(c->stream);
+        LS_HIP(hipGetLastError());
+        first = false;
+    }
+    // systems whose last operation was a minimal-residual update: their residual norm
+    bool any_stale = false;
+    for (int q = 0; q < nrhs; ++q) {
+        const bool want = stale[q] && st[q].status == 0;
+        any_stale = any_stale || want;
+        hc[(size_t)q * kCoef + kCoef - 1] = want ? 1.0 : 0.0;
+    }
+    if (any_stale) {
+        LS_HIP(hipMemcpyAsync(coef, hc.data(), sizeof(double) * nrhs * kCoef, hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL((k_dot_l<T>), g, dim3(kThreads), 0, c->stream, rhat, R.v[0], m, coef, c->gpart);
+        LS_HIP(hipGetLastError());
+        if ((rc = reduce(3))) return rc;
+        for (int q = 0; q < nrhs; ++q)
+            if (stale[q] && st[q].status == 0) {
+                const double r2 = c->red_host[q * kGramSlots + 2];
+                record(q, r2);
+                if (!std::isfinite(r2)) st[q].status = 3;
+                else if (r2 <= tol2 * st[q].bnorm2) st[q].done = true;
+            }
+    }
+    for (auto& q : st)
+        if (!q.done && q.status == 0) q.status = 1;
     return LS_OK;
 }
 
@@ -537,7 +996,41 @@ int true_residual(Ctx* c, int i_omega, const z128* b, const z128* x, z128* ax, z
     return LS_OK;
 }
 
+// the vectors of BiCGSTAB(l) in the order r_0..r_l, u_0..u_l, rhat: the six of Bi-CGSTAB, then the extras
+template <typename T>
+std::vector<cpx<T>*> krylov_vectors(Ctx* c) {
+    std::vector<cpx<T>*> v;
+    if (sizeof(T) == 8) {
+        for (z128* p : {c->r, c->rhat, c->p, c->v, c->s, c->t}) v.push_back((cpx<T>*)p);
+        for (void* p : c->kry128) v.push_back((cpx<T>*)p);
+    } else {
+        for (z64* p : {c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32}) v.push_back((cpx<T>*)p);
+        for (void* p : c->kry64) v.push_back((cpx<T>*)p);
+    }
+    return v;
+}
+
 }  // namespace
+
+int krylov_setup(Ctx* c) {
+    const int l = c->bicgstab_l;
+    if (l < 2) return LS_OK;
+    const size_t fe = c->field_elems() * (size_t)c->max_rhs;
+    int rc = LS_OK;
+    if (!c->gpart) rc = dalloc(c, (void**)&c->gpart, (size_t)c->max_rhs * kGramSlots * kRedBlocks * sizeof(double));
+    const size_t extra = (size_t)std::max(0, 2 * l + 3 - 6);
+    while (rc == LS_OK && c->kry128.size() < extra) {
+        void* p = nullptr;
+        rc = dalloc(c, &p, fe * sizeof(z128));
+        if (rc == LS_OK) c->kry128.push_back(p);
+    }
+    while (rc == LS_OK && c->mixed && c->kry64.size() < extra) {
+        void* p = nullptr;
+        rc = dalloc(c, &p, fe * sizeof(z64));
+        if (rc == LS_OK) c->kry64.push_back(p);
+    }
+    return rc;
+}
 
 int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int maxit, int precision, const z128* x0,
                   z128* u_out, ls_info* info, bool transposed) {
@@ -555,7 +1048,31 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
     std::vector<double> rel, nrm;
     std::vector<int> iters;
     int rc = LS_OK;
-    if (precision == LS_PREC_C128) {
+    if (precision == LS_PREC_C128 && c->bicgstab_l > 1) {
+        auto apply = [&](const z128* in, z128* out) { return op_apply<double>(c, i_omega, in, out, nrhs, transposed); };
+        const std::vector<z128*> vec = krylov_vectors<double>(c);
+        const z128* ax0 = nullptr;
+        if (x0) {
+            if ((rc = apply(u_out, vec[1]))) return rc;   // r_1's vector is free until the first cycle
+            ax0 = vec[1];
+        }
+        std::vector<LState> ls;
+        rc = bicgstab_l<double, double>(c, b, u_out, ax0, vec.data(), c->bicgstab_l, nrhs, tol, maxit, apply, ls);
+        if (rc) return rc;
+        if ((rc = true_residual(c, i_omega, b, u_out, c->v, nullptr, nrhs, rel, nrm, transposed))) return rc;
+        for (int q = 0; q < nrhs; ++q) {
+            inf[q].iters = ls[q].iters;
+            inf[q].matvecs = ls[q].matvecs + (x0 ? 1 : 0) + 1;
+            inf[q].rel_res = ls[q].bnorm2 > 0 ? std::sqrt(ls[q].rnorm2 / ls[q].bnorm2) : 0.0;
+            inf[q].rel_res_true = rel[q];
+            if (ls[q].status == 3 || !std::isfinite(rel[q]))
+                inf[q].status = LS_ERR_NONFINITE;
+            else if (ls[q].status == 2)
+                inf[q].status = LS_ERR_BREAKDOWN;
+            else if (ls[q].status == 1)
+                inf[q].status = LS_ERR_NOT_CONVERGED;
+        }
+    } else if (precision == LS_PREC_C128) {
         auto apply = [&](const z128* in, z128* out) { return op_apply<double>(c, i_omega, in, out, nrhs, transposed); };
         // A breakdown (rho = 0 or rhat^H v = 0) restarts once from the current iterate, which re-seeds the
         // shadow residual with the current residual; systems already within tol take no further iteration.
@@ -598,10 +1115,12 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
         }
     } else {
         if (!c->mixed) return fail(LS_ERR_STATE, "mixed precision needs a context built with LS_PREC_MIXED");
-        // outer FP64 refinement: r = b - A x (FP64), inner FP32 BiCGSTAB on A d = r / ||r||
+        // outer FP64 refinement: r = b - A x (FP64), inner FP32 BiCGSTAB on A d = r / ||r||.  A correction
+        // that does not lower the FP64 true residual is taken back and ends that system's refinement (the
+        // iterate stays the best one found); one that lowers it by less than 10 % is kept and ends it too.
         const int max_outer = 30;
-        std::vector<double> scale(nrhs), inv(nrhs);
-        std::vector<int> active(nrhs, 1);
+        std::vector<double> scale(nrhs), inv(nrhs), prev(nrhs, 0.0), undo(nrhs, 0.0);
+        std::vector<int> active(nrhs, 1), stopped(nrhs, 0);
         int outer = 0;
         double* dscale = c->red + 2 * kRedBlocks;
         for (; outer <= max_outer; ++outer) {
@@ -619,12 +1138,34 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 nrm.assign(c->red_host + kRedBlocks, c->red_host + kRedBlocks + nrhs);
             } else {
                 if ((rc = true_residual(c, i_omega, b, u_out, c->v, c->r, nrhs, rel, nrm, transposed))) return rc;
-                for (int q = 0; q < nrhs; ++q) inf[q].matvecs += 1;
+                bool any_undo = false;
+                for (int q = 0; q < nrhs; ++q) {
+                    inf[q].matvecs += 1;
+                    undo[q] = 0.0;
+                    if (outer == 0 || !active[q] || !std::isfinite(rel[q])) continue;
+                    if (!(rel[q] < prev[q])) {
+                        undo[q] = -inv[q];
+                        any_undo = true;
+                        rel[q] = prev[q];
+                        stopped[q] = 1;
+                    } else if (rel[q] > 0.9 * prev[q]) {
+                        stopped[q] = 1;
+                    }
+                }
+                if (any_undo) {
+                    // x -= d for the systems whose last correction raised the true residual (x32 still holds d)
+                    LS_HIP(hipMemcpyAsync(dscale, undo.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice,
+                                          c->stream));
+                    hipLaunchKernelGGL(k_add32, vgrid(nrhs), dim3(kThreads), 0, c->stream, u_out, c->x32, m, dscale);
+                    LS_HIP(hipGetLastError());
+                    LS_HIP(hipStreamSynchronize(c->stream));
+                }
             }
             bool any = false;
             double worst = 0.0;
             for (int q = 0; q < nrhs; ++q) {
-                active[q] = rel[q] > tol && std::isfinite(rel[q]) && nrm[q] > 0.0;
+                prev[q] = rel[q];
+                active[q] = !stopped[q] && rel[q] > tol && std::isfinite(rel[q]) && nrm[q] > 0.0;
                 any = any || active[q];
                 if (active[q]) worst = std::max(worst, rel[q]);
             }
@@ -642,15 +1183,28 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
             auto apply32 = [&](const z64* in, z64* out) {
                 return op_apply<float>(c, i_omega, in, out, nrhs, transposed);
             };
-            rc = bicgstab<float, float>(c, c->b32, c->x32, nullptr, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32,
-                                        nrhs, eta, maxit, apply32, iters, rel.data());
-            if (rc) return rc;
-            for (int q = 0; q < nrhs; ++q) {
-                if (!active[q]) continue;
-                const double* sq = &c->red_host[(size_t)q * kStateLen];
-                const bool half = sq[S_DONE] == 1.0 && sq[S_SNORM2] == sq[S_RNORM2];
-                inf[q].iters += iters[q];
-                inf[q].matvecs += 2 * iters[q] - (half ? 1 : 0);
+            if (c->bicgstab_l > 1) {
+                const std::vector<z64*> vec = krylov_vectors<float>(c);
+                std::vector<LState> ls;
+                rc = bicgstab_l<float, float>(c, c->b32, c->x32, nullptr, vec.data(), c->bicgstab_l, nrhs, eta, maxit,
+                                              apply32, ls, rel.data());
+                if (rc) return rc;
+                for (int q = 0; q < nrhs; ++q) {
+                    if (!active[q]) continue;
+                    inf[q].iters += ls[q].iters;
+                    inf[q].matvecs += ls[q].matvecs;
+                }
+            } else {
+                rc = bicgstab<float, float>(c, c->b32, c->x32, nullptr, c->r32, c->rhat32, c->p32, c->v32, c->s32,
+                                            c->t32, nrhs, eta, maxit, apply32, iters, rel.data());
+                if (rc) return rc;
+                for (int q = 0; q < nrhs; ++q) {
+                    if (!active[q]) continue;
+                    const double* sq = &c->red_host[(size_t)q * kStateLen];
+                    const bool half = sq[S_DONE] == 1.0 && sq[S_SNORM2] == sq[S_RNORM2];
+                    inf[q].iters += iters[q];
+                    inf[q].matvecs += 2 * iters[q] - (half ? 1 : 0);
+                }
             }
             LS_HIP(hipMemcpyAsync(dscale, inv.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
             hipLaunchKernelGGL(k_add32, vgrid(nrhs), dim3(kThreads), 0, c->stream, u_out, c->x32, m, dscale);

@@ -59,7 +59,8 @@ class Grid(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("green_mode", ctypes.c_int), ("max_rhs", ctypes.c_int),
-                ("flags", ctypes.c_int), ("taper", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("flags", ctypes.c_int), ("taper", ctypes.c_int), ("bicgstab_l", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class Info(ctypes.Structure):
@@ -172,11 +173,12 @@ def check_buffer(t, shape, dtype, device, name="out"):
 # C-named entry points (torch tensors in, plain pointers to the library)
 
 def ls_setup(shape, h, C0, rho0, dC, drho, omegas, precision=LS_PREC_C128, green_mode=LS_GREEN_EXACT,
-             max_rhs=1, stream=None, flags=0, taper=0):
+             max_rhs=1, stream=None, flags=0, taper=0, bicgstab_l=1):
     """dC, drho: contiguous float64 CUDA tensors [21, N3, N2, N1] and [N3, N2, N1]; returns a handle."""
     lib = load()
     g = Grid((ctypes.c_int * 3)(*[int(v) for v in shape]), float(h))
-    opt = Options(int(precision), int(green_mode), int(max_rhs), int(flags), int(taper), (ctypes.c_int * 3)())
+    opt = Options(int(precision), int(green_mode), int(max_rhs), int(flags), int(taper), int(bicgstab_l),
+                  (ctypes.c_int * 2)())
     c0, c0p = _dbl(C0, 36)
     om, omp = _dbl(omegas, len(np.atleast_1d(omegas)))
     out = ctypes.c_void_p()
@@ -363,7 +365,7 @@ class Context:
     """One grid + medium + frequency set on one GPU (owns the library context)."""
 
     def __init__(self, shape, h, C0, rho0, dc21, drho, omegas, precision="c128", green_mode="exact", max_rhs=1,
-                 device="cuda:0", graphs=True, autotune=False, taper=0):
+                 device="cuda:0", graphs=True, autotune=False, taper=0, bicgstab_l=1):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the LS library runs only on the GPU")
@@ -384,7 +386,7 @@ class Context:
                                GREEN_MODES[green_mode], max_rhs,
                                self.stream.cuda_stream,
                                (0 if graphs else LS_FLAG_NO_GRAPH) | (LS_FLAG_AUTOTUNE if autotune else 0),
-                               int(taper))
+                               int(taper), int(bicgstab_l))
         del dc, dr
 
     def close(self):
@@ -594,7 +596,8 @@ def solve_batch(contexts, jobs, tol=1e-8, maxit=2000, precision="c128", raise_on
 
 
 def context_from_model(model, precision="c128", max_rhs=1, green_mode="exact", device="cuda:0", omegas=None,
-                       graphs=True, autotune=False, taper=0):
+                       graphs=True, autotune=False, taper=0, bicgstab_l=1):
     return Context(model.shape, model.h, model.C0, model.rho0, model.dc21, model.drho,
                    model.omegas if omegas is None else omegas, precision=precision, green_mode=green_mode,
-                   max_rhs=max_rhs, device=device, graphs=graphs, autotune=autotune, taper=taper)
+                   max_rhs=max_rhs, device=device, graphs=graphs, autotune=autotune, taper=taper,
+                   bicgstab_l=bicgstab_l)
