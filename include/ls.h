@@ -46,7 +46,7 @@ enum {
     LS_ERR_OOM = -2,            /* device allocation failed                                */
     LS_ERR_HIP = -3,            /* a HIP runtime call failed                               */
     LS_ERR_BREAKDOWN = -4,      /* BiCGSTAB breakdown (rho, r^H v or t^H t vanished)       */
-    LS_ERR_NOT_CONVERGED = -5,  /* maxit reached; the output holds the last iterate        */
+    LS_ERR_NOT_CONVERGED = -5,  /* maxit reached; the output holds the best iterate found  */
     LS_ERR_NONFINITE = -6,      /* NaN or Inf met in the residual                          */
     LS_ERR_STATE = -7           /* the context was not built for the requested precision   */
 };

@@ -95,7 +95,7 @@ static void release(Ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
                     c->xd, c->bd, c->gs, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
-                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes, c->gpart};
+                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes, c->gpart, c->xbest};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto q : c->ghat) (void)hipFree(q);
@@ -377,6 +377,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     z128** v128[] = {&c->r, &c->rhat, &c->p, &c->v, &c->s, &c->t};
     for (auto pp : v128) A((void**)pp, fe * sizeof(z128));
     A((void**)&c->bd, 3 * n * sizeof(z128));
+    A((void**)&c->xbest, fe * sizeof(z128));
     A(&c->gs, fe * sizeof(z128));
     if (c->mixed) {
         z64** v64[] = {&c->r32, &c->rhat32, &c->p32, &c->v32, &c->s32, &c->t32, &c->x32, &c->b32};

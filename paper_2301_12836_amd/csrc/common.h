@@ -121,6 +121,7 @@ struct Ctx {
     // Krylov vectors, c128 [max_rhs][3][ncell] each
     z128 *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
     z128 *xd = nullptr, *bd = nullptr;           // FP64 iterate / rhs copies for refinement
+    z128* xbest = nullptr;       // best iterate of the FP64 solves [max_rhs][3][ncell]
     void* gs = nullptr;          // Gconv y scratch of the transposed operator [max_rhs][3][ncell] (c128 size)
     // c64 Krylov vectors for the inner solve of the mixed path
     z64 *r32 = nullptr, *rhat32 = nullptr, *p32 = nullptr, *v32 = nullptr, *s32 = nullptr, *t32 = nullptr,

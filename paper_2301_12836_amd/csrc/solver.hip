@@ -405,6 +405,25 @@ int finalize(Ctx* c, int phase, int nslots, int nrhs, double tol2 = 0.0, double*
     return LS_OK;
 }
 
+// The iterate with the smallest recursive residual seen, saved whenever that residual halves (so at most
+// about log2(1/tol) copies per system): a solve that stops short of tol returns it, not its last iterate.
+struct BestIterate {
+    z128* x = nullptr;           // [nrhs][3 ncell]
+    std::vector<double> r2;      // residual norm^2 of the saved iterate, per system
+    int save(Ctx* c, const z128* from, int q, long long m) {
+        hipLaunchKernelGGL(k_copy, dim3(kRedBlocks, 1), dim3(kThreads), 0, c->stream, from + (long long)q * m,
+                           x + (long long)q * m, m);
+        LS_HIP(hipGetLastError());
+        return LS_OK;
+    }
+    int restore(Ctx* c, z128* to, int q, long long m) {
+        hipLaunchKernelGGL(k_copy, dim3(kRedBlocks, 1), dim3(kThreads), 0, c->stream, (const z128*)x + (long long)q * m,
+                           to + (long long)q * m, m);
+        LS_HIP(hipGetLastError());
+        return LS_OK;
+    }
+};
+
 // Iterations without a 10 % gain on the best residual norm after which an FP32 inner solve stops:
 // 30 once the residual is within 1e-4 of the inner right-hand side (FP32's attainable accuracy is
 // near), 300 above that, where hard systems (high frequency, many wavelengths) cross long plateaus.
@@ -414,13 +433,24 @@ inline int stall_window(double r2, double b2) { return r2 < 1e-8 * b2 ? 30 : 300
 template <typename T, typename X, typename ApplyFn>
 int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, cpx<T>* rhat, cpx<T>* p, cpx<T>* v,
              cpx<T>* s, cpx<T>* t, int nrhs, double tol, int maxit, ApplyFn apply, std::vector<int>& iters,
-             const double* hscale = nullptr) {
+             const double* hscale = nullptr, BestIterate* keep = nullptr) {
     const long long m = (long long)c->field_elems();
     const dim3 g = vgrid(nrhs);
     hipLaunchKernelGGL((k_init<T>), g, dim3(kThreads), 0, c->stream, b, ax0, r, rhat, p, v, m, c->partials);
     LS_HIP(hipGetLastError());
     int rc = finalize(c, PH_INIT, 2, nrhs, tol * tol);
     if (rc) return rc;
+    if constexpr (sizeof(X) == 8) {
+        if (keep && keep->r2.empty()) {
+            LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * nrhs * kStateLen, hipMemcpyDeviceToHost,
+                                  c->stream));
+            LS_HIP(hipStreamSynchronize(c->stream));
+            keep->r2.resize(nrhs);
+            for (int q = 0; q < nrhs; ++q) keep->r2[q] = c->red_host[q * kStateLen + S_RNORM2];
+            hipLaunchKernelGGL(k_copy, g, dim3(kThreads), 0, c->stream, (const z128*)x, keep->x, m);
+            LS_HIP(hipGetLastError());
+        }
+    }
     // One iteration is a fixed sequence of launches whose scalars live on the device, so it is
     // captured once into a graph and replayed; the host only reads the active flags in between.
     auto body = [&]() -> int {
@@ -497,6 +527,12 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
             if ((int)sq[S_ITERS] > last_it[q] && sq[S_BNORM2] > 0.0 && (size_t)q < c->history.size()) {
                 last_it[q] = (int)sq[S_ITERS];
                 c->history[q].push_back(std::sqrt(sq[S_RNORM2] / sq[S_BNORM2]) * (hscale ? hscale[q] : 1.0));
+            }
+            if constexpr (sizeof(X) == 8) {
+                if (keep && sq[S_DONE] != 1.0 && sq[S_RNORM2] < 0.25 * keep->r2[q]) {
+                    keep->r2[q] = sq[S_RNORM2];
+                    if ((rc = keep->save(c, (const z128*)x, q, m))) return rc;
+                }
             }
             if (sq[S_ACTIVE] == 0.0) continue;
             if (sizeof(T) == 4) {
@@ -751,7 +787,8 @@ bool mr_coefficients(const double* z, int l, std::complex<double>* g) {
 
 template <typename T, typename X, typename ApplyFn>
 int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* const* vecs, int l, int nrhs,
-               double tol, int maxit, ApplyFn apply, std::vector<LState>& st, const double* hscale = nullptr) {
+               double tol, int maxit, ApplyFn apply, std::vector<LState>& st, const double* hscale = nullptr,
+               BestIterate* best = nullptr) {
     using Cd = std::complex<double>;
     const long long m = (long long)c->field_elems();
     const dim3 g = vgrid(nrhs);
@@ -775,6 +812,14 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
     LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * nrhs * kStateLen, hipMemcpyDeviceToHost, c->stream));
     LS_HIP(hipStreamSynchronize(c->stream));
     const double tol2 = tol * tol;
+    if constexpr (sizeof(X) == 8) {
+        if (best) {
+            best->r2.resize(nrhs);
+            for (int q = 0; q < nrhs; ++q) best->r2[q] = c->red_host[q * kStateLen + S_RNORM2];
+            hipLaunchKernelGGL(k_copy, g, dim3(kThreads), 0, c->stream, (const z128*)x, best->x, m);
+            LS_HIP(hipGetLastError());
+        }
+    }
     for (int q = 0; q < nrhs; ++q) {
         st[q].bnorm2 = c->red_host[q * kStateLen + S_BNORM2];
         st[q].rnorm2 = c->red_host[q * kStateLen + S_RNORM2];
@@ -805,9 +850,16 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
             if (q.active) return true;
         return false;
     };
+    int save_rc = LS_OK;
     auto record = [&](int q, double r2) {
         st[q].rnorm2 = r2;
         stale[q] = 0;
+        if constexpr (sizeof(X) == 8) {
+            if (best && r2 < 0.25 * best->r2[q] && !(r2 <= tol2 * st[q].bnorm2)) {
+                best->r2[q] = r2;
+                if (save_rc == LS_OK) save_rc = best->save(c, (const z128*)x, q, m);
+            }
+        }
         if ((size_t)q < c->history.size() && st[q].bnorm2 > 0.0)
             c->history[q].push_back(std::sqrt(r2 / st[q].bnorm2) * (hscale ? hscale[q] : 1.0));
     };
@@ -971,7 +1023,7 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
     }
     for (auto& q : st)
         if (!q.done && q.status == 0) q.status = 1;
-    return LS_OK;
+    return save_rc;
 }
 
 // ||b - A x|| / ||b|| per system with the FP64 operator; writes r = b - A x if r != null.
@@ -1057,8 +1109,15 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
             ax0 = vec[1];
         }
         std::vector<LState> ls;
-        rc = bicgstab_l<double, double>(c, b, u_out, ax0, vec.data(), c->bicgstab_l, nrhs, tol, maxit, apply, ls);
+        BestIterate best{c->xbest, {}};
+        rc = bicgstab_l<double, double>(c, b, u_out, ax0, vec.data(), c->bicgstab_l, nrhs, tol, maxit, apply, ls,
+                                        nullptr, &best);
         if (rc) return rc;
+        for (int q = 0; q < nrhs; ++q)
+            if (ls[q].status == 1 && best.r2[q] < ls[q].rnorm2) {
+                if ((rc = best.restore(c, u_out, q, m))) return rc;
+                ls[q].rnorm2 = best.r2[q];
+            }
         if ((rc = true_residual(c, i_omega, b, u_out, c->v, nullptr, nrhs, rel, nrm, transposed))) return rc;
         for (int q = 0; q < nrhs; ++q) {
             inf[q].iters = ls[q].iters;
@@ -1078,6 +1137,7 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
         // shadow residual with the current residual; systems already within tol take no further iteration.
         std::vector<double> st;
         std::vector<int> total(nrhs, 0), extra(nrhs, 0);
+        BestIterate best{c->xbest, {}};
         for (int attempt = 0; attempt < 2; ++attempt) {
             const z128* ax0 = nullptr;
             if (x0 || attempt > 0) {
@@ -1086,7 +1146,7 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 for (int q = 0; q < nrhs; ++q) extra[q] += 1;
             }
             rc = bicgstab<double, double>(c, b, u_out, ax0, c->r, c->rhat, c->p, c->v, c->s, c->t, nrhs, tol, maxit,
-                                          apply, iters);
+                                          apply, iters, nullptr, &best);
             if (rc) return rc;
             st.assign(c->red_host, c->red_host + (size_t)nrhs * kStateLen);
             bool broke = false;
@@ -1098,6 +1158,14 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 broke = broke || sq[S_FLAG] == 2.0;
             }
             if (!broke) break;
+        }
+        // a system that stopped short of tol returns its best iterate
+        for (int q = 0; q < nrhs; ++q) {
+            double* sq = &st[(size_t)q * kStateLen];
+            if (sq[S_DONE] != 1.0 && sq[S_FLAG] != 3.0 && best.r2[q] < sq[S_RNORM2]) {
+                if ((rc = best.restore(c, u_out, q, m))) return rc;
+                sq[S_RNORM2] = best.r2[q];
+            }
         }
         if ((rc = true_residual(c, i_omega, b, u_out, c->v, nullptr, nrhs, rel, nrm, transposed))) return rc;
         for (int q = 0; q < nrhs; ++q) {

@@ -78,7 +78,7 @@ def test_gradients_match_oracle_dense_adjoint():
     obs = torch.tensor(np.array(data), dtype=torch.complex128, device=ctx.device)
     L = adjoint.misfit(dc, dr, M, setup, obs)
     L.backward()
-    print("J", float(L), J, "g21", rel(to_np(dc.grad), g21), "grho", rel(to_np(dr.grad), grho),
+    print("J", float(L.detach()), J, "g21", rel(to_np(dc.grad), g21), "grho", rel(to_np(dr.grad), grho),
           "gM", rel(to_np(M.grad), gM), flush=True)
     assert abs(float(L) - J) < 1e-9 * J
     assert rel(to_np(dc.grad), g21) < 1e-8

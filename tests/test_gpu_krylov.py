@@ -104,3 +104,21 @@ def test_initial_guess_and_failure_codes():
     ctx.close()
     with pytest.raises(lsvie.LsError):
         lsvie.context_from_model(m, omegas=[W15], bicgstab_l=5)
+
+
+@pytest.mark.parametrize("ell", [1, 4])
+def test_unconverged_solve_returns_its_best_iterate(ell):
+    """A solve stopped by maxit returns the iterate with (within a factor 2) the smallest residual seen,
+    never a worse last iterate: the saved copy is refreshed whenever the residual halves."""
+    m, P = hard_problem()
+    ctx = lsvie.context_from_model(m, omegas=[W15], bicgstab_l=ell)
+    b = ctx.rhs_moment(models.EXPLOSION, (2, 2, 3))
+    for maxit in (4, 8, 12):   # whole BiCGSTAB(4) cycles
+        u, info = ctx.solve(b, tol=1e-14, maxit=maxit, precision="c128", raise_on_error=False)
+        h = np.array(ctx.residual_history(0))
+        assert info[0]["status"] == lsvie.LS_ERR_NOT_CONVERGED
+        true = info[0]["rel_res_true"]
+        print("l", ell, "maxit", maxit, "history", h, "returned", true, flush=True)
+        assert true <= 2.0 * (1 + 1e-6) * min(h.min(), 1.0)
+        assert true <= h[-1] * (1 + 1e-6)
+    ctx.close()
