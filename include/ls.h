@@ -96,12 +96,14 @@ typedef struct {
  *          + i/(8 pi^2) int_{n.x > 0} sum_m P_m k_m / lambda_m e^{i k_m n.x} dS(n),
  * and the zero-offset cell takes the integral over the sphere of volume h^3,
  *     1/(4 pi) int sum_m P_m I(k_m) / lambda_m dS,  I(k) = int_0^R r e^{i k r} dr,  R = (3/(4 pi))^{1/3} h
- * (for an isotropic C0 both equal the LS_GREEN_EXACT table).  Requirements, checked at set-up
- * (LS_ERR_ARG otherwise): C0 has the three coordinate mirror planes (orthorhombic, VTI or isotropic in
- * the grid axes: C14..C16, C24..C26, C34..C36, C45, C46, C56 zero), is positive definite, its quasi-P
- * eigenvalue stays at least 5 % above the quasi-S ones in every direction, and the largest phase
- * w r / v_min over the grid is at most 1600 rad.  Nothing is folded into the contrast.  The table is
- * computed once per frequency at set-up (FP64 quadrature on the device, seconds at 256^3). */
+ * (for an isotropic C0 both equal the LS_GREEN_EXACT table).  Any stiffness is accepted: one with the
+ * three coordinate mirror planes (orthorhombic, VTI or isotropic in the grid axes: C14..C16, C24..C26,
+ * C34..C36, C45, C46, C56 zero) keeps the octant k-space table, any other (tilted media) uses a table
+ * over the half-space k_x <= L1/2 (4 times the memory and table traffic).  Checked at set-up (LS_ERR_ARG
+ * otherwise): C0 is positive definite, its quasi-P eigenvalue stays at least 5 % above the quasi-S ones
+ * in every direction, and the largest phase w r / v_min over the grid is at most 1600 rad.  Nothing is
+ * folded into the contrast.  The table is computed once per frequency at set-up (FP64 quadrature on the
+ * device: about 1.3 s per frequency for a tilted background at 128^3). */
 
 /* ls_options.flags:
  *   LS_FLAG_NO_GRAPH  run every BiCGSTAB iteration as separate launches instead of replaying one

@@ -276,13 +276,16 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     if (o.precision != LS_PREC_C128 && o.precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
     if (o.green_mode != LS_GREEN_EXACT && o.green_mode != LS_GREEN_PAPER_SUM && o.green_mode != LS_GREEN_ANISO)
         return fail(LS_ERR_ARG, "bad green_mode");
+    // LS_GREEN_ANISO: a background with the three coordinate mirror planes (no coupling of normal and shear
+    // strains or of different shears) keeps the octant table; any other takes the half-space table
+    // (LS_GREEN_TABLE=half in the environment forces the half-space table, a test hook)
+    bool half = false;
     if (o.green_mode == LS_GREEN_ANISO) {
-        // the three coordinate mirror planes: no coupling of normal and shear strains or of different shears
         for (int I = 0; I < 6; ++I)
             for (int J = I + 1; J < 6; ++J)
-                if ((J >= 3) && std::fabs(C0[I * 6 + J]) > 1e-12 * cmax)
-                    return fail(LS_ERR_ARG, "LS_GREEN_ANISO needs a background with the three coordinate mirror "
-                                            "planes (C14..C16, C24..C26, C34..C36, C45, C46, C56 zero)");
+                if (J >= 3 && std::fabs(C0[I * 6 + J]) > 1e-12 * cmax) half = true;
+        const char* e = std::getenv("LS_GREEN_TABLE");
+        if (e && std::strcmp(e, "half") == 0) half = true;
     }
     if (o.max_rhs < 1 || o.max_rhs > 64) return fail(LS_ERR_ARG, "max_rhs must be in [1, 64]");
     if (o.taper < 0 || 2 * o.taper > std::min(grid->n[0], std::min(grid->n[1], grid->n[2])))
@@ -319,6 +322,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     c->h = grid->h;
     c->mixed = o.precision == LS_PREC_MIXED;
     c->green_mode = o.green_mode;
+    c->green_half = half;
     c->max_rhs = o.max_rhs;
     c->rho0 = rho0;
     std::copy(C0, C0 + 36, c->C0);
@@ -351,7 +355,8 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
 
     const size_t n = (size_t)c->ncell;
     const size_t fe = 3 * n * (size_t)c->max_rhs;  // field elements of a batch
-    const size_t oct = (size_t)(c->L1 / 2 + 1) * (c->L2 / 2 + 1) * (c->L3 / 2 + 1);
+    const size_t oct = c->green_half ? (size_t)(c->L1 / 2 + 1) * c->L2 * c->L3
+                                     : (size_t)(c->L1 / 2 + 1) * (c->L2 / 2 + 1) * (c->L3 / 2 + 1);
     int rc = LS_OK;
     auto A = [&](void** p, size_t bytes) {
         if (rc == LS_OK) rc = dalloc(c, p, bytes);
@@ -370,7 +375,8 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     }
     if (c->green_mode == LS_GREEN_ANISO) {
         c->greal.assign(n_omega, nullptr);
-        for (int i = 0; i < n_omega; ++i) A((void**)&c->greal[i], 6 * n * sizeof(z128));
+        const size_t nreal = c->green_half ? (size_t)c->n1 * (2 * c->n2 - 1) * (2 * c->n3 - 1) : n;
+        for (int i = 0; i < n_omega; ++i) A((void**)&c->greal[i], 6 * nreal * sizeof(z128));
     }
     A(&c->work, (size_t)c->max_rhs * 3 * c->n3 * c->L2 * c->L1 * sizeof(z128));
     if (!use_fused_contrast()) A(&c->tau, (size_t)c->max_rhs * 6 * n * sizeof(z128));  // split contrast only

@@ -81,6 +81,8 @@ struct Ctx {
     double h = 0;
     int mixed = 0;
     int green_mode = LS_GREEN_EXACT;
+    bool green_half = false;      // k-space table over the half-space k_x <= L1/2 (backgrounds without the
+                                  // three coordinate mirror planes) instead of the octant
     int max_rhs = 1;
     double rho0 = 0, alpha = 0, beta = 0;
     double fold21[21] = {0};      // C0 - C_iso, packed, added to every cell's contrast (zero for LS_GREEN_ANISO)
@@ -103,10 +105,12 @@ struct Ctx {
     float* dc32 = nullptr;
     float* drho32 = nullptr;
 
-    // k-space Green's tables per frequency: octant [L3/2+1][L2/2+1][L1/2+1][6], already scaled by
-    // 1/(L1 L2 L3) so the inverse FFT needs no normalisation
+    // k-space Green's tables per frequency: octant [L3/2+1][L2/2+1][L1/2+1][6] (half-space
+    // [L3][L2][L1/2+1][6] when green_half), already scaled by 1/(L1 L2 L3) so the inverse FFT needs no
+    // normalisation
     std::vector<z128*> ghat;
     std::vector<z128*> greal;     // LS_GREEN_ANISO: h^3 G at the offsets of one octant, [N3][N2][N1][6] per frequency
+                                  // (half-space: [2 N3 - 1][2 N2 - 1][N1][6])
     std::vector<z64*> ghat32;
     double* gl_nodes = nullptr;   // LS_GREEN_ANISO: Gauss-Legendre nodes and weights on [0, 1] (device)
 

@@ -133,7 +133,9 @@ __device__ __forceinline__ void load_g6(const z128* __restrict__ ghat, long long
 // Fused z pass: forward z FFT of the three components, v^ = G^(k) f^, inverse z FFT.
 // G^ holds the octant [L3/2+1][L2/2+1][L1/2+1][6] (Voigt order 11,22,33,23,13,12); under
 // k_a -> L_a - k_a an off-diagonal component ij changes sign once for each of i, j equal to a.
-template <typename T, int L, int TX>
+// HALF: G^ holds the half-space [L3][L2][L1/2+1][6] (backgrounds without the mirror planes) and
+// k_x > L1/2 reads the entry at -k (G^ is even), with no sign change.
+template <typename T, int L, int TX, bool HALF = false>
 __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1, int L2,
                                                          long long CS, long long RS, long long ES, int n3,
                                                          const cpx<T>* __restrict__ ghat,
@@ -161,15 +163,20 @@ __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ da
     for (int idx = tid; idx < L * TX; idx += kThreads) {
         const int t = idx % TX, kz0 = idx / TX;
         const int kx0 = x0 + t;
-        const bool fx = kx0 > L1 / 2, fz = kz0 > L / 2;
-        const int kx = fx ? L1 - kx0 : kx0, kz = fz ? L - kz0 : kz0;
         cpx<T> g[6];
-        load_g6(ghat, ((long long)kz * O2 + ky) * O1 + kx, g);
-        const cpx<T> g11 = g[0], g22 = g[1], g33 = g[2];
-        cpx<T> g23 = g[3], g13 = g[4], g12 = g[5];
-        if (fy != fz) g23 = T(-1) * g23;
-        if (fx != fz) g13 = T(-1) * g13;
-        if (fx != fy) g12 = T(-1) * g12;
+        if constexpr (HALF) {
+            const bool neg = kx0 > L1 / 2;
+            const int hx = neg ? L1 - kx0 : kx0, hy = neg ? (L2 - y) % L2 : y, hz = neg ? (L - kz0) % L : kz0;
+            load_g6(ghat, ((long long)hz * L2 + hy) * O1 + hx, g);
+        } else {
+            const bool fx = kx0 > L1 / 2, fz = kz0 > L / 2;
+            const int kx = fx ? L1 - kx0 : kx0, kz = fz ? L - kz0 : kz0;
+            load_g6(ghat, ((long long)kz * O2 + ky) * O1 + kx, g);
+            if (fy != fz) g[3] = T(-1) * g[3];
+            if (fx != fz) g[4] = T(-1) * g[4];
+            if (fx != fy) g[5] = T(-1) * g[5];
+        }
+        const cpx<T> g11 = g[0], g22 = g[1], g33 = g[2], g23 = g[3], g13 = g[4], g12 = g[5];
         cpx<T>* row = s + kz0 * NL + t;
         const cpx<T> f1 = row[0], f2 = row[TX], f3 = row[2 * TX];
         row[0] = g11 * f1 + g12 * f2 + g13 * f3;
@@ -327,7 +334,7 @@ __device__ __forceinline__ void fold_index(int k, int L, int& kf, bool& flipped)
 // Fused z pass with the four-step FFT: three components per column held in registers.  Logical
 // block order (XCD-aware): right-hand side fastest, then x tiles and y rows in mirror pairs, so the
 // blocks that read the same octant rows of G^ run together on one XCD.  The data occupy z < n3 <= L/2.
-template <typename T, int L, int TX>
+template <typename T, int L, int TX, bool HALF = false>
 __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
                                                                     int n3, const cpx<T>* __restrict__ ghat,
@@ -363,18 +370,26 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void 
     bool fx, fy;
     fold_index(kx0, L1, kx, fx);
     fold_index(y, L2, ky, fy);
+    // half-space table: k_x > L1/2 reads the entry at -k
+    const bool hneg = kx0 > L1 / 2;
+    const int hx = hneg ? L1 - kx0 : kx0, hy = hneg ? (L2 - y) % L2 : y;
 #pragma unroll
     for (int i = 0; i < F::N2; ++i) {
-        int kz;
-        bool fz;
-        fold_index(spectral_index<L>(q, i), L, kz, fz);
         cpx<T> g[6];
-        load_g6(ghat, ((long long)kz * O2 + ky) * O1 + kx, g);
-        const cpx<T> g11 = g[0], g22 = g[1], g33 = g[2];
-        cpx<T> g23 = g[3], g13 = g[4], g12 = g[5];
-        if (fy != fz) g23 = T(-1) * g23;
-        if (fx != fz) g13 = T(-1) * g13;
-        if (fx != fy) g12 = T(-1) * g12;
+        if constexpr (HALF) {
+            const int kz0 = spectral_index<L>(q, i);
+            const int hz = hneg ? (L - kz0) % L : kz0;
+            load_g6(ghat, ((long long)hz * L2 + hy) * O1 + hx, g);
+        } else {
+            int kz;
+            bool fz;
+            fold_index(spectral_index<L>(q, i), L, kz, fz);
+            load_g6(ghat, ((long long)kz * O2 + ky) * O1 + kx, g);
+            if (fy != fz) g[3] = T(-1) * g[3];
+            if (fx != fz) g[4] = T(-1) * g[4];
+            if (fx != fy) g[5] = T(-1) * g[5];
+        }
+        const cpx<T> g11 = g[0], g22 = g[1], g33 = g[2], g23 = g[3], g13 = g[4], g12 = g[5];
         const cpx<T> f1 = v[0][i], f2 = v[1][i], f3 = v[2][i];
         v[0][i] = g11 * f1 + g12 * f2 + g13 * f3;
         v[1][i] = g12 * f1 + g22 * f2 + g23 * f3;
@@ -499,16 +514,25 @@ int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<
                 if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");           \
                 const long long nb = (long long)nrhs * (L1 / TX) * L2;                                        \
                 const long long nb_launch = (nb + 7) / 8 * 8;                                                 \
-                hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX>), dim3((unsigned)nb_launch),                       \
-                                   dim3(fs_threads<T, LL>()), 0, c->stream, data, nrhs, L1, L2, CS, RS, ES,   \
-                                   c->n3, ghat, tw, nb);                                                      \
+                if (c->green_half)                                                                            \
+                    hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX, true>), dim3((unsigned)nb_launch),             \
+                                       dim3(fs_threads<T, LL>()), 0, c->stream, data, nrhs, L1, L2, CS, RS,   \
+                                       ES, c->n3, ghat, tw, nb);                                              \
+                else                                                                                          \
+                    hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX>), dim3((unsigned)nb_launch),                   \
+                                       dim3(fs_threads<T, LL>()), 0, c->stream, data, nrhs, L1, L2, CS, RS,   \
+                                       ES, c->n3, ghat, tw, nb);                                              \
                 break;                                                                                        \
             }                                                                                                 \
         }                                                                                                     \
         constexpr int TX = zpass_cols<T, LL>();                                                               \
         if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");                   \
-        hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), 0,        \
-                           c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw);                       \
+        if (c->green_half)                                                                                    \
+            hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX, true>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), \
+                               0, c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw);                \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), 0,    \
+                               c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw);                   \
         break;                                                                                                \
     }
         LS_FOR_LENGTHS(CASE)

@@ -157,10 +157,11 @@ __global__ void k_extract_octant(const z128* __restrict__ buf, z128* __restrict_
 }
 
 // b_i(x) = phase * sum_q [ G_ij(x - q) F_j(q)  (x != q);  self/h^3 F_i(q)  (x == q) ]
-// greal (LS_GREEN_ANISO): the octant table h^3 G, read with the mirror signs; else the closed form.
+// greal (LS_GREEN_ANISO): the octant table h^3 G, read with the mirror signs, or (half) the half-space
+// table, read at -m for m_x < 0; else the closed form.
 __global__ void k_rhs_points(z128* __restrict__ b, int N1, int N2, int N3, double h, GreenParams P, z128 self_over_h3,
                              const int* __restrict__ cells, const double* __restrict__ F, int npts, z128 phase,
-                             const z128* __restrict__ greal) {
+                             const z128* __restrict__ greal, int half) {
     const long long n = (long long)N1 * N2 * N3;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -169,7 +170,17 @@ __global__ void k_rhs_points(z128* __restrict__ b, int N1, int N2, int N3, doubl
     for (int t = 0; t < npts; ++t) {
         const int di = i - cells[3 * t], dj = j - cells[3 * t + 1], dk = k - cells[3 * t + 2];
         const double f0 = F[3 * t], f1 = F[3 * t + 1], f2 = F[3 * t + 2];
-        if (greal) {
+        if (greal && half) {
+            const int s = di < 0 ? -1 : 1;
+            const z128* e = greal + (((long long)(s * dk + N3 - 1) * (2 * N2 - 1) + (s * dj + N2 - 1)) * N1 + s * di) * 6;
+            const double ih3 = 1.0 / (h * h * h);
+            z128 g[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) g[q] = ih3 * e[q];
+            acc[0] = acc[0] + f0 * g[0] + f1 * g[5] + f2 * g[4];
+            acc[1] = acc[1] + f0 * g[5] + f1 * g[1] + f2 * g[3];
+            acc[2] = acc[2] + f0 * g[4] + f1 * g[3] + f2 * g[2];
+        } else if (greal) {
             const z128* e = greal + (((long long)abs(dk) * N2 + abs(dj)) * N1 + abs(di)) * 6;
             const double ih3 = 1.0 / (h * h * h);
             const double syz = ((dj < 0) != (dk < 0)) ? -ih3 : ih3;
@@ -199,7 +210,7 @@ __global__ void k_rhs_points(z128* __restrict__ b, int N1, int N2, int N3, doubl
 }
 
 // ---------------------------------------------------------------------------------------------
-// Anisotropic background with the three coordinate mirror planes (LS_GREEN_ANISO).
+// Anisotropic background (LS_GREEN_ANISO).
 //
 // With Gamma(n) the Christoffel matrix, lambda_m, P_m its eigenvalues and eigenprojectors and
 // k_m = w sqrt(rho / lambda_m), the outgoing solution of Eq 7 has the plane-wave form (the inverse
@@ -208,8 +219,9 @@ __global__ void k_rhs_points(z128* __restrict__ b, int N1, int N2, int N3, doubl
 //        + i/(8 pi^2) int_{n.x>0} sum_m P_m k_m/lambda_m e^{i k_m n.x} dS(n),
 // and the zero-offset cell takes the integral over the sphere of volume h^3,
 //   1/(4 pi) int_{S^2} sum_m P_m I(k_m)/lambda_m dS,  I(k) = int_0^R r e^{i k r} dr.
-// The mirror planes give G_ab(s x) = s_a s_b G_ab(x): one octant of offsets is evaluated, one
-// thread per offset, and the padded table is filled from it with those signs.
+// Every homogeneous medium gives G(-x) = G(x); a background with the three coordinate mirror planes also
+// gives G_ab(s x) = s_a s_b G_ab(x).  So one octant of offsets (mirror planes) or one half-space
+// (x >= 0, any stiffness) is evaluated, one thread per offset, and the padded table is filled from it.
 //
 // Per quadrature node the matrix function sum_m f(lambda_m) P_m is formed without eigenvectors:
 // the quasi-P eigenvalue lambda_c (the largest, kept apart from the other two by a set-up check)
@@ -221,19 +233,22 @@ __global__ void k_rhs_points(z128* __restrict__ b, int N1, int N2, int N3, doubl
 //   sum_m f(lambda_m) P_m = (f_c - f_m - D (lambda_c - s/2)) P_c + (f_m - D s/2) I + D Gamma,
 // f_m = (f(lambda_a) + f(lambda_b)) / 2.
 
-struct Ortho {
-    double c11, c22, c33, c44, c55, c66, c12, c13, c23;
+// Christoffel matrix as a quadratic form: component q of Gamma(n) = sum_m a[q][m] mono_m(n), the monomials
+// (n1 n1, n2 n2, n3 n3, n2 n3, n1 n3, n1 n2).  Symmetric 3x3 matrices are stored as (00, 11, 22, 12, 02,
+// 01), the table's component order.
+struct Quad {
+    double a[6][6];
 };
 
-// symmetric 3x3 matrices are stored as (00, 11, 22, 12, 02, 01), the table's component order
-__host__ __device__ inline void christoffel(const Ortho& m, double n1, double n2, double n3, double g[6]) {
-    const double a = n1 * n1, b = n2 * n2, d = n3 * n3;
-    g[0] = m.c11 * a + m.c66 * b + m.c55 * d;
-    g[1] = m.c66 * a + m.c22 * b + m.c44 * d;
-    g[2] = m.c55 * a + m.c44 * b + m.c33 * d;
-    g[3] = (m.c23 + m.c44) * n2 * n3;
-    g[4] = (m.c13 + m.c55) * n1 * n3;
-    g[5] = (m.c12 + m.c66) * n1 * n2;
+__host__ __device__ inline void christoffel(const Quad& Q, double n1, double n2, double n3, double g[6]) {
+    const double mono[6] = {n1 * n1, n2 * n2, n3 * n3, n2 * n3, n1 * n3, n1 * n2};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) v += Q.a[q][m] * mono[m];
+        g[q] = v;
+    }
 }
 
 __host__ __device__ inline double det_sym(const double g[6]) {
@@ -274,7 +289,7 @@ __device__ inline z128 f_plane_deriv(double lam, double wsr, double ru) {
 }
 
 struct AnisoParams {
-    Ortho m;
+    Quad m;
     double wsr;      // w sqrt(rho)
     double kmax;     // upper bound of w / v over directions and modes
     double h;
@@ -285,25 +300,30 @@ struct AnisoParams {
 constexpr int kGlLevels = 64;   // Gauss-Legendre rules with 8 l nodes, l = 1..64
 constexpr int kCircleNodes = 64;
 
-// h^3 G at the octant offsets (i, j, k) h, i < N1, j < N2, k < N3; out [N3][N2][N1][6].
-// A block is a 4 x 4 x 4 cube of offsets, so the node counts (which grow with r) vary little
-// within a wavefront.  gl: rule l at pairs 4 l (l - 1) .. 4 l (l + 1) - 1 of (node, weight) on [0, 1].
+// h^3 G at the offsets of one octant or one half-space; out [D3][D2][D1][6] with (D1, D2, D3) =
+// (N1, N2, N3) for the octant (offset (i, j, k)) and (N1, 2 N2 - 1, 2 N3 - 1) for the half-space
+// (offset (i, j - N2 + 1, k - N3 + 1)).  A block is a 4 x 4 x 4 cube of offsets, so the node counts
+// (which grow with r) vary little within a wavefront.  gl: rule l at pairs 4 l (l - 1) .. 4 l (l + 1) - 1
+// of (node, weight) on [0, 1].
+template <bool HALF>
 __global__ __launch_bounds__(64) void k_green_aniso(z128* __restrict__ out, AnisoParams P,
                                                     const double* __restrict__ gl) {
     const int t = threadIdx.x;
-    const int bx = (P.N1 + 3) / 4, by = (P.N2 + 3) / 4;
+    const int D1 = P.N1, D2 = HALF ? 2 * P.N2 - 1 : P.N2, D3 = HALF ? 2 * P.N3 - 1 : P.N3;
+    const int bx = (D1 + 3) / 4, by = (D2 + 3) / 4;
     const int b = blockIdx.x;
     const int i = 4 * (b % bx) + (t & 3);
     const int j = 4 * ((b / bx) % by) + ((t >> 2) & 3);
     const int k = 4 * (b / (bx * by)) + (t >> 4);
-    if (i >= P.N1 || j >= P.N2 || k >= P.N3) return;
-    z128* o = out + (((long long)k * P.N2 + j) * P.N1 + i) * 6;
-    if (i == 0 && j == 0 && k == 0) {
+    if (i >= D1 || j >= D2 || k >= D3) return;
+    z128* o = out + (((long long)k * D2 + j) * D1 + i) * 6;
+    const int mx = i, my = HALF ? j - (P.N2 - 1) : j, mz = HALF ? k - (P.N3 - 1) : k;
+    if (mx == 0 && my == 0 && mz == 0) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) o[q] = P.self[q];
         return;
     }
-    const double x0 = i * P.h, x1 = j * P.h, x2 = k * P.h;
+    const double x0 = mx * P.h, x1 = my * P.h, x2 = mz * P.h;
     const double r = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
     const double ir = 1.0 / r;
     const double xh[3] = {x0 * ir, x1 * ir, x2 * ir};
@@ -397,7 +417,9 @@ __global__ __launch_bounds__(64) void k_green_aniso(z128* __restrict__ out, Anis
     for (int q = 0; q < 6; ++q) o[q] = {cs * gs[q] - cr * acc[q].y, cr * acc[q].x};   // i * acc
 }
 
-// one component of the padded real-space table from the octant: T_ab(m) = s_a s_b greal_ab(|m|)
+// one component of the padded real-space table: from the octant, T_ab(m) = s_a s_b greal_ab(|m|); from
+// the half-space, T(m) = greal(m) for m_x >= 0 and greal(-m) otherwise
+template <bool HALF>
 __global__ void k_fill_aniso(z128* __restrict__ buf, const z128* __restrict__ greal, int comp, int L1, int L2, int L3,
                              int N1, int N2, int N3) {
     const long long total = (long long)L1 * L2 * L3;
@@ -418,12 +440,35 @@ __global__ void k_fill_aniso(z128* __restrict__ buf, const z128* __restrict__ gr
     int mx, my, mz;
     z128 v = {0.0, 0.0};
     if (offset(x, L1, N1, mx) && offset(y, L2, N2, my) && offset(z, L3, N3, mz)) {
-        v = greal[(((long long)abs(mz) * N2 + abs(my)) * N1 + abs(mx)) * 6 + comp];
-        const bool sx = mx < 0, sy = my < 0, sz = mz < 0;
-        const bool neg = comp == 3 ? (sy != sz) : comp == 4 ? (sx != sz) : comp == 5 ? (sx != sy) : false;
-        if (neg) v = {-v.x, -v.y};
+        if constexpr (HALF) {
+            if (mx < 0) {
+                mx = -mx;
+                my = -my;
+                mz = -mz;
+            }
+            v = greal[(((long long)(mz + N3 - 1) * (2 * N2 - 1) + (my + N2 - 1)) * N1 + mx) * 6 + comp];
+        } else {
+            v = greal[(((long long)abs(mz) * N2 + abs(my)) * N1 + abs(mx)) * 6 + comp];
+            const bool sx = mx < 0, sy = my < 0, sz = mz < 0;
+            const bool neg = comp == 3 ? (sy != sz) : comp == 4 ? (sx != sz) : comp == 5 ? (sx != sy) : false;
+            if (neg) v = {-v.x, -v.y};
+        }
     }
     buf[q] = v;
+}
+
+// the half-space k_x <= L1/2 of one transformed component, scaled, into [L3][L2][L1/2+1][6]
+__global__ void k_extract_half(const z128* __restrict__ buf, z128* __restrict__ g, z64* __restrict__ g32, int comp,
+                               int L1, int L2, int L3, double scale) {
+    const int O1 = L1 / 2 + 1;
+    const long long total = (long long)O1 * L2 * L3;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int x = (int)(q % O1), y = (int)((q / O1) % L2), z = (int)(q / ((long long)O1 * L2));
+    const z128 v = buf[((long long)z * L2 + y) * L1 + x];
+    const z128 s = {v.x * scale, v.y * scale};
+    g[q * 6 + comp] = s;
+    if (g32) g32[q * 6 + comp] = {(float)s.x, (float)s.y};
 }
 
 // Gauss-Legendre nodes and weights of n points on [-1, 1] (Newton's method on P_n from the
@@ -503,15 +548,27 @@ void jacobi3(const double g[6], double lam[3], double V[3][3]) {
         for (int b = 0; b < 3; ++b) V[a][b] = W[a][b];
 }
 
-Ortho ortho_of(const double* C) {
-    return {C[0], C[7], C[14], C[21], C[28], C[35], C[1], C[2], C[8]};
+// Gamma_ik(n) = c_ijkl n_j n_l as a quadratic form in n, from the Voigt stiffness (row-major 6x6): the
+// coefficient of n_j n_j is c_ijkj, that of n_j n_l (j < l) is c_ijkl + c_ilkj.
+Quad quad_of(const double* C) {
+    auto voigt = [](int a, int b) { return a == b ? a : 6 - a - b; };   // 00 11 22 -> 0 1 2; 12 -> 3, 02 -> 4, 01 -> 5
+    auto c4 = [&](int i, int j, int k, int l) { return C[voigt(i, j) * 6 + voigt(k, l)]; };
+    const int pi[6] = {0, 1, 2, 1, 0, 0}, pk[6] = {0, 1, 2, 2, 2, 1};   // component q = (i, k)
+    const int mj[6] = {0, 1, 2, 1, 0, 0}, ml[6] = {0, 1, 2, 2, 2, 1};   // monomial m = n_j n_l
+    Quad Q;
+    for (int q = 0; q < 6; ++q)
+        for (int m = 0; m < 6; ++m) {
+            const int i = pi[q], k = pk[q], j = mj[m], l = ml[m];
+            Q.a[q][m] = j == l ? c4(i, j, k, j) : c4(i, j, k, l) + c4(i, l, k, j);
+        }
+    return Q;
 }
 
 // Set-up quantities of the anisotropic table from a sampling of the sphere (GL 48 in cos(theta),
 // 96 azimuths): the smallest eigenvalue (kmax = 1.1 w sqrt(rho / lambda_min)), the quasi-P gap check,
 // and the zero-offset entry 1/(4 pi) int sum_m P_m I(k_m) / lambda_m dS for each frequency.
 int aniso_setup(const Ctx* c, double w, double* kmax, z128 self[6]) {
-    const Ortho m = ortho_of(c->C0);
+    const Quad m = quad_of(c->C0);
     constexpr int NT = 48, NP = 96;
     double tx[NT], tw[NT];
     gauss_legendre(NT, tx, tw);
@@ -575,7 +632,7 @@ int build_aniso_real(Ctx* c, int i) {
         LS_HIP(hipMemcpy(c->gl_nodes, gl.data(), gl.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     AnisoParams P;
-    P.m = ortho_of(c->C0);
+    P.m = quad_of(c->C0);
     P.wsr = c->omega[i] * std::sqrt(c->rho0);
     P.h = c->h;
     P.N1 = c->n1;
@@ -583,8 +640,14 @@ int build_aniso_real(Ctx* c, int i) {
     P.N3 = c->n3;
     int rc = aniso_setup(c, c->omega[i], &P.kmax, P.self);
     if (rc) return rc;
-    const long long blocks = (long long)((c->n1 + 3) / 4) * ((c->n2 + 3) / 4) * ((c->n3 + 3) / 4);
-    hipLaunchKernelGGL(k_green_aniso, dim3((unsigned)blocks), dim3(64), 0, c->stream, c->greal[i], P, c->gl_nodes);
+    const int D2 = c->green_half ? 2 * c->n2 - 1 : c->n2, D3 = c->green_half ? 2 * c->n3 - 1 : c->n3;
+    const long long blocks = (long long)((c->n1 + 3) / 4) * ((D2 + 3) / 4) * ((D3 + 3) / 4);
+    if (c->green_half)
+        hipLaunchKernelGGL(k_green_aniso<true>, dim3((unsigned)blocks), dim3(64), 0, c->stream, c->greal[i], P,
+                           c->gl_nodes);
+    else
+        hipLaunchKernelGGL(k_green_aniso<false>, dim3((unsigned)blocks), dim3(64), 0, c->stream, c->greal[i], P,
+                           c->gl_nodes);
     LS_HIP(hipGetLastError());
     return LS_OK;
 }
@@ -597,6 +660,7 @@ int build_green_tables(Ctx* c) {
     const int L1 = c->L1, L2 = c->L2, L3 = c->L3;
     const long long total = (long long)L1 * L2 * L3;
     const long long oct = (long long)(L1 / 2 + 1) * (L2 / 2 + 1) * (L3 / 2 + 1);
+    const long long half = (long long)(L1 / 2 + 1) * L2 * L3;
     z128* buf = nullptr;
     LS_HIP(hipMallocAsync((void**)&buf, total * sizeof(z128), c->stream));
     int rc = LS_OK;
@@ -606,9 +670,12 @@ int build_green_tables(Ctx* c) {
         const z128 self = aniso ? z128{0.0, 0.0} : self_term(c->h, P);
         if (aniso && (rc = build_aniso_real(c, (int)i))) break;
         for (int comp = 0; comp < 6 && rc == LS_OK; ++comp) {
-            if (aniso)
-                hipLaunchKernelGGL(k_fill_aniso, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream, buf,
-                                   (const z128*)c->greal[i], comp, L1, L2, L3, c->n1, c->n2, c->n3);
+            if (aniso && c->green_half)
+                hipLaunchKernelGGL(k_fill_aniso<true>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream,
+                                   buf, (const z128*)c->greal[i], comp, L1, L2, L3, c->n1, c->n2, c->n3);
+            else if (aniso)
+                hipLaunchKernelGGL(k_fill_aniso<false>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream,
+                                   buf, (const z128*)c->greal[i], comp, L1, L2, L3, c->n1, c->n2, c->n3);
             else
                 hipLaunchKernelGGL(k_sample_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream,
                                    buf, comp, L1, L2, L3, c->n1, c->n2, c->n3, c->h, P, self);
@@ -618,9 +685,14 @@ int build_green_tables(Ctx* c) {
             }
             rc = fft_full_3d_forward<double>(c, buf);
             if (rc) break;
-            hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((oct + 255) / 256)), dim3(256), 0, c->stream, buf,
-                               c->ghat[i], c->mixed ? c->ghat32[i] : nullptr, comp, L1, L2, L3,
-                               1.0 / (double)total);
+            if (c->green_half)
+                hipLaunchKernelGGL(k_extract_half, dim3((unsigned)((half + 255) / 256)), dim3(256), 0, c->stream, buf,
+                                   c->ghat[i], c->mixed ? c->ghat32[i] : nullptr, comp, L1, L2, L3,
+                                   1.0 / (double)total);
+            else
+                hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((oct + 255) / 256)), dim3(256), 0, c->stream, buf,
+                                   c->ghat[i], c->mixed ? c->ghat32[i] : nullptr, comp, L1, L2, L3,
+                                   1.0 / (double)total);
             if (hipGetLastError() != hipSuccess) rc = fail(LS_ERR_HIP, "octant extraction launch failed");
         }
     }
@@ -652,7 +724,8 @@ int rhs_points_launch(Ctx* c, int i_omega, const int* cells, const double* force
     c->prof.begin(c->stream, "rhs_points");
     hipLaunchKernelGGL(k_rhs_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, b, c->n1, c->n2, c->n3,
                        c->h, P, self_h3, dcells, dF, npts, phase,
-                       c->green_mode == LS_GREEN_ANISO ? (const z128*)c->greal[i_omega] : nullptr);
+                       c->green_mode == LS_GREEN_ANISO ? (const z128*)c->greal[i_omega] : nullptr,
+                       c->green_half ? 1 : 0);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     // the staging area is reused by the next call: wait for the copies to be consumed

@@ -23,6 +23,7 @@ from paper_2301_12836_amd import lsvie  # noqa: E402
 
 W15 = 2 * np.pi * 15.0
 C_ORTHO, RHO_ORTHO = models.ortho_background()
+C_TTI = models.tti_cfg3()   # no coordinate mirror plane: the half-space table
 
 
 def rel(a, b):
@@ -57,12 +58,14 @@ def test_isotropic_background_gives_the_exact_table():
     ca.close()
 
 
-@pytest.mark.parametrize("bg", ["vti", "ortho"])
+@pytest.mark.parametrize("bg", ["vti", "ortho", "tti"])
 @pytest.mark.parametrize("shape", [(6, 7, 5), (4, 3, 6)])
 def test_apply_matches_oracle(bg, shape):
     m = models.random_medium(shape, seed=sum(shape) + 1, rel=0.1, aniso_background=True)
     if bg == "ortho":
         with_background(m, C_ORTHO, RHO_ORTHO)
+    if bg == "tti":
+        with_background(m, C_TTI, 2400.0)
     P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, W15, mode="aniso")
     u = models.random_field(shape, seed=3)
     want = P.apply_fft(u)
@@ -75,11 +78,15 @@ def test_apply_matches_oracle(bg, shape):
     ctx.close()
 
 
-def test_table_and_incident_field_at_64_cubed():
-    """Config-2 grid and VTI background: the convolution of a point force at the origin cell returns
-    h^3 G F at every offset of the octant (the whole FFT table pipeline); the incident field of a
-    point force at an interior cell reads the octant table with the mirror signs (all eight octants)."""
+@pytest.mark.parametrize("bg", ["vti", "tti"])
+def test_table_and_incident_field_at_64_cubed(bg):
+    """Config-2 grid with its VTI background (octant table) or the tilted config-3 medium (half-space
+    table): the convolution of a point force at the origin cell returns h^3 G F at every offset of the
+    octant (the whole FFT table pipeline); the incident field of a point force at an interior cell reads
+    the real-space table at offsets in all eight octants."""
     m = models.config2()
+    if bg == "tti":
+        with_background(m, C_TTI, 2400.0)
     w = m.omegas[0]
     ctx = context(m, [w], "aniso")
     F = np.array([1.0, 0.5, -0.3])
@@ -130,11 +137,38 @@ def test_solve_matches_dense_oracle_orthorhombic():
     ctx.close()
 
 
-def test_background_without_mirror_planes_is_rejected():
-    m = models.random_medium((4, 4, 4), seed=1, rel=0.05)
-    with_background(m, models.tti_cfg3(), 2400.0)
-    with pytest.raises(lsvie.LsError, match="mirror"):
-        context(m, [W15], "aniso")
+def test_half_space_table_equals_octant_table(monkeypatch):
+    """A mirror-symmetric (VTI) background through the half-space table (forced by LS_GREEN_TABLE=half)
+    gives the operator of the octant table."""
+    m = models.random_medium((9, 8, 10), seed=5, rel=0.1, aniso_background=True)
+    u = torch.from_numpy(models.random_field(m.shape, seed=4))
+    co = context(m, [W15], "aniso", precision="mixed")
+    monkeypatch.setenv("LS_GREEN_TABLE", "half")
+    ch = context(m, [W15], "aniso", precision="mixed")
+    for dt in (torch.complex128, torch.complex64):
+        a, b = to_np(ch.apply(u.to(dt))), to_np(co.apply(u.to(dt)))
+        print("half vs octant", dt, rel(a, b), flush=True)
+        assert rel(a, b) < (1e-13 if dt == torch.complex128 else 1e-6)
+    assert ch.device_bytes > co.device_bytes
+    co.close()
+    ch.close()
+
+
+def test_solve_matches_dense_oracle_tilted_background():
+    m = with_background(models.random_medium((5, 6, 4), seed=13, rel=0.08, aniso_background=True), C_TTI, 2400.0)
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, W15, mode="aniso")
+    M = models.double_couple(30, 60, 90)
+    b = P.rhs_moment(M, (2, 3, 1))
+    want = solve.solve_dense(P.dense_A(), b)
+    ctx = context(m, [W15], "aniso", precision="mixed")
+    bg = ctx.rhs_moment(M, (2, 3, 1))
+    assert rel(to_np(bg), b) < 1e-10
+    u, info = ctx.solve(bg, tol=1e-12, maxit=500, precision="c128")
+    print("tti c128 solve", rel(to_np(u), want), info, flush=True)
+    assert rel(to_np(u), want) < 1e-10
+    u, info = ctx.solve(bg, tol=1e-7, maxit=500, precision="mixed")
+    assert rel(to_np(u), want) < 1e-5
+    ctx.close()
 
 
 def test_anisotropic_background_needs_fewer_iterations_than_the_fold():
