@@ -95,7 +95,7 @@ static void release(Ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
                     c->xd, c->bd, c->gs, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
-                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes, c->gpart, c->xbest};
+                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes, c->gpart, c->xbest, c->dparts};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto q : c->ghat) (void)hipFree(q);
@@ -390,6 +390,8 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
         for (auto pp : v64) A((void**)pp, fe * sizeof(z64));
     }
     A((void**)&c->partials, (size_t)c->max_rhs * kRedSlots * kRedBlocks * sizeof(double));
+    // fused inner products: at most 3 N3 N2 / 8 epilogue blocks per right-hand side (c128 tiles of 8 lines)
+    A((void**)&c->dparts, (size_t)c->max_rhs * kRedSlots * (3 * (size_t)c->n3 * c->n2 / 8 + 1) * sizeof(double));
     A((void**)&c->state, (size_t)c->max_rhs * kStateLen * sizeof(double));
     A((void**)&c->red, 4 * kRedBlocks * sizeof(double));
     A(&c->stage, 8192);

@@ -140,6 +140,16 @@ struct Ctx {
     int bicgstab_l = 1;          // Krylov method: 1 Bi-CGSTAB (graph-captured), 2..4 BiCGSTAB(l)
     double* gpart = nullptr;     // BiCGSTAB(l) reduction partials [max_rhs][slots][kRedBlocks]
     std::vector<void*> kry128, kry64;  // BiCGSTAB(l) vectors beyond the six of Bi-CGSTAB, per precision
+    // inner products fused into the x-inverse epilogue of the next forward operator application:
+    // mode 1 = a^H (u - v), mode 2 = (u - v)^H u and ||u - v||^2; set by the solver around the call
+    struct DotRequest {
+        int mode = 0;
+        const void* a = nullptr;
+        double* parts = nullptr;
+        long long lines = 1;   // x lines per right-hand side
+        int nparts = 0;        // epilogue blocks per right-hand side
+    } dot;
+    double* dparts = nullptr;    // partials of the fused inner products [max_rhs][kRedSlots][blocks per RHS]
     double* red = nullptr;       // reduction results (device)
     double* red_host = nullptr;  // pinned host mirror
     long long bytes = 0;
@@ -162,6 +172,8 @@ int fft_apply_passes(Ctx* c, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>*
                      bool subtract_from_u);
 template <typename T>
 int fft_full_3d_forward(Ctx* c, cpx<T>* buf);
+template <typename T>
+int fused_dot_blocks(const Ctx* c);  // epilogue blocks per right-hand side if the dots can be fused, else 0
 template <typename T>
 int autotune_passes(Ctx* c);
 int supported_fft_length(int n);

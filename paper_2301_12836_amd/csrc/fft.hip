@@ -270,12 +270,20 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_strided(cpx<T>* __r
 
 // Contiguous (x) pass over TY lines per block.  MODE 0: forward in place; MODE 1: inverse with
 // out = u - v (compact); MODE 2: inverse with out = v (compact).
-template <typename T, int L, int TY, int SIGN, int MODE, bool PRUNE>
+// DOT (MODE 1 only): inner products of the written field, fused for the Bi-CGSTAB iteration that
+// called the operator: 1 = a^H out (slots re, im), 2 = out^H u and ||out||^2 (slots re, im, norm),
+// summed over the block in a fixed order into dot_parts[(rhs kRedSlots + slot) nparts + block of the
+// right-hand side] (every block holds lines of one right-hand side: dot_lines, the lines per
+// right-hand side, is a multiple of TY).
+template <typename T, int L, int TY, int SIGN, int MODE, bool PRUNE, int DOT = 0>
 __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __restrict__ data, long long nlines,
                                                                     int D2, long long S1, long long S2, int n_in,
                                                                     int n_out, const cpx<T>* __restrict__ tw,
                                                                     const cpx<T>* __restrict__ u,
-                                                                    cpx<T>* __restrict__ out) {
+                                                                    cpx<T>* __restrict__ out,
+                                                                    const cpx<T>* __restrict__ dot_a = nullptr,
+                                                                    double* __restrict__ dot_parts = nullptr,
+                                                                    long long dot_lines = 1, int dot_nparts = 0) {
     using F = FourStep<L>;
     constexpr int LDP = TY + 1;
     __shared__ cpx<T> lds[L * LDP];
@@ -310,17 +318,51 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
         }
         __syncthreads();
         fs_backward<T, L, LDP, SIGN>(v, lds, tws, ln, q);
+        double acc[3] = {0.0, 0.0, 0.0};
         if (valid) {
 #pragma unroll
             for (int j = 0; j < F::N2; ++j) {
                 const int e = q + F::N1 * j;
                 if (!half_slot<L, PRUNE>(j) && e < n_out) {
                     const long long qq = line * n_out + e;
-                    if constexpr (MODE == 1)
-                        out[qq] = u[qq] - v[j];
-                    else
+                    if constexpr (MODE == 1) {
+                        const cpx<T> uu = u[qq];
+                        const cpx<T> o = uu - v[j];
+                        out[qq] = o;
+                        if constexpr (DOT == 1) {   // a^H o
+                            const cpx<T> a = dot_a[qq];
+                            acc[0] += (double)a.x * o.x + (double)a.y * o.y;
+                            acc[1] += (double)a.x * o.y - (double)a.y * o.x;
+                        } else if constexpr (DOT == 2) {   // o^H u, |o|^2
+                            acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
+                            acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
+                            acc[2] += (double)o.x * o.x + (double)o.y * o.y;
+                        }
+                    } else {
                         out[qq] = v[j];
+                    }
                 }
+            }
+        }
+        if constexpr (MODE == 1 && DOT != 0) {
+            // fixed-order block sum: wavefront shuffles, then the wavefronts in order
+            constexpr int NW = (TY * F::N1 + 63) / 64;   // whole wavefronts only (checked by fused_dot_blocks)
+            constexpr int NS = DOT == 1 ? 2 : 3;
+            __shared__ double red[NW][NS];
+            const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                double x = acc[k];
+                for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+                if (lane == 0) red[wave][k] = x;
+            }
+            __syncthreads();
+            if (tid < NS) {
+                double x = 0.0;
+                for (int w = 0; w < NW; ++w) x += red[w][tid];
+                const long long l0 = (long long)blockIdx.x * TY;
+                const long long rr = l0 / dot_lines, blk = (l0 - rr * dot_lines) / TY;
+                dot_parts[(rr * kRedSlots + tid) * dot_nparts + blk] = x;
             }
         }
     }
@@ -430,11 +472,12 @@ bool use_fourstep() {
     return fs;
 }
 
-template <typename T, int SIGN, int MODE, bool PRUNE>
+template <typename T, int SIGN, int MODE, bool PRUNE, int DOT = 0>
 int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long long S1, long long S2, int n_in,
                   int n_out, const cpx<T>* tw, const cpx<T>* u, cpx<T>* out, const char* name, int variant = 0) {
     c->prof.begin(c->stream, name);
     const bool fs = variant == 0 && use_fourstep();
+    if (DOT != 0 && !fs) return fail(LS_ERR_STATE, "fused inner products need the register four-step x pass");
     switch (L) {
 #define CASE(LL)                                                                                             \
     case LL: {                                                                                               \
@@ -442,12 +485,14 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
             if (fs) {                                                                                        \
                 constexpr int TY = seg_cols<T>();                                                            \
                 const long long nb = (nlines + TY - 1) / TY;                                                 \
-                hipLaunchKernelGGL((k_fs_contig<T, LL, TY, SIGN, MODE, PRUNE>), dim3((unsigned)nb),                  \
+                hipLaunchKernelGGL((k_fs_contig<T, LL, TY, SIGN, MODE, PRUNE, DOT>), dim3((unsigned)nb),             \
                                    dim3(fs_threads<T, LL>()), 0, c->stream, data, nlines, D2, S1, S2, n_in,  \
-                                   n_out, tw, u, out);                                                       \
+                                   n_out, tw, u, out, (const cpx<T>*)c->dot.a, c->dot.parts, c->dot.lines,   \
+                                   c->dot.nparts);                                                           \
                 break;                                                                                       \
             }                                                                                                \
         }                                                                                                    \
+        if constexpr (DOT != 0) return fail(LS_ERR_STATE, "fused inner products need a power-of-two x length"); \
         constexpr int TY = contig_lines<T, LL>();                                                            \
         const long long nb = (nlines + TY - 1) / TY;                                                         \
         hipLaunchKernelGGL((k_fft_contig<T, LL, TY, SIGN, MODE>), dim3((unsigned)nb), dim3(kThreads), 0,     \
@@ -590,6 +635,12 @@ int run_pass(Ctx* c, int pass, int variant, int i_omega, cpx<T>* work, const cpx
             return launch_strided<T, +1, true>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, L2, N2,
                                                twiddles<T>(c, L2), LS_PNAME(T, "fft_y_inv"), variant);
         default:
+            if (subtract_from_u && c->dot.mode == 1)
+                return launch_contig<T, +1, 1, true, 1>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1,
+                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant);
+            if (subtract_from_u && c->dot.mode == 2)
+                return launch_contig<T, +1, 1, true, 2>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1,
+                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant);
             if (subtract_from_u)
                 return launch_contig<T, +1, 1, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1,
                                                      twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant);
@@ -663,6 +714,33 @@ int fft_full_3d_forward(Ctx* c, cpx<T>* buf) {
     if (rc_) return rc_;
     return launch_strided<T, -1, false>(c, L3, buf, L1, L2, 1, 0, L1, plane, L3, L3, twiddles<T>(c, L3), "table_fft_z");
 }
+
+// Blocks per right-hand side of the x-inverse epilogue when the Bi-CGSTAB inner products can be fused
+// into it (register four-step variant, whole wavefronts per block, whole blocks per right-hand side),
+// else 0.
+template <typename T>
+int fused_dot_blocks(const Ctx* c) {
+    const int prec = sizeof(T) == 8 ? 0 : 1;
+    if (c->variant[prec][4] != 0 || !use_fourstep()) return 0;
+    bool ok = false;
+    switch (c->L1) {
+#define CASE(LL)                                                         \
+    case LL:                                                             \
+        if constexpr (fs_ok<T, LL>()) ok = fs_threads<T, LL>() % 64 == 0; \
+        break;
+        LS_FOR_LENGTHS(CASE)
+#undef CASE
+        default:
+            ok = false;
+    }
+    constexpr int TY = seg_cols<T>();
+    const long long lines = 3LL * c->n3 * c->n2;
+    if (!ok || lines % TY != 0) return 0;
+    return (int)(lines / TY);
+}
+
+template int fused_dot_blocks<double>(const Ctx*);
+template int fused_dot_blocks<float>(const Ctx*);
 
 template int fft_apply_passes<double>(Ctx*, int, z128*, const z128*, z128*, int, bool);
 template int fft_apply_passes<float>(Ctx*, int, z64*, const z64*, z64*, int, bool);

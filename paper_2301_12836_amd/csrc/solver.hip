@@ -261,8 +261,11 @@ __global__ void k_copy(const z128* __restrict__ a, z128* __restrict__ b, long lo
 // Sum the kRedBlocks partials of each slot in a fixed order, then advance the scalars.
 enum Phase { PH_INIT = 0, PH_ALPHA = 1, PH_S = 2, PH_OMEGA = 3, PH_RHO = 4, PH_RESID = 5 };
 
-__global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict__ partials, double* __restrict__ state,
-                                                       int phase, int nslots, double tol2, double* __restrict__ out) {
+// partials: [rhs][kRedSlots][nparts] (nparts = kRedBlocks, or the x-inverse epilogue's blocks per right-hand
+// side for the inner products fused there)
+__global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict__ partials, int nparts,
+                                                       double* __restrict__ state, int phase, int nslots, double tol2,
+                                                       double* __restrict__ out) {
     __shared__ double sh[kRedSlots][kThreads];
     const int rr = blockIdx.x;
     double* st = state + rr * kStateLen;
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict_
     if (phase != PH_INIT && phase != PH_RESID && st[S_ACTIVE] == 0.0) return;
     for (int q = 0; q < nslots; ++q) {
         double a = 0;
-        for (int k = tid; k < kRedBlocks; k += kThreads) a += partials[((long long)rr * kRedSlots + q) * kRedBlocks + k];
+        for (int k = tid; k < nparts; k += kThreads) a += partials[((long long)rr * kRedSlots + q) * nparts + k];
         sh[q][tid] = a;
     }
     __syncthreads();
@@ -398,9 +401,10 @@ struct Vecs32 {
 
 dim3 vgrid(int nrhs) { return dim3(kRedBlocks, nrhs); }
 
-int finalize(Ctx* c, int phase, int nslots, int nrhs, double tol2 = 0.0, double* out = nullptr) {
-    hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kThreads), 0, c->stream, c->partials, c->state, phase, nslots, tol2,
-                       out);
+int finalize(Ctx* c, int phase, int nslots, int nrhs, double tol2 = 0.0, double* out = nullptr,
+             const double* parts = nullptr, int nparts = kRedBlocks) {
+    hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kThreads), 0, c->stream, parts ? parts : c->partials, nparts,
+                       c->state, phase, nslots, tol2, out);
     LS_HIP(hipGetLastError());
     return LS_OK;
 }
@@ -433,9 +437,13 @@ inline int stall_window(double r2, double b2) { return r2 < 1e-8 * b2 ? 30 : 300
 template <typename T, typename X, typename ApplyFn>
 int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, cpx<T>* rhat, cpx<T>* p, cpx<T>* v,
              cpx<T>* s, cpx<T>* t, int nrhs, double tol, int maxit, ApplyFn apply, std::vector<int>& iters,
-             const double* hscale = nullptr, BestIterate* keep = nullptr) {
+             const double* hscale = nullptr, BestIterate* keep = nullptr, bool fuse = false) {
     const long long m = (long long)c->field_elems();
     const dim3 g = vgrid(nrhs);
+    // r^H v and (t^H s, t^H t) come from the x-inverse epilogue of the operator call that writes v and t,
+    // when it can compute them (forward operator, register four-step x pass)
+    const int fblocks = fuse ? fused_dot_blocks<T>(c) : 0;
+    const long long flines = 3LL * c->n3 * c->n2;
     hipLaunchKernelGGL((k_init<T>), g, dim3(kThreads), 0, c->stream, b, ax0, r, rhat, p, v, m, c->partials);
     LS_HIP(hipGetLastError());
     int rc = finalize(c, PH_INIT, 2, nrhs, tol * tol);
@@ -458,22 +466,36 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_update_p<T>), g, dim3(kThreads), 0, c->stream, r, p, v, m, c->state);
         c->prof.end(c->stream);
-        if ((brc = apply(p, v))) return brc;
-        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
-        hipLaunchKernelGGL((k_dot<T>), g, dim3(kThreads), 0, c->stream, rhat, v, m, c->state, c->partials);
-        c->prof.end(c->stream);
-        if ((brc = finalize(c, PH_ALPHA, 2, nrhs))) return brc;
+        if (fblocks) c->dot = {1, rhat, c->dparts, flines, fblocks};
+        brc = apply(p, v);
+        c->dot = {};
+        if (brc) return brc;
+        if (fblocks) {
+            if ((brc = finalize(c, PH_ALPHA, 2, nrhs, 0.0, nullptr, c->dparts, fblocks))) return brc;
+        } else {
+            c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+            hipLaunchKernelGGL((k_dot<T>), g, dim3(kThreads), 0, c->stream, rhat, v, m, c->state, c->partials);
+            c->prof.end(c->stream);
+            if ((brc = finalize(c, PH_ALPHA, 2, nrhs))) return brc;
+        }
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_update_s<T>), g, dim3(kThreads), 0, c->stream, r, v, s, m, c->state, c->partials);
         c->prof.end(c->stream);
         if ((brc = finalize(c, PH_S, 1, nrhs))) return brc;
         hipLaunchKernelGGL((k_update_x_half<T, X>), g, dim3(kThreads), 0, c->stream, x, p, m, c->state);
         hipLaunchKernelGGL(k_clear_half, dim3(1), dim3(64), 0, c->stream, c->state, nrhs);
-        if ((brc = apply(s, t))) return brc;
-        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
-        hipLaunchKernelGGL((k_dot_ts<T>), g, dim3(kThreads), 0, c->stream, t, s, m, c->state, c->partials);
-        c->prof.end(c->stream);
-        if ((brc = finalize(c, PH_OMEGA, 3, nrhs))) return brc;
+        if (fblocks) c->dot = {2, nullptr, c->dparts, flines, fblocks};
+        brc = apply(s, t);
+        c->dot = {};
+        if (brc) return brc;
+        if (fblocks) {
+            if ((brc = finalize(c, PH_OMEGA, 3, nrhs, 0.0, nullptr, c->dparts, fblocks))) return brc;
+        } else {
+            c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+            hipLaunchKernelGGL((k_dot_ts<T>), g, dim3(kThreads), 0, c->stream, t, s, m, c->state, c->partials);
+            c->prof.end(c->stream);
+            if ((brc = finalize(c, PH_OMEGA, 3, nrhs))) return brc;
+        }
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
         hipLaunchKernelGGL((k_update_xr<T, X>), g, dim3(kThreads), 0, c->stream, x, p, s, t, r, rhat, m, c->state,
                            c->partials);
@@ -1146,7 +1168,7 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 for (int q = 0; q < nrhs; ++q) extra[q] += 1;
             }
             rc = bicgstab<double, double>(c, b, u_out, ax0, c->r, c->rhat, c->p, c->v, c->s, c->t, nrhs, tol, maxit,
-                                          apply, iters, nullptr, &best);
+                                          apply, iters, nullptr, &best, !transposed);
             if (rc) return rc;
             st.assign(c->red_host, c->red_host + (size_t)nrhs * kStateLen);
             bool broke = false;
@@ -1264,7 +1286,7 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 }
             } else {
                 rc = bicgstab<float, float>(c, c->b32, c->x32, nullptr, c->r32, c->rhat32, c->p32, c->v32, c->s32,
-                                            c->t32, nrhs, eta, maxit, apply32, iters, rel.data());
+                                            c->t32, nrhs, eta, maxit, apply32, iters, rel.data(), nullptr, !transposed);
                 if (rc) return rc;
                 for (int q = 0; q < nrhs; ++q) {
                     if (!active[q]) continue;
