@@ -97,3 +97,35 @@ def test_header_is_plain_c():
             r = subprocess.run([comp, std, "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.join(ROOT, "include"), f],
                                capture_output=True, text=True)
             assert r.returncode == 0, r.stderr
+
+
+def test_ctypes_structures_match_the_header_layout():
+    """The binding's ctypes mirrors of ls_grid, ls_options, ls_info and ls_job have the C layout: sizes and
+    field offsets printed by a C program compiled against include/ls.h."""
+    import ctypes
+    import shutil
+    import subprocess
+    import tempfile
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    from paper_2301_12836_amd import lsvie
+    structs = {"ls_grid": lsvie.Grid, "ls_options": lsvie.Options, "ls_info": lsvie.Info, "ls_job": lsvie.Job}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ls.h"', 'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(src, "w").write("\n".join(lines) + "\n")
+        r = subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
