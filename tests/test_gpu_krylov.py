@@ -122,3 +122,29 @@ def test_unconverged_solve_returns_its_best_iterate(ell):
         assert true <= 2.0 * (1 + 1e-6) * min(h.min(), 1.0)
         assert true <= h[-1] * (1 + 1e-6)
     ctx.close()
+
+
+def test_transposed_solve_and_uneven_batch_with_bicgstab_l():
+    """BiCGSTAB(4) behind the adjoint solve (A^T, no fused inner products) matches the dense transpose
+    solve, and a batch over two contexts with different grids and l matches each job's single solve."""
+    m, P = hard_problem()
+    ctx = lsvie.context_from_model(m, omegas=[W15], precision="mixed", bicgstab_l=4)
+    b = models.random_field(m.shape, 3)
+    want = solve.solve_dense(P.dense_A().T, b)
+    x, info = ctx.solve_T(torch.from_numpy(b), tol=1e-12, maxit=600, precision="c128")
+    print("solve_T l=4", rel(to_np(x), want), info, flush=True)
+    assert rel(to_np(x), want) < 1e-10
+    xm, info = ctx.solve_T(torch.from_numpy(b), tol=1e-7, maxit=600, precision="mixed")
+    assert rel(to_np(xm), want) < 1e-5
+    mb = models.random_medium((9, 7, 8), seed=8, rel=0.2, aniso_background=True)
+    B = lsvie.context_from_model(mb, omegas=[W15], precision="mixed", max_rhs=2, bicgstab_l=2)
+    jobs = [(0, 0, models.EXPLOSION, (2, 2, 3), 0.0), (1, 0, models.double_couple(30, 60, 90), (4, 3, 4), 0.0),
+            (1, 0, np.eye(6)[2], (1, 5, 6), 0.001)]
+    outs, infos = lsvie.solve_batch([ctx, B], jobs, tol=1e-10, maxit=600, precision="c128")
+    for (ci, iw, M, src, t0), u, inf in zip(jobs, outs, infos):
+        c = (ctx, B)[ci]
+        single, _ = c.solve(c.rhs_moment(M, src, i_omega=iw, t0=t0), i_omega=iw, tol=1e-10, maxit=600,
+                            precision="c128")
+        assert inf["status"] == 0 and rel(to_np(u), to_np(single)) < 1e-9, (ci, src)
+    ctx.close()
+    B.close()
