@@ -23,11 +23,12 @@ def frequency_indices(nt, dt, fp, eps):
 
 
 def seismograms(model, sources, receivers, nt, dt, fp, ts, eps=1e-6, tol=1e-8, precision="mixed", chunk=16,
-                maxit=3000, taper=0, device="cuda:0"):
+                maxit=3000, taper=0, device="cuda:0", green_mode="exact", bicgstab_l=1):
     """Traces [n_src, n_rec, 3, nt] (float64, on the device) of the displacement at the receiver cells
     [n_rec, 3] for the moment-tensor sources [(M6, (i, j, k), t0)], each with the Ricker time function of
     peak frequency fp delayed by ts; returns (traces, k, infos) with k the solved frequency indices and
-    infos the per-system solver reports."""
+    infos the per-system solver reports.  green_mode and bicgstab_l are the context options of the same
+    names (the background's own anisotropic tensor; BiCGSTAB(l) for the high frequencies)."""
     import torch
     k = frequency_indices(nt, dt, fp, eps)
     receivers = np.asarray(receivers, dtype=np.int64).reshape(-1, 3)
@@ -38,7 +39,7 @@ def seismograms(model, sources, receivers, nt, dt, fp, ts, eps=1e-6, tol=1e-8, p
         if ctx is not None:
             ctx.close()
         ctx = lsvie.context_from_model(model, precision=precision, max_rhs=nsrc, omegas=2 * np.pi * kc / (nt * dt),
-                                       taper=taper, device=device)
+                                       taper=taper, device=device, green_mode=green_mode, bicgstab_l=bicgstab_l)
         if spectra is None:
             spectra = torch.empty((len(k), nsrc, nrec, 3), dtype=torch.complex128, device=ctx.device)
         jobs = [(0, i, M, src, t0) for i in range(len(kc)) for (M, src, t0) in sources]
