@@ -117,10 +117,10 @@ def test_symmetries(rng):
             assert (err < 1e-12) if mirrored else (err > 1e-3)
 
 
-@pytest.mark.parametrize("name", ["vti", "ortho"])
+@pytest.mark.parametrize("name", ["vti", "ortho", "tti"])
 def test_self_term_is_the_ball_integral(name):
     """S = integral of G over the sphere of volume h^3: Gauss-Legendre in r and cos(theta), trapezoid in phi."""
-    C = {"vti": C_VTI, "ortho": C_ORTHO}[name]
+    C = {"vti": C_VTI, "ortho": C_ORTHO, "tti": C_TTI}[name]
     h, w = 10.0, 2 * np.pi * 25.0
     a = green.SPHERE_RADIUS_FACTOR * h
     xr, wr = leggauss(8)
