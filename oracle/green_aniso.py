@@ -81,7 +81,7 @@ def _frame(xhat):
 
 def node_counts(kr):
     """(n_u, n_phi, n_circle) for a point whose largest phase k_max r is kr."""
-    return int(np.ceil(0.3 * kr)) + 28, int(np.ceil(0.3 * kr)) + 56, 96
+    return int(np.ceil(0.3 * kr)) + 36, int(np.ceil(0.3 * kr)) + 72, 128
 
 
 def _green_points(X, omega, C, rho, n_u, n_phi, n_c):

@@ -363,11 +363,11 @@ __global__ __launch_bounds__(64) void k_green_aniso(z128* __restrict__ out, Anis
 
     // regular part: the half sphere n . x > 0, u = n . xh (Gauss-Legendre) times phi (trapezoid)
     const double kr = P.kmax * r;
-    int nu = (int)ceil(0.3 * kr) + 24;
+    int nu = (int)ceil(0.3 * kr) + 32;
     nu = min(8 * kGlLevels, (nu + 7) & ~7);
     const int lev = nu / 8;
     const double* rule = gl + 2 * (4 * lev * (lev - 1));
-    const int nphi = (int)ceil(0.3 * kr) + 48;
+    const int nphi = (int)ceil(0.3 * kr) + 64;
     double sd, cd;
     sincospi(2.0 / nphi, &sd, &cd);
     z128 acc[6] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
