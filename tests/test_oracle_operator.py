@@ -307,3 +307,15 @@ def test_bicgstab_l_reaches_lu_solution(ell):
     # the recursively updated residual is the true one
     assert abs(solve.relative_residual(P.apply_fft, x, b) - hist[-1]) < 1e-12
     assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) < 1e-10
+
+
+def test_model1_vti_folds_to_the_printed_isotropic_background():
+    from golden_fixtures import load_model1
+    """The paper's worked example: its VTI stiffness splits into the isotropic background it prints (c11 = 26.5,
+    c44 = 10.4 GPa) plus a contrast; the oracle's reference-medium rule reproduces that background."""
+    C, rho, c11, c44 = load_model1()
+    alpha, beta, c_iso = op.iso_reference(C, rho)
+    assert abs(c_iso[0, 0] - c11) < 1e-6 and abs(c_iso[3, 3] - c44) < 1e-6
+    assert abs(alpha - np.sqrt(c11 / rho)) < 1e-9 and abs(beta - np.sqrt(c44 / rho)) < 1e-9
+    total = op.unpack21(op.total_contrast21(C, rho, np.zeros((21, 1, 1, 1))))[:, :, 0, 0, 0]
+    assert np.allclose(total + c_iso, C, rtol=0, atol=1e-3)
