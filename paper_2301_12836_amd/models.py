@@ -22,6 +22,8 @@ Recipes (sizes, value ranges and structure mirror the paper's experiments):
   2400); 6 elementary moment tensors x 8 frequencies 5-40 Hz at the centre.
   It stands in for the paper's Hess/SEG model, which is not available here.
 * ``config4`` - 96^3 ellipsoid anomaly in config 2's VTI background.
+* ``paper_model2`` - the paper's own Model 2 (Table 2 stiffnesses, 320 m cube, h = 2.5 m, three layers
+  108 / 104 / 108 m thick, density 2500), for running the paper's workloads as printed.
 
 Every function also takes ``n`` so the same recipe can be drawn at small sizes
 for parity tests.
@@ -335,3 +337,37 @@ def random_medium(shape, seed, rel=0.1, h=10.0, aniso_background=False):
     dc = rel * scale * rng.uniform(-1.0, 1.0, size=(21, n3, n2, n1))
     drho = rel * rho0 * rng.uniform(-1.0, 1.0, size=(n3, n2, n1))
     return Model(tuple(shape), h, C0, rho0, dc, drho, [15.0], [], 1e-8, "random")
+
+
+# The paper's Model 2 (heterogeneous VTI model, Table 2): stiffnesses in GPa per layer as printed, in the
+# order (c11, c33, c55 = c44, c66, c13); the layers are 108, 104 and 108 m thick from the top (z = 0).
+PAPER_MODEL2_LAYERS = ((34.0, 26.5, 10.4, 11.7, 6.9),     # top VTI layer
+                       (29.05, 29.05, 10.0, 10.0, 9.05),  # isotropic layer
+                       (33.8, 21.9, 6.0, 12.0, 8.0))      # bottom VTI layer
+PAPER_MODEL2_THICKNESS = (108.0, 104.0, 108.0)
+
+
+def paper_model2(n=128, h=2.5, freqs=(50.0,), background="middle"):
+    """The paper's Model 2 on an n^3 grid of spacing h (128 x 2.5 m = 320 m as printed): cell (i, j, k) takes
+    the layer containing its centre depth k h; density 2500 everywhere; an explosion at the grid centre (in
+    the middle layer).  Background: "middle", the isotropic middle layer (zero contrast there, usable with
+    the closed-form isotropic tensor); or "mean", the thickness-weighted mean of the three VTI stiffnesses,
+    itself VTI, for the anisotropic background tensor.  The total stiffness is the same either way."""
+    rho = 2500.0
+    layers = [vti_C(*(1e9 * np.array(p))) for p in PAPER_MODEL2_LAYERS]
+    if background == "middle":
+        C0 = layers[1]
+    elif background == "mean":
+        w = np.array(PAPER_MODEL2_THICKNESS) / sum(PAPER_MODEL2_THICKNESS)
+        C0 = sum(wi * C for wi, C in zip(w, layers))
+    else:
+        raise ValueError("background must be 'middle' or 'mean'")
+    bounds = np.cumsum(PAPER_MODEL2_THICKNESS)
+    depth = np.arange(n) * h
+    which = np.searchsorted(bounds, depth, side="right").clip(0, 2)
+    dc = np.zeros((21, n, n, n))
+    for L, C in enumerate(layers):
+        dc[:, which == L] = pack21(C - C0)[:, None, None, None]
+    m = n // 2
+    return Model((n, n, n), h, C0, rho, dc, np.zeros((n, n, n)), list(map(float, freqs)), [(EXPLOSION, (m, m, m))],
+                 1e-6, "paper_model2")

@@ -23,12 +23,14 @@ def frequency_indices(nt, dt, fp, eps):
 
 
 def seismograms(model, sources, receivers, nt, dt, fp, ts, eps=1e-6, tol=1e-8, precision="mixed", chunk=16,
-                maxit=3000, taper=0, device="cuda:0", green_mode="exact", bicgstab_l=1):
+                maxit=3000, taper=0, device="cuda:0", green_mode="exact", bicgstab_l=1, raise_on_error=True):
     """Traces [n_src, n_rec, 3, nt] (float64, on the device) of the displacement at the receiver cells
     [n_rec, 3] for the moment-tensor sources [(M6, (i, j, k), t0)], each with the Ricker time function of
     peak frequency fp delayed by ts; returns (traces, k, infos) with k the solved frequency indices and
     infos the per-system solver reports.  green_mode and bicgstab_l are the context options of the same
-    names (the background's own anisotropic tensor; BiCGSTAB(l) for the high frequencies)."""
+    names (the background's own anisotropic tensor; BiCGSTAB(l) for the high frequencies).  With
+    raise_on_error=False a system that stops short of tol keeps its best iterate and reports its status in
+    infos instead of raising."""
     import torch
     k = frequency_indices(nt, dt, fp, eps)
     receivers = np.asarray(receivers, dtype=np.int64).reshape(-1, 3)
@@ -43,7 +45,8 @@ def seismograms(model, sources, receivers, nt, dt, fp, ts, eps=1e-6, tol=1e-8, p
         if spectra is None:
             spectra = torch.empty((len(k), nsrc, nrec, 3), dtype=torch.complex128, device=ctx.device)
         jobs = [(0, i, M, src, t0) for i in range(len(kc)) for (M, src, t0) in sources]
-        outs, inf = lsvie.solve_batch([ctx], jobs, tol=tol, maxit=maxit, precision=precision)
+        outs, inf = lsvie.solve_batch([ctx], jobs, tol=tol, maxit=maxit, precision=precision,
+                                      raise_on_error=raise_on_error)
         infos.extend(inf)
         for i in range(len(kc)):
             spectra[c0 + i] = ctx.sample(torch.stack(outs[i * nsrc:(i + 1) * nsrc]), receivers)

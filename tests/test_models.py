@@ -64,3 +64,18 @@ def test_anisotropic_double_couple():
     Cvti = models.vti_from_thomsen(**models.VTI_CFG2)
     M = models.double_couple_aniso(Cvti, 30, 60, 90)
     assert abs(M[0] + M[1] + M[2]) > 1e-3 * np.abs(M).max()
+
+
+def test_paper_model2_layers_and_backgrounds():
+    """Model 2: layer k takes the printed stiffness of the layer holding depth k h (boundaries at 108 and
+    212 m); both backgrounds give the same total stiffness, and the mean background is the thickness mean."""
+    mid = models.paper_model2(n=128, h=2.5)
+    mean = models.paper_model2(n=128, h=2.5, background="mean")
+    layers = [models.vti_C(*(1e9 * np.array(p))) for p in models.PAPER_MODEL2_LAYERS]
+    for k, L in ((0, 0), (43, 0), (44, 1), (84, 1), (85, 2), (127, 2)):   # 43*2.5 = 107.5, 85*2.5 = 212.5
+        want = models.pack21(layers[L])
+        assert np.allclose(mid.dc21[:, k, 5, 7] + models.pack21(mid.C0), want, rtol=0, atol=1.0)
+        assert np.allclose(mean.dc21[:, k, 3, 9] + models.pack21(mean.C0), want, rtol=0, atol=1.0)
+    assert np.array_equal(mid.C0, layers[1]) and not mid.dc21[:, 60].any()
+    assert np.allclose(mean.C0, (108 * layers[0] + 104 * layers[1] + 108 * layers[2]) / 320, rtol=1e-14)
+    assert mean.rho0 == 2500.0 and not mean.drho.any() and mid.sources[0][1] == (64, 64, 64)
