@@ -376,6 +376,34 @@ __device__ __forceinline__ void fold_index(int k, int L, int& kf, bool& flipped)
 // Fused z pass with the four-step FFT: three components per column held in registers.  Logical
 // block order (XCD-aware): right-hand side fastest, then x tiles and y rows in mirror pairs, so the
 // blocks that read the same octant rows of G^ run together on one XCD.  The data occupy z < n3 <= L/2.
+// a b + c with one rounding
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// g1 f1 + g2 f2 + g3 f3 as two chains of fused multiply-adds (12 operations instead of 16)
+template <typename T>
+__device__ __forceinline__ cpx<T> cdot3(cpx<T> g1, cpx<T> f1, cpx<T> g2, cpx<T> f2, cpx<T> g3, cpx<T> f3) {
+    T re = g1.x * f1.x, im = g1.x * f1.y;
+    re = fmadd(-g1.y, f1.y, re);
+    im = fmadd(g1.y, f1.x, im);
+    re = fmadd(g2.x, f2.x, re);
+    im = fmadd(g2.x, f2.y, im);
+    re = fmadd(-g2.y, f2.y, re);
+    im = fmadd(g2.y, f2.x, im);
+    re = fmadd(g3.x, f3.x, re);
+    im = fmadd(g3.x, f3.y, im);
+    re = fmadd(-g3.y, f3.y, re);
+    im = fmadd(g3.y, f3.x, im);
+    return {re, im};
+}
+
+// Lean forms (FP64): addresses split into a part common to the block (scalar registers) and the lane's
+// byte offset in 32 bits, so that no per-element 64-bit arithmetic is needed (the host guarantees that
+// (N1 - 1) ES + TX elements of the field and the whole table span less than 4 GiB); the 3 x 3 product as
+// fused multiply-add chains; the first forward stage skips the known-zero half.  They cut the FP64
+// kernel's vector instructions by 13 % and its time by 8 % at length 256, 6 right-hand sides; in FP32
+// they cut the instructions as much but schedule worse (0.738 against 0.728 ms), so FP32 keeps the
+// plain forms.
 template <typename T, int L, int TX, bool HALF = false>
 __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
@@ -393,21 +421,30 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void 
     const int xt = paired_row((int)((lb / nrhs) % ntx), ntx);
     const int y = paired_row((int)(lb / ((long long)nrhs * ntx)), L2);
     const int kx0 = xt * TX + t;
-    cpx<T>* base = data + (long long)rhs * RS + (long long)y * L1 + kx0;
+    constexpr bool LEAN = sizeof(T) == 8;
+    char* const ub = reinterpret_cast<char*>(data + (long long)rhs * RS + (long long)y * L1 + (long long)xt * TX);
+    const unsigned lane = ((unsigned)t + (unsigned)q * (unsigned)ES) * (unsigned)sizeof(cpx<T>);
+    // element j of component c of this thread's line
+    auto elem = [&](int c, int j) __attribute__((always_inline)) {
+        if constexpr (LEAN)   // scalar base plus the lane offset
+            return reinterpret_cast<cpx<T>*>(ub + (c * CS + (long long)(F::N1 * j) * ES) * (long long)sizeof(cpx<T>) +
+                                             lane);
+        else
+            return data + (long long)rhs * RS + (long long)y * L1 + kx0 + c * CS + (long long)(q + F::N1 * j) * ES;
+    };
     cpx<T> v[3][F::N2];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int j = 0; j < F::N2; ++j) {
+        for (int j = 0; j < (LEAN ? F::N2 / 2 : F::N2); ++j) {
             const int e = q + F::N1 * j;
-            v[c][j] = (!half_slot<L, true>(j) && e < n3) ? base[c * CS + e * ES] : cpx<T>{T(0), T(0)};
+            v[c][j] = (j < F::N2 / 2 && e < n3) ? *elem(c, j) : cpx<T>{T(0), T(0)};
         }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fs_forward<T, L, TX, -1>(v[c], lds, tws, t, q);
+    for (int c = 0; c < 3; ++c) fs_forward<T, L, TX, -1, LEAN>(v[c], lds, tws, t, q);
 
-    const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1, O3 = L / 2 + 1;
-    (void)O3;
+    const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1;
     int kx, ky;
     bool fx, fy;
     fold_index(kx0, L1, kx, fx);
@@ -415,36 +452,50 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void 
     // half-space table: k_x > L1/2 reads the entry at -k
     const bool hneg = kx0 > L1 / 2;
     const int hx = hneg ? L1 - kx0 : kx0, hy = hneg ? (L2 - y) % L2 : y;
+    const char* const gb = reinterpret_cast<const char*>(ghat);
+    auto table_at = [&](int a, int b, int n, int c) __attribute__((always_inline)) {   // entry (a n + b) O1 + c
+        if constexpr (LEAN)
+            return reinterpret_cast<const cpx<T>*>(
+                gb + (((unsigned)a * (unsigned)n + (unsigned)b) * (unsigned)O1 + (unsigned)c) * (unsigned)(6 * sizeof(cpx<T>)));
+        else
+            return ghat + (((long long)a * n + b) * O1 + c) * 6;
+    };
 #pragma unroll
     for (int i = 0; i < F::N2; ++i) {
         cpx<T> g[6];
         if constexpr (HALF) {
             const int kz0 = spectral_index<L>(q, i);
             const int hz = hneg ? (L - kz0) % L : kz0;
-            load_g6(ghat, ((long long)hz * L2 + hy) * O1 + hx, g);
+            load_g6(table_at(hz, hy, L2, hx), 0, g);
         } else {
             int kz;
             bool fz;
             fold_index(spectral_index<L>(q, i), L, kz, fz);
-            load_g6(ghat, ((long long)kz * O2 + ky) * O1 + kx, g);
+            load_g6(table_at(kz, ky, O2, kx), 0, g);
             if (fy != fz) g[3] = T(-1) * g[3];
             if (fx != fz) g[4] = T(-1) * g[4];
             if (fx != fy) g[5] = T(-1) * g[5];
         }
         const cpx<T> g11 = g[0], g22 = g[1], g33 = g[2], g23 = g[3], g13 = g[4], g12 = g[5];
         const cpx<T> f1 = v[0][i], f2 = v[1][i], f3 = v[2][i];
-        v[0][i] = g11 * f1 + g12 * f2 + g13 * f3;
-        v[1][i] = g12 * f1 + g22 * f2 + g23 * f3;
-        v[2][i] = g13 * f1 + g23 * f2 + g33 * f3;
+        if constexpr (LEAN) {
+            v[0][i] = cdot3(g11, f1, g12, f2, g13, f3);
+            v[1][i] = cdot3(g12, f1, g22, f2, g23, f3);
+            v[2][i] = cdot3(g13, f1, g23, f2, g33, f3);
+        } else {
+            v[0][i] = g11 * f1 + g12 * f2 + g13 * f3;
+            v[1][i] = g12 * f1 + g22 * f2 + g23 * f3;
+            v[2][i] = g13 * f1 + g23 * f2 + g33 * f3;
+        }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) fs_backward<T, L, TX, +1>(v[c], lds, tws, t, q);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int j = 0; j < F::N2; ++j) {
+        for (int j = 0; j < F::N2 / 2; ++j) {
             const int e = q + F::N1 * j;
-            if (!half_slot<L, true>(j) && e < n3) base[c * CS + e * ES] = v[c][j];
+            if (e < n3) *elem(c, j) = v[c][j];
         }
 }
 
@@ -548,8 +599,14 @@ int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<
     const long long CS = (long long)c->n3 * L2 * L1;
     const long long RS = 3 * CS;
     const long long ES = (long long)L2 * L1;
+    // the register kernel addresses a thread's line and the table with 32-bit byte offsets; larger
+    // grids take the LDS kernel
+    const long long table = c->green_half ? (long long)L * L2 * (L1 / 2 + 1)
+                                          : (long long)(L / 2 + 1) * (L2 / 2 + 1) * (L1 / 2 + 1);
+    const bool off32 = (16 * ES + seg_cols<T>()) * (long long)sizeof(cpx<T>) < (1LL << 32) &&
+                       table * 6 * (long long)sizeof(cpx<T>) < (1LL << 32);
     c->prof.begin(c->stream, LS_PNAME(T, "fft_z_green"));
-    const bool fs = variant == 0 && use_fourstep();
+    const bool fs = variant == 0 && use_fourstep() && off32;
     switch (L) {
 #define CASE(LL)                                                                                              \
     case LL: {                                                                                                \

@@ -22,6 +22,8 @@ __device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {  // a * (SIGN * i)
 template <int SIGN, int R, typename T>
 struct SmallDft;
 
+// run_half (lengths 2, 4, 8): the same DFT when the upper half of the input (v[j], j >= R/2) is known
+// to be zero; those elements are not read.
 template <int SIGN, typename T>
 struct SmallDft<SIGN, 2, T> {
     static __device__ __forceinline__ void run(cpx<T>* v) {
@@ -29,6 +31,7 @@ struct SmallDft<SIGN, 2, T> {
         v[0] = a + v[1];
         v[1] = a - v[1];
     }
+    static __device__ __forceinline__ void run_half(cpx<T>* v) { v[1] = v[0]; }
 };
 
 // X1,2 = a - (b + c)/2 +- SIGN i (sqrt(3)/2)(b - c)  (the cube roots of unity e^{SIGN 2 pi i/3})
@@ -54,6 +57,13 @@ struct SmallDft<SIGN, 4, T> {
         v[1] = t1 + t3;
         v[3] = t1 - t3;
     }
+    static __device__ __forceinline__ void run_half(cpx<T>* v) {
+        const cpx<T> a = v[0], b = v[1], sb = mul_si<SIGN>(v[1]);
+        v[0] = a + b;
+        v[2] = a - b;
+        v[1] = a + sb;
+        v[3] = a - sb;
+    }
 };
 
 template <int SIGN, typename T>
@@ -63,6 +73,17 @@ struct SmallDft<SIGN, 8, T> {
         cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
         SmallDft<SIGN, 4, T>::run(e);
         SmallDft<SIGN, 4, T>::run(o);
+        combine(e, o, v);
+    }
+    static __device__ __forceinline__ void run_half(cpx<T>* v) {
+        cpx<T> e[4] = {v[0], v[2]};
+        cpx<T> o[4] = {v[1], v[3]};
+        SmallDft<SIGN, 4, T>::run_half(e);
+        SmallDft<SIGN, 4, T>::run_half(o);
+        combine(e, o, v);
+    }
+    // v = the length-8 DFT from the length-4 DFTs of the even (e) and odd (o) elements
+    static __device__ __forceinline__ void combine(const cpx<T>* e, const cpx<T>* o, cpx<T>* v) {
         const T r = T(0.70710678118654752440);
         const T s = T(SIGN);
         // W8 = (1 + SIGN i)/sqrt(2);  W8^2 = SIGN i;  W8^3 = W8^2 W8

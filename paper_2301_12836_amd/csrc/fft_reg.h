@@ -47,11 +47,16 @@ __device__ __forceinline__ constexpr cpx<T> unit_root(int m) {
     return {T(c), T(SIGN * s)};
 }
 
-// In-register DFT of length N (2, 4, 8, 16, 32) with sign SIGN, natural order in and out.
-template <int SIGN, int N, typename T>
+// In-register DFT of length N (2, 4, 8, 16, 32) with sign SIGN, natural order in and out.  HALF: the
+// upper half of the input (v[j], j >= N/2) is zero and is not read; in the split n = a + 4 b every
+// length-N/4 column then has the same zero upper half.
+template <int SIGN, int N, typename T, bool HALF = false>
 __device__ __forceinline__ void reg_dft(cpx<T>* v) {
     if constexpr (N <= 8) {
-        SmallDft<SIGN, N, T>::run(v);
+        if constexpr (HALF)
+            SmallDft<SIGN, N, T>::run_half(v);
+        else
+            SmallDft<SIGN, N, T>::run(v);
     } else {
         constexpr int A = 4, B = N / A;   // n = a + A b, k = k2 + B k1
         cpx<T> tmp[N];
@@ -59,8 +64,8 @@ __device__ __forceinline__ void reg_dft(cpx<T>* v) {
         for (int a = 0; a < A; ++a) {
             cpx<T> w[B];
 #pragma unroll
-            for (int b = 0; b < B; ++b) w[b] = v[a + A * b];
-            reg_dft<SIGN, B, T>(w);
+            for (int b = 0; b < (HALF ? B / 2 : B); ++b) w[b] = v[a + A * b];
+            reg_dft<SIGN, B, T, HALF>(w);
 #pragma unroll
             for (int k2 = 0; k2 < B; ++k2) tmp[a * B + k2] = (a * k2 == 0) ? w[k2] : w[k2] * unit_root<SIGN, N, T>(a * k2);
         }
@@ -92,11 +97,12 @@ __device__ __forceinline__ cpx<T> tw_at(const cpx<T>* __restrict__ tw, int m) {
     return w;
 }
 
-// natural -> spectral, one line per column.  lds: L * TX values, free on entry; free on exit.
-template <typename T, int L, int TX, int SIGN>
+// natural -> spectral, one line per column.  lds: L * TX values, free on entry; free on exit.  HALF:
+// the upper half of the line (slots j >= N2/2 of every thread) is zero and is not read.
+template <typename T, int L, int TX, int SIGN, bool HALF = false>
 __device__ __forceinline__ void fs_forward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int q) {
     using F = FourStep<L>;
-    reg_dft<SIGN, F::N2, T>(v);
+    reg_dft<SIGN, F::N2, T, HALF>(v);
 #pragma unroll
     for (int k2 = 1; k2 < F::N2; ++k2) v[k2] = v[k2] * tw_at<SIGN>(tw, q * k2);
 #pragma unroll
