@@ -352,7 +352,8 @@ def paper_model2(n=128, h=2.5, freqs=(50.0,), background="middle"):
     the layer containing its centre depth k h; density 2500 everywhere; an explosion at the grid centre (in
     the middle layer).  Background: "middle", the isotropic middle layer (zero contrast there, usable with
     the closed-form isotropic tensor); or "mean", the thickness-weighted mean of the three VTI stiffnesses,
-    itself VTI, for the anisotropic background tensor.  The total stiffness is the same either way."""
+    itself VTI, for the anisotropic background tensor.  The stiffness inside the box is the same either way;
+    outside it, where the background continues, the two choices are different media."""
     rho = 2500.0
     layers = [vti_C(*(1e9 * np.array(p))) for p in PAPER_MODEL2_LAYERS]
     if background == "middle":
