@@ -212,8 +212,8 @@ def main():
     if args.mode == "apply-profile":
         return apply_profile(args)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver shards by "
-              "(grid, frequency) jobs across GPUs, which this build does not launch", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): sharding the independent "
+              "(grid, frequency) jobs over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
