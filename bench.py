@@ -173,6 +173,7 @@ def apply_profile(args):
 
     from paper_2301_12836_amd import lsvie, models
     model = models.config3(n=args.n)
+    log(f"model built: {args.n}^3")
     nrhs = len(model.sources)
     ctx = lsvie.context_from_model(model, precision="mixed", max_rhs=nrhs, omegas=model.omegas[-1:])
     u = torch.from_numpy(np.stack([models.random_field(model.shape, s) for s in range(nrhs)])).to(ctx.device)
