@@ -220,8 +220,9 @@ __device__ __forceinline__ void stage_twiddles(cpx<T>* tws, const cpx<T>* __rest
 }
 
 // Non-temporal access for data streamed once per pass (the caches are left to the tables).  Used where
-// it measured faster at 128^3, 6 right-hand sides: the y forward, z and x-inverse passes (c64 apply
-// 2.43 -> 2.32 ms); the x forward and y inverse passes measured slightly slower with it.
+// it measured faster at 128^3, 6 right-hand sides: the y forward, z and x-inverse passes and the loads
+// of the y inverse (c64 apply 2.43 -> 2.31 ms); the x forward and the y-inverse stores measured no faster
+// or slower with it.
 template <typename T>
 __device__ __forceinline__ cpx<T> load_nt(const cpx<T>* a) {
     return {__builtin_nontemporal_load(&a->x), __builtin_nontemporal_load(&a->y)};
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_strided(cpx<T>* __r
 #pragma unroll
         for (int i = 0; i < F::N2; ++i) {
             const int k = spectral_index<L>(q, i);
-            v[i] = k < n_in ? base[k * ES] : cpx<T>{T(0), T(0)};
+            v[i] = k < n_in ? load_nt(&base[k * ES]) : cpx<T>{T(0), T(0)};
         }
         __syncthreads();
         fs_backward<T, L, TX, SIGN>(v, lds, tws, t, q);
