@@ -40,6 +40,18 @@ __host__ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
     return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
 }
 
+// Non-temporal access for data a kernel streams once: the caches are left to data that is reused (the
+// Green's tables, the contrast shared by neighbouring blocks).
+template <typename T>
+__device__ __forceinline__ cpx<T> load_nt(const cpx<T>* a) {
+    return {__builtin_nontemporal_load(&a->x), __builtin_nontemporal_load(&a->y)};
+}
+template <typename T>
+__device__ __forceinline__ void store_nt(cpx<T>* a, cpx<T> v) {
+    __builtin_nontemporal_store(v.x, &a->x);
+    __builtin_nontemporal_store(v.y, &a->y);
+}
+
 // ------------------------------------------------------------------------------------------
 // error reporting
 

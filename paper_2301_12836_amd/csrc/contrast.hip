@@ -409,12 +409,9 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
                 const long long cpitch = (long long)N3 * L2 * L1;
                 cpx<T>* w_ = out + (long long)rhs * 3 * cpitch + ((long long)k * L2 + gy) * L1 + gx;
                 // written once and read by the next pass: non-temporal stores (measured 1-2 % faster)
-                __builtin_nontemporal_store(g0.x, &w_[0].x);
-                __builtin_nontemporal_store(g0.y, &w_[0].y);
-                __builtin_nontemporal_store(g1.x, &w_[cpitch].x);
-                __builtin_nontemporal_store(g1.y, &w_[cpitch].y);
-                __builtin_nontemporal_store(g2.x, &w_[2 * cpitch].x);
-                __builtin_nontemporal_store(g2.y, &w_[2 * cpitch].y);
+                store_nt(&w_[0], g0);
+                store_nt(&w_[cpitch], g1);
+                store_nt(&w_[2 * cpitch], g2);
             } else {
                 const cpx<T>* yr = y + (long long)rhs * 3 * n;
                 cpx<T>* o_ = out + (long long)rhs * 3 * n;

@@ -219,19 +219,9 @@ __device__ __forceinline__ void stage_twiddles(cpx<T>* tws, const cpx<T>* __rest
     for (int m = tid; m < L; m += nthreads) tws[m] = tw[m];
 }
 
-// Non-temporal access for data streamed once per pass (the caches are left to the tables).  Used where
-// it measured faster at 128^3, 6 right-hand sides: the y forward, z and x-inverse passes and the loads
-// of the y inverse (c64 apply 2.43 -> 2.31 ms); the x forward and the y-inverse stores measured no faster
-// or slower with it.
-template <typename T>
-__device__ __forceinline__ cpx<T> load_nt(const cpx<T>* a) {
-    return {__builtin_nontemporal_load(&a->x), __builtin_nontemporal_load(&a->y)};
-}
-template <typename T>
-__device__ __forceinline__ void store_nt(cpx<T>* a, cpx<T> v) {
-    __builtin_nontemporal_store(v.x, &a->x);
-    __builtin_nontemporal_store(v.y, &a->y);
-}
+// Non-temporal access (load_nt, store_nt) is used where it measured faster at 128^3, 6 right-hand
+// sides: the y forward, z and x-inverse passes and the loads of the y inverse (c64 apply 2.43 -> 2.31
+// ms); the x forward and the y-inverse stores measured no faster or slower with it.
 
 // Natural-layout element j of a line is zero by construction (PRUNE: the data occupy the first
 // half, n < L/2, which always holds for the zero-padded convolution) or beyond n_in.

@@ -70,16 +70,7 @@ __device__ __forceinline__ cpx<double> wide(cpx<T> a) {
 // Loop helper: element indices of this thread for one right-hand side of length m.
 #define LS_FOR_ELEMS(m) for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < (m); e += (long long)kRedBlocks * kThreads)
 
-// Non-temporal access for the vectors the Bi-CGSTAB updates stream once (about 1 % per solve step).
-template <typename T>
-__device__ __forceinline__ cpx<T> ldn(const cpx<T>* a) {
-    return {__builtin_nontemporal_load(&a->x), __builtin_nontemporal_load(&a->y)};
-}
-template <typename T>
-__device__ __forceinline__ void stn(cpx<T>* a, cpx<T> v) {
-    __builtin_nontemporal_store(v.x, &a->x);
-    __builtin_nontemporal_store(v.y, &a->y);
-}
+// The Bi-CGSTAB updates stream their vectors once: non-temporal access (about 1 % per solve step).
 
 // r = b - ax (ax may be null), rhat = r, p = v = 0; partials: ||b||^2, ||r||^2
 template <typename T>
@@ -115,7 +106,10 @@ __global__ __launch_bounds__(kThreads) void k_update_p(const cpx<T>* __restrict_
     const cpx<T> beta = {(T)st[S_BETA], (T)st[S_BETA + 1]};
     const cpx<T> om = {(T)st[S_OMEGA], (T)st[S_OMEGA + 1]};
     const long long off = (long long)rr * m;
-    LS_FOR_ELEMS(m) { stn(&p[off + e], ldn(&r[off + e]) + beta * (ldn(&p[off + e]) - om * ldn(&v[off + e]))); }
+    LS_FOR_ELEMS(m) {
+        const cpx<T> pv = load_nt(&p[off + e]), vv = load_nt(&v[off + e]);
+        store_nt(&p[off + e], load_nt(&r[off + e]) + beta * (pv - om * vv));
+    }
 }
 
 // partials: r^H v (complex)
@@ -148,8 +142,8 @@ __global__ __launch_bounds__(kThreads) void k_update_s(const cpx<T>* __restrict_
     const long long off = (long long)rr * m;
     double ss = 0;
     LS_FOR_ELEMS(m) {
-        const cpx<T> sv = ldn(&r[off + e]) - al * ldn(&v[off + e]);
-        stn(&s[off + e], sv);
+        const cpx<T> sv = load_nt(&r[off + e]) - al * load_nt(&v[off + e]);
+        store_nt(&s[off + e], sv);
         ss += (double)sv.x * sv.x + (double)sv.y * sv.y;
     }
     write_partials(partials, rr, 0, ss, 0.0, sh);
@@ -208,13 +202,14 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(cpx<X>* __restrict__ x, 
     const long long off = (long long)rr * m;
     double nr = 0, re = 0, im = 0;
     LS_FOR_ELEMS(m) {
-        const cpx<T> pv = ldn(&p[off + e]), sv = ldn(&s[off + e]);
-        stn(&x[off + e], ldn(&x[off + e]) + alx * cpx<X>{(X)pv.x, (X)pv.y} + omx * cpx<X>{(X)sv.x, (X)sv.y});
-        const cpx<T> rv = sv - om * ldn(&t[off + e]);
-        stn(&r[off + e], rv);
+        const cpx<T> pv = load_nt(&p[off + e]), sv = load_nt(&s[off + e]);
+        const cpx<X> xv = load_nt(&x[off + e]);
+        store_nt(&x[off + e], xv + alx * cpx<X>{(X)pv.x, (X)pv.y} + omx * cpx<X>{(X)sv.x, (X)sv.y});
+        const cpx<T> rv = sv - om * load_nt(&t[off + e]);
+        store_nt(&r[off + e], rv);
         const cpx<double> rw = wide(rv);
         nr += rw.x * rw.x + rw.y * rw.y;
-        const cpx<double> z = cmulc(wide(ldn(&rhat[off + e])), rw);
+        const cpx<double> z = cmulc(wide(load_nt(&rhat[off + e])), rw);
         re += z.x;
         im += z.y;
     }
