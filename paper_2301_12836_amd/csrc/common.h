@@ -52,6 +52,17 @@ __device__ __forceinline__ void store_nt(cpx<T>* a, cpx<T> v) {
     __builtin_nontemporal_store(v.y, &a->y);
 }
 
+// Padded work buffer [rhs][component][z][y][x] with z planes in blocks of B = 2^zbs interleaved row by row:
+// row y of plane z sits at (z / B) L2 B L1 + (y B + z mod B) L1, so the rows of one z block are
+// contiguous and a z line spans N3 / B blocks instead of N3 planes (fewer pages per block of the z
+// pass).  zbs = 0 is the plain [z][y][x] layout.
+__host__ __device__ __forceinline__ long long zplane_offset(int z, int zbs, int L2, int L1) {
+    return ((long long)(z >> zbs) * L2 << zbs) * L1 + (long long)(z & ((1 << zbs) - 1)) * L1;
+}
+__host__ __device__ __forceinline__ long long zrow_offset(int y, int zbs, int L1) {
+    return ((long long)y << zbs) * L1;
+}
+
 // ------------------------------------------------------------------------------------------
 // error reporting
 
@@ -89,6 +100,7 @@ struct Profiler {
 struct Ctx {
     int n1 = 0, n2 = 0, n3 = 0;   // cells per axis (x, y, z)
     int L1 = 0, L2 = 0, L3 = 0;   // FFT lengths per axis (>= 2n - 1, supported sizes)
+    int zbs = 0;                  // log2 of the z planes interleaved per block of the padded work buffer (below)
     long long ncell = 0;
     double h = 0;
     int mixed = 0;

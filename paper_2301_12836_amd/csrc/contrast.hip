@@ -114,13 +114,13 @@ __global__ __launch_bounds__(kThreads) void k_strain_stress(const cpx<T>* __rest
 }
 
 // f_c(p) = -sum_a (D_a^T tau_{V(a,c)})(p) + w^2 drho(p) u_c(p).
-// OUT 0: f written to work[r][c][z][y][x] (row pitch L1, plane pitch L2 L1, component pitch N3 L2 L1).
+// OUT 0: f written to the padded work buffer (layout of zplane_offset; component pitch N3 L2 L1).
 // OUT 1: the transposed operator's epilogue, work[compact] = y - f (work is then a compact field array).
 template <typename T, int OUT>
 __global__ __launch_bounds__(kThreads) void k_divergence(const cpx<T>* __restrict__ tau, const cpx<T>* __restrict__ u,
                                                          const T* __restrict__ drho, cpx<T>* __restrict__ work,
                                                          int nrhs, int N1, int N2, int N3, int L1, int L2, T inv_h,
-                                                         T w2, const cpx<T>* __restrict__ y) {
+                                                         T w2, const cpx<T>* __restrict__ y, int zbs) {
     const long long n = (long long)N1 * N2 * N3;
     const long long lb = xcd_logical_block(blockIdx.x, (n + kThreads - 1) / kThreads);
     const long long p = lb * kThreads + threadIdx.x;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void k_divergence(const cpx<T>* __restric
     const long long sx = 1, sy = N1, sz = (long long)N1 * N2;
     const T wr = w2 * drho[p];
     const long long cpitch = (long long)N3 * L2 * L1;
-    const long long wpos = ((long long)k * L2 + j) * L1 + i;
+    const long long wpos = zplane_offset(k, zbs, L2, L1) + zrow_offset(j, zbs, L1) + i;
     for (int r = 0; r < nrhs; ++r) {
         const cpx<T>* t = tau + (long long)r * 6 * n;
         const cpx<T>* ur = u + (long long)r * 3 * n;
@@ -205,7 +205,7 @@ template <typename T, int BX, int BY, int NT, int MINB, bool DB, int OUT>
 __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     const cpx<T>* __restrict__ u, const T* __restrict__ dc, const T* __restrict__ drho, cpx<T>* __restrict__ out,
     const cpx<T>* __restrict__ y, int nrhs, int N1, int N2, int N3, int L1, int L2, T inv_h, T w2, int tx, int ty,
-    int nzc, long long nb_real) {
+    int nzc, long long nb_real, int zbs) {
     constexpr int NOWN = BX * BY;
     constexpr int UX = BX + 4, UY = BY + 4, UP = UX * UY;  // u plane (halo 2)
     constexpr int SX = BX + 2, SY = BY + 2, SP = SX * SY;  // tau plane (halo 1)
@@ -407,7 +407,7 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
             const cpx<T> g0 = wr * uk[0] - f0, g1 = wr * uk[UP] - f1, g2 = wr * uk[2 * UP] - f2;
             if constexpr (OUT == 0) {
                 const long long cpitch = (long long)N3 * L2 * L1;
-                cpx<T>* w_ = out + (long long)rhs * 3 * cpitch + ((long long)k * L2 + gy) * L1 + gx;
+                cpx<T>* w_ = out + (long long)rhs * 3 * cpitch + zplane_offset(k, zbs, L2, L1) + zrow_offset(gy, zbs, L1) + gx;
                 // written once and read by the next pass: non-temporal stores (measured 1-2 % faster)
                 store_nt(&w_[0], g0);
                 store_nt(&w_[cpitch], g1);
@@ -440,10 +440,10 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     }
 }
 
-// compact field f[r][c][n] -> zero-padded work[r][c][z][y][x] (data cells only)
+// compact field f[r][c][n] -> zero-padded work buffer (layout of zplane_offset; data cells only)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_to_work(const cpx<T>* __restrict__ f, cpx<T>* __restrict__ work,
-                                                      int nrhs, int N1, int N2, int N3, int L1, int L2) {
+                                                      int nrhs, int N1, int N2, int N3, int L1, int L2, int zbs) {
     const long long n = (long long)N1 * N2 * N3;
     const long long p = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (p >= n) return;
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(kThreads) void k_to_work(const cpx<T>* __restrict__
     const int j = (int)((p / N1) % N2);
     const int k = (int)(p / ((long long)N1 * N2));
     const long long cpitch = (long long)N3 * L2 * L1;
-    const long long wpos = ((long long)k * L2 + j) * L1 + i;
+    const long long wpos = zplane_offset(k, zbs, L2, L1) + zrow_offset(j, zbs, L1) + i;
     for (int r = 0; r < 3 * nrhs; ++r) work[r * cpitch + wpos] = f[r * n + p];
 }
 
@@ -648,7 +648,7 @@ int launch_fused(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* out, const cpx<T>
     c->prof.begin(c->stream, OUT == 0 ? LS_PNAME(T, "contrast_fused") : LS_PNAME(T, "contrast_fused_T"));
     hipLaunchKernelGGL((k_contrast_zmarch<T, S::BX, S::BY, S::NT, S::PER_CU, S::DB, OUT>), dim3(nbl), dim3(S::NT), 0,
                        c->stream, u, contrast_of<T>(c), density_of<T>(c), out, y, nrhs, c->n1, c->n2, c->n3, c->L1,
-                       c->L2, T(1.0 / c->h), T(w * w), tx, ty, nzc, nb);
+                       c->L2, T(1.0 / c->h), T(w * w), tx, ty, nzc, nb, c->zbs);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
@@ -669,7 +669,7 @@ int contrast_to_work(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* work, cpx<T>*
     LS_HIP(hipGetLastError());
     c->prof.begin(c->stream, LS_PNAME(T, "contrast_divergence"));
     hipLaunchKernelGGL((k_divergence<T, 0>), dim3(nb), dim3(kThreads), 0, c->stream, tau, u, density_of<T>(c), work,
-                       nrhs, c->n1, c->n2, c->n3, c->L1, c->L2, inv_h, T(w * w), nullptr);
+                       nrhs, c->n1, c->n2, c->n3, c->L1, c->L2, inv_h, T(w * w), nullptr, c->zbs);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
@@ -694,7 +694,7 @@ int contrast_transposed_epilogue(Ctx* c, int i_omega, const cpx<T>* g, const cpx
     LS_HIP(hipGetLastError());
     c->prof.begin(c->stream, LS_PNAME(T, "contrast_divergence_T"));
     hipLaunchKernelGGL((k_divergence<T, 1>), dim3(nb), dim3(kThreads), 0, c->stream, tau, g, density_of<T>(c), out,
-                       nrhs, c->n1, c->n2, c->n3, c->L1, c->L2, inv_h, T(w * w), y);
+                       nrhs, c->n1, c->n2, c->n3, c->L1, c->L2, inv_h, T(w * w), y, c->zbs);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
@@ -709,7 +709,7 @@ int to_work(Ctx* c, const cpx<T>* f, cpx<T>* work, int nrhs) {
     const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
     c->prof.begin(c->stream, LS_PNAME(T, "to_work"));
     hipLaunchKernelGGL((k_to_work<T>), dim3(nb), dim3(kThreads), 0, c->stream, f, work, nrhs, c->n1, c->n2, c->n3,
-                       c->L1, c->L2);
+                       c->L1, c->L2, c->zbs);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;

@@ -40,12 +40,22 @@ constexpr int zpass_cols() {
     return tx >= 8 ? 8 : (tx >= 4 ? 4 : (tx >= 2 ? 2 : 1));
 }
 
+// Row of the compact field [.. component ..][z][y] that x line `line` of the padded work buffer holds:
+// with z blocks of 2^zbs planes (zplane_offset) the lines of a block run (y, z mod B) with z fastest,
+// D2 = N2 B lines per block; zbs = 0 is the identity.
+__device__ __forceinline__ long long compact_row(long long line, int D2, int zbs) {
+    if (zbs == 0) return line;
+    const long long g = line / D2, rem = line - g * D2;
+    return g * D2 + (rem & ((1 << zbs) - 1)) * (D2 >> zbs) + (rem >> zbs);
+}
+
 // MODE 0: in place into data; 1: out = u - v (compact); 2: out = v (compact)
 template <typename T, int L, int TY, int SIGN, int MODE>
 __global__ __launch_bounds__(kThreads) void k_fft_contig(cpx<T>* __restrict__ data, long long nlines, int D2,
                                                          long long S1, long long S2, int n_in, int n_out,
                                                          const cpx<T>* __restrict__ tw,
-                                                         const cpx<T>* __restrict__ u, cpx<T>* __restrict__ out) {
+                                                         const cpx<T>* __restrict__ u, cpx<T>* __restrict__ out,
+                                                         int zbs) {
     constexpr int LDP = TY + 1;
     __shared__ cpx<T> s[L * LDP];
     const int tid = threadIdx.x;
@@ -71,7 +81,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_contig(cpx<T>* __restrict__ da
                 const long long o1 = line / D2, o2 = line - o1 * D2;
                 data[o1 * S1 + o2 * S2 + e] = v;
             } else {
-                const long long q = line * n_out + e;   // compact [.. lines ..][n_out]
+                const long long q = compact_row(line, D2, zbs) * n_out + e;   // compact [.. rows ..][n_out]
                 if constexpr (MODE == 1)
                     out[q] = u[q] - v;
                 else
@@ -139,18 +149,19 @@ template <typename T, int L, int TX, bool HALF = false>
 __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1, int L2,
                                                          long long CS, long long RS, long long ES, int n3,
                                                          const cpx<T>* __restrict__ ghat,
-                                                         const cpx<T>* __restrict__ tw) {
+                                                         const cpx<T>* __restrict__ tw, int zbs) {
     constexpr int NL = 3 * TX;
     __shared__ cpx<T> s[L * NL];
     const int tid = threadIdx.x;
     const int rhs = blockIdx.x % nrhs;
     const int x0 = (blockIdx.x / nrhs) * TX;
     const int y = paired_row(blockIdx.y, L2);
-    cpx<T>* base = data + (long long)rhs * RS + (long long)y * L1 + x0;
+    (void)ES;   // the plane pitch: element offsets follow zplane_offset
+    cpx<T>* base = data + (long long)rhs * RS + zrow_offset(y, zbs, L1) + x0;
     for (int idx = tid; idx < L * NL; idx += kThreads) {
         const int t = idx % TX, c = (idx / TX) % 3, e = idx / NL;
         cpx<T> val = {T(0), T(0)};
-        if (e < n3) val = base[c * CS + e * ES + t];
+        if (e < n3) val = base[c * CS + zplane_offset(e, zbs, L2, L1) + t];
         s[e * NL + c * TX + t] = val;
     }
     __syncthreads();
@@ -187,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ da
     lds_fft<T, L, NL, NL, kThreads, +1>(s, tw, tid);
     for (int idx = tid; idx < L * NL; idx += kThreads) {
         const int t = idx % TX, c = (idx / TX) % 3, e = idx / NL;
-        if (e < n3) base[c * CS + e * ES + t] = s[e * NL + c * TX + t];
+        if (e < n3) base[c * CS + zplane_offset(e, zbs, L2, L1) + t] = s[e * NL + c * TX + t];
     }
 }
 
@@ -287,7 +298,8 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
                                                                     cpx<T>* __restrict__ out,
                                                                     const cpx<T>* __restrict__ dot_a = nullptr,
                                                                     double* __restrict__ dot_parts = nullptr,
-                                                                    long long dot_lines = 1, int dot_nparts = 0) {
+                                                                    long long dot_lines = 1, int dot_nparts = 0,
+                                                                    int zbs = 0) {
     using F = FourStep<L>;
     constexpr int LDP = TY + 1;
     __shared__ cpx<T> lds[L * LDP];
@@ -328,7 +340,7 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
             for (int j = 0; j < F::N2; ++j) {
                 const int e = q + F::N1 * j;
                 if (!half_slot<L, PRUNE>(j) && e < n_out) {
-                    const long long qq = line * n_out + e;
+                    const long long qq = compact_row(line, D2, zbs) * n_out + e;
                     if constexpr (MODE == 1) {
                         const cpx<T> uu = load_nt(&u[qq]);
                         const cpx<T> o = uu - v[j];
@@ -412,7 +424,8 @@ template <typename T, int L, int TX, bool HALF = false>
 __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
                                                                     int n3, const cpx<T>* __restrict__ ghat,
-                                                                    const cpx<T>* __restrict__ tw, long long nb_real) {
+                                                                    const cpx<T>* __restrict__ tw, long long nb_real,
+                                                                    int zbs) {
     using F = FourStep<L>;
     __shared__ cpx<T> lds[L * TX];
     __shared__ cpx<T> tws[L];
@@ -426,15 +439,20 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void 
     const int y = paired_row((int)(lb / ((long long)nrhs * ntx)), L2);
     const int kx0 = xt * TX + t;
     constexpr bool LEAN = sizeof(T) == 8;
-    char* const ub = reinterpret_cast<char*>(data + (long long)rhs * RS + (long long)y * L1 + (long long)xt * TX);
-    const unsigned lane = ((unsigned)t + (unsigned)q * (unsigned)ES) * (unsigned)sizeof(cpx<T>);
+    // work buffer layout of zplane_offset: element e of a line at (e >> zbs) ZS + (e mod 2^zbs) L1, ZS the
+    // z-block pitch; 2^zbs divides N1 (host), so thread q's part of that offset is the same for all its elements
+    const long long ZS = ES << zbs;
+    char* const ub = reinterpret_cast<char*>(data + (long long)rhs * RS + zrow_offset(y, zbs, L1) + (long long)xt * TX);
+    const unsigned lane = ((unsigned)t + (unsigned)(q >> zbs) * (unsigned)ZS + (unsigned)(q & ((1 << zbs) - 1)) * (unsigned)L1) *
+                          (unsigned)sizeof(cpx<T>);
     // element j of component c of this thread's line
     auto elem = [&](int c, int j) __attribute__((always_inline)) {
         if constexpr (LEAN)   // scalar base plus the lane offset
-            return reinterpret_cast<cpx<T>*>(ub + (c * CS + (long long)(F::N1 * j) * ES) * (long long)sizeof(cpx<T>) +
+            return reinterpret_cast<cpx<T>*>(ub + (c * CS + (long long)((F::N1 >> zbs) * j) * ZS) * (long long)sizeof(cpx<T>) +
                                              lane);
         else
-            return data + (long long)rhs * RS + (long long)y * L1 + kx0 + c * CS + (long long)(q + F::N1 * j) * ES;
+            return data + (long long)rhs * RS + zrow_offset(y, zbs, L1) + kx0 + c * CS +
+                   zplane_offset(q + F::N1 * j, zbs, L2, L1);
     };
     cpx<T> v[3][F::N2];
 #pragma unroll
@@ -530,7 +548,8 @@ bool use_fourstep() {
 
 template <typename T, int SIGN, int MODE, bool PRUNE, int DOT = 0>
 int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long long S1, long long S2, int n_in,
-                  int n_out, const cpx<T>* tw, const cpx<T>* u, cpx<T>* out, const char* name, int variant = 0) {
+                  int n_out, const cpx<T>* tw, const cpx<T>* u, cpx<T>* out, const char* name, int variant = 0,
+                  int zbs = 0) {
     c->prof.begin(c->stream, name);
     const bool fs = variant == 0 && use_fourstep();
     if (DOT != 0 && !fs) return fail(LS_ERR_STATE, "fused inner products need the register four-step x pass");
@@ -544,7 +563,7 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
                 hipLaunchKernelGGL((k_fs_contig<T, LL, TY, SIGN, MODE, PRUNE, DOT>), dim3((unsigned)nb),             \
                                    dim3(fs_threads<T, LL>()), 0, c->stream, data, nlines, D2, S1, S2, n_in,  \
                                    n_out, tw, u, out, (const cpx<T>*)c->dot.a, c->dot.parts, c->dot.lines,   \
-                                   c->dot.nparts);                                                           \
+                                   c->dot.nparts, zbs);                                                      \
                 break;                                                                                       \
             }                                                                                                \
         }                                                                                                    \
@@ -552,7 +571,7 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
         constexpr int TY = contig_lines<T, LL>();                                                            \
         const long long nb = (nlines + TY - 1) / TY;                                                         \
         hipLaunchKernelGGL((k_fft_contig<T, LL, TY, SIGN, MODE>), dim3((unsigned)nb), dim3(kThreads), 0,     \
-                           c->stream, data, nlines, D2, S1, S2, n_in, n_out, tw, u, out);                    \
+                           c->stream, data, nlines, D2, S1, S2, n_in, n_out, tw, u, out, zbs);               \
         break;                                                                                               \
     }
         LS_FOR_LENGTHS(CASE)
@@ -616,7 +635,8 @@ int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<
 #define CASE(LL)                                                                                              \
     case LL: {                                                                                                \
         if constexpr (fs_z_ok<T, LL>()) {                                                                     \
-            if (fs) {                                                                                         \
+            /* the register kernel needs 2^zbs to divide the threads per line */                              \
+            if (fs && (fs_threads<T, LL>() / seg_cols<T>()) % (1 << c->zbs) == 0) {                          \
                 constexpr int TX = seg_cols<T>();                                                             \
                 if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");           \
                 const long long nb = (long long)nrhs * (L1 / TX) * L2;                                        \
@@ -624,11 +644,11 @@ int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<
                 if (c->green_half)                                                                            \
                     hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX, true>), dim3((unsigned)nb_launch),             \
                                        dim3(fs_threads<T, LL>()), 0, c->stream, data, nrhs, L1, L2, CS, RS,   \
-                                       ES, c->n3, ghat, tw, nb);                                              \
+                                       ES, c->n3, ghat, tw, nb, c->zbs);                                      \
                 else                                                                                          \
                     hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX>), dim3((unsigned)nb_launch),                   \
                                        dim3(fs_threads<T, LL>()), 0, c->stream, data, nrhs, L1, L2, CS, RS,   \
-                                       ES, c->n3, ghat, tw, nb);                                              \
+                                       ES, c->n3, ghat, tw, nb, c->zbs);                                      \
                 break;                                                                                        \
             }                                                                                                 \
         }                                                                                                     \
@@ -636,10 +656,10 @@ int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<
         if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");                   \
         if (c->green_half)                                                                                    \
             hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX, true>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), \
-                               0, c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw);                \
+                               0, c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw, c->zbs);        \
         else                                                                                                  \
             hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), 0,    \
-                               c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw);                   \
+                               c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw, c->zbs);           \
         break;                                                                                                \
     }
         LS_FOR_LENGTHS(CASE)
@@ -684,30 +704,38 @@ int run_pass(Ctx* c, int pass, int variant, int i_omega, cpx<T>* work, const cpx
     const int N1 = c->n1, N2 = c->n2, N3 = c->n3, L1 = c->L1, L2 = c->L2, L3 = c->L3;
     const long long rc = 3LL * nrhs;
     const long long plane = (long long)L2 * L1;
+    // work buffer layout (zplane_offset): x lines run over z blocks (stride plane B) and the N2 B data rows of
+    // a block (stride L1); y lines over z blocks and the B planes of a block, with elements B L1 apart
+    const int zbs = c->zbs, B = 1 << zbs;
+    const long long zblock = plane << zbs;
     switch (pass) {
         case 0:  // x forward on the N2 x N3 data lines
-            return launch_contig<T, -1, 0, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, N1, L1, twiddles<T>(c, L1),
-                                                 nullptr, nullptr, LS_PNAME(T, "fft_x_fwd"), variant);
+            return launch_contig<T, -1, 0, true>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, N1, L1,
+                                                 twiddles<T>(c, L1), nullptr, nullptr, LS_PNAME(T, "fft_x_fwd"), variant,
+                                                 zbs);
         case 1:  // y forward on all L1 columns of the N3 data planes
-            return launch_strided<T, -1, true>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, N2, L2,
-                                               twiddles<T>(c, L2), LS_PNAME(T, "fft_y_fwd"), variant);
+            return launch_strided<T, -1, true>(c, L2, work, L1, B, (int)((rc * N3) >> zbs), zblock, L1, (long long)L1 * B,
+                                               N2, L2, twiddles<T>(c, L2), LS_PNAME(T, "fft_y_fwd"), variant);
         case 2:
             return launch_zgreen<T>(c, work, nrhs, green_table<T>(c, i_omega), twiddles<T>(c, L3), variant);
         case 3:
-            return launch_strided<T, +1, true>(c, L2, work, L1, 1, (int)(rc * N3), plane, 0, L1, L2, N2,
-                                               twiddles<T>(c, L2), LS_PNAME(T, "fft_y_inv"), variant);
+            return launch_strided<T, +1, true>(c, L2, work, L1, B, (int)((rc * N3) >> zbs), zblock, L1, (long long)L1 * B,
+                                               L2, N2, twiddles<T>(c, L2), LS_PNAME(T, "fft_y_inv"), variant);
         default:
             if (subtract_from_u && c->dot.mode == 1)
-                return launch_contig<T, +1, 1, true, 1>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1,
-                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant);
+                return launch_contig<T, +1, 1, true, 1>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, L1, N1,
+                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant,
+                                                        zbs);
             if (subtract_from_u && c->dot.mode == 2)
-                return launch_contig<T, +1, 1, true, 2>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1,
-                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant);
+                return launch_contig<T, +1, 1, true, 2>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, L1, N1,
+                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant,
+                                                        zbs);
             if (subtract_from_u)
-                return launch_contig<T, +1, 1, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1,
-                                                     twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant);
-            return launch_contig<T, +1, 2, true>(c, L1, work, rc * N3 * N2, N2, plane, L1, L1, N1, twiddles<T>(c, L1),
-                                                 u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant);
+                return launch_contig<T, +1, 1, true>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, L1, N1,
+                                                     twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant,
+                                                     zbs);
+            return launch_contig<T, +1, 2, true>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, L1, N1,
+                                                 twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant, zbs);
     }
 }
 
