@@ -145,11 +145,12 @@ __device__ __forceinline__ void load_g6(const z128* __restrict__ ghat, long long
 // k_a -> L_a - k_a an off-diagonal component ij changes sign once for each of i, j equal to a.
 // HALF: G^ holds the half-space [L3][L2][L1/2+1][6] (backgrounds without the mirror planes) and
 // k_x > L1/2 reads the entry at -k (G^ is even), with no sign change.
-template <typename T, int L, int TX, bool HALF = false>
+template <typename T, int L, int TX, bool HALF = false, int ZBS = 0>
 __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1, int L2,
                                                          long long CS, long long RS, long long ES, int n3,
                                                          const cpx<T>* __restrict__ ghat,
-                                                         const cpx<T>* __restrict__ tw, int zbs) {
+                                                         const cpx<T>* __restrict__ tw) {
+    constexpr int zbs = ZBS;   // work buffer layout (zplane_offset), fixed at compile time
     constexpr int NL = 3 * TX;
     __shared__ cpx<T> s[L * NL];
     const int tid = threadIdx.x;
@@ -420,13 +421,13 @@ __device__ __forceinline__ cpx<T> cdot3(cpx<T> g1, cpx<T> f1, cpx<T> g2, cpx<T> 
 // kernel's vector instructions by 13 % and its time by 8 % at length 256, 6 right-hand sides; in FP32
 // they cut the instructions as much but schedule worse (0.738 against 0.728 ms), so FP32 keeps the
 // plain forms.
-template <typename T, int L, int TX, bool HALF = false>
+template <typename T, int L, int TX, bool HALF = false, int ZBS = 0>
 __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
                                                                     int n3, const cpx<T>* __restrict__ ghat,
-                                                                    const cpx<T>* __restrict__ tw, long long nb_real,
-                                                                    int zbs) {
+                                                                    const cpx<T>* __restrict__ tw, long long nb_real) {
     using F = FourStep<L>;
+    constexpr int zbs = ZBS;   // work buffer layout (zplane_offset), fixed at compile time
     __shared__ cpx<T> lds[L * TX];
     __shared__ cpx<T> tws[L];
     const long long lb = xcd_logical_block(blockIdx.x, nb_real);
@@ -617,6 +618,29 @@ int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long lon
     return LS_OK;
 }
 
+// z-pass launches for one layout (ZBS, compile time): register kernel / LDS kernel, full or half table
+template <typename T, int LL, int TX, int ZBS>
+void launch_fs_z(Ctx* c, unsigned nbl, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES,
+                 const cpx<T>* ghat, const cpx<T>* tw, long long nb) {
+    if (c->green_half)
+        hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX, true, ZBS>), dim3(nbl), dim3(fs_threads<T, LL>()), 0, c->stream,
+                           data, nrhs, c->L1, c->L2, CS, RS, ES, c->n3, ghat, tw, nb);
+    else
+        hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX, false, ZBS>), dim3(nbl), dim3(fs_threads<T, LL>()), 0, c->stream,
+                           data, nrhs, c->L1, c->L2, CS, RS, ES, c->n3, ghat, tw, nb);
+}
+template <typename T, int LL, int TX, int ZBS>
+void launch_lds_z(Ctx* c, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES, const cpx<T>* ghat,
+                  const cpx<T>* tw) {
+    const dim3 grid(nrhs * (c->L1 / TX), c->L2, 1);
+    if (c->green_half)
+        hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX, true, ZBS>), grid, dim3(kThreads), 0, c->stream, data, nrhs,
+                           c->L1, c->L2, CS, RS, ES, c->n3, ghat, tw);
+    else
+        hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX, false, ZBS>), grid, dim3(kThreads), 0, c->stream, data, nrhs,
+                           c->L1, c->L2, CS, RS, ES, c->n3, ghat, tw);
+}
+
 template <typename T>
 int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<T>* tw, int variant = 0) {
     const int L1 = c->L1, L2 = c->L2, L = c->L3;
@@ -640,26 +664,20 @@ int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<
                 constexpr int TX = seg_cols<T>();                                                             \
                 if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");           \
                 const long long nb = (long long)nrhs * (L1 / TX) * L2;                                        \
-                const long long nb_launch = (nb + 7) / 8 * 8;                                                 \
-                if (c->green_half)                                                                            \
-                    hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX, true>), dim3((unsigned)nb_launch),             \
-                                       dim3(fs_threads<T, LL>()), 0, c->stream, data, nrhs, L1, L2, CS, RS,   \
-                                       ES, c->n3, ghat, tw, nb, c->zbs);                                      \
+                const unsigned nbl = (unsigned)((nb + 7) / 8 * 8);                                            \
+                if (c->zbs)                                                                                   \
+                    launch_fs_z<T, LL, TX, 3>(c, nbl, data, nrhs, CS, RS, ES, ghat, tw, nb);                  \
                 else                                                                                          \
-                    hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX>), dim3((unsigned)nb_launch),                   \
-                                       dim3(fs_threads<T, LL>()), 0, c->stream, data, nrhs, L1, L2, CS, RS,   \
-                                       ES, c->n3, ghat, tw, nb, c->zbs);                                      \
+                    launch_fs_z<T, LL, TX, 0>(c, nbl, data, nrhs, CS, RS, ES, ghat, tw, nb);                  \
                 break;                                                                                        \
             }                                                                                                 \
         }                                                                                                     \
         constexpr int TX = zpass_cols<T, LL>();                                                               \
         if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");                   \
-        if (c->green_half)                                                                                    \
-            hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX, true>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), \
-                               0, c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw, c->zbs);        \
+        if (c->zbs)                                                                                           \
+            launch_lds_z<T, LL, TX, 3>(c, data, nrhs, CS, RS, ES, ghat, tw);                                  \
         else                                                                                                  \
-            hipLaunchKernelGGL((k_fft_zgreen<T, LL, TX>), dim3(nrhs * (L1 / TX), L2, 1), dim3(kThreads), 0,    \
-                               c->stream, data, nrhs, L1, L2, CS, RS, ES, c->n3, ghat, tw, c->zbs);           \
+            launch_lds_z<T, LL, TX, 0>(c, data, nrhs, CS, RS, ES, ghat, tw);                                  \
         break;                                                                                                \
     }
         LS_FOR_LENGTHS(CASE)
