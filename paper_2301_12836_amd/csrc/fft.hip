@@ -422,11 +422,12 @@ __device__ __forceinline__ cpx<T> cdot3(cpx<T> g1, cpx<T> f1, cpx<T> g2, cpx<T> 
 // they cut the instructions as much but schedule worse (0.738 against 0.728 ms), so FP32 keeps the
 // plain forms.
 template <typename T, int L, int TX, bool HALF = false, int ZBS = 0>
-__global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
+__global__ __launch_bounds__((TX * ZSplit<L, HALF>::N1), (sizeof(T) == 4 ? (z_paired<L, HALF>() ? 2 : 3) : 1)) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
                                                                     int n3, const cpx<T>* __restrict__ ghat,
                                                                     const cpx<T>* __restrict__ tw, long long nb_real) {
-    using F = FourStep<L>;
+    using F = ZSplit<L, HALF>;
+    constexpr bool PAIRED = z_paired<L, HALF>();
     constexpr int zbs = ZBS;   // work buffer layout (zplane_offset), fixed at compile time
     __shared__ cpx<T> lds[L * TX];
     __shared__ cpx<T> tws[L];
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void 
         }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fs_forward<T, L, TX, -1, LEAN>(v[c], lds, tws, t, q);
+    for (int c = 0; c < 3; ++c) z_forward<T, L, TX, -1, PAIRED, LEAN>(v[c], lds, tws, t, q);
 
     const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1;
     int kx, ky;
@@ -488,13 +489,13 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void 
     for (int i = 0; i < F::N2; ++i) {
         cpx<T> g[6];
         if constexpr (HALF) {
-            const int kz0 = spectral_index<L>(q, i);
+            const int kz0 = z_spectral_index<L, PAIRED>(q, i);
             const int hz = hneg ? (L - kz0) % L : kz0;
             load_g6(table_at(hz, hy, L2, hx), 0, g);
         } else {
             int kz;
             bool fz;
-            fold_index(spectral_index<L>(q, i), L, kz, fz);
+            fold_index(z_spectral_index<L, PAIRED>(q, i), L, kz, fz);
             load_g6(table_at(kz, ky, O2, kx), 0, g);
             if (fy != fz) g[3] = T(-1) * g[3];
             if (fx != fz) g[4] = T(-1) * g[4];
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void 
         }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) fs_backward<T, L, TX, +1>(v[c], lds, tws, t, q);
+    for (int c = 0; c < 3; ++c) z_backward<T, L, TX, +1, PAIRED>(v[c], lds, tws, t, q);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -523,13 +524,13 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1, sizeof(T) == 4 ? 3 : 1) void 
         }
 }
 
-// z pass in registers where three components of N2 values fit (c64 up to 512, c128 up to 256)
-template <typename T, int L>
+// z pass in registers where three components of N2 values fit (both precisions up to 512, paired at 512)
+template <typename T, int L, bool HALF>
 constexpr bool fs_z_ok() {
     if constexpr (!fs_ok<T, L>())
         return false;
     else
-        return 3 * FourStep<L>::N2 * (int)sizeof(cpx<T>) <= 3 * 32 * 8;
+        return 3 * ZSplit<L, HALF>::N2 * (int)sizeof(cpx<T>) <= 3 * 32 * 8;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -618,17 +619,35 @@ int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long lon
     return LS_OK;
 }
 
-// z-pass launches for one layout (ZBS, compile time): register kernel / LDS kernel, full or half table
-template <typename T, int LL, int TX, int ZBS>
-void launch_fs_z(Ctx* c, unsigned nbl, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES,
-                 const cpx<T>* ghat, const cpx<T>* tw, long long nb) {
-    if (c->green_half)
-        hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX, true, ZBS>), dim3(nbl), dim3(fs_threads<T, LL>()), 0, c->stream,
-                           data, nrhs, c->L1, c->L2, CS, RS, ES, c->n3, ghat, tw, nb);
-    else
-        hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX, false, ZBS>), dim3(nbl), dim3(fs_threads<T, LL>()), 0, c->stream,
-                           data, nrhs, c->L1, c->L2, CS, RS, ES, c->n3, ghat, tw, nb);
+// threads per block of the register z pass
+template <typename T, int LL, bool HALF>
+constexpr int z_threads() {
+    return seg_cols<T>() * ZSplit<LL, HALF>::N1;
 }
+// Register z pass for one table layout (HALF) and work-buffer layout (c->zbs): 1 if launched, 0 if the
+// register kernel does not apply (the caller takes the LDS kernel), -1 on a tile mismatch.
+template <typename T, int LL, bool HALF>
+int try_fs_z(Ctx* c, bool fs, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES, const cpx<T>* ghat,
+             const cpx<T>* tw) {
+    if constexpr (fs_z_ok<T, LL, HALF>()) {
+        // the register kernel needs 2^zbs to divide the threads per line
+        if (fs && (z_threads<T, LL, HALF>() / seg_cols<T>()) % (1 << c->zbs) == 0) {
+            constexpr int TX = seg_cols<T>();
+            if (c->L1 % TX) return -1;
+            const long long nb = (long long)nrhs * (c->L1 / TX) * c->L2;
+            const unsigned nbl = (unsigned)((nb + 7) / 8 * 8);
+            if (c->zbs)
+                hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX, HALF, 3>), dim3(nbl), dim3(z_threads<T, LL, HALF>()), 0,
+                                   c->stream, data, nrhs, c->L1, c->L2, CS, RS, ES, c->n3, ghat, tw, nb);
+            else
+                hipLaunchKernelGGL((k_fs_zgreen<T, LL, TX, HALF, 0>), dim3(nbl), dim3(z_threads<T, LL, HALF>()), 0,
+                                   c->stream, data, nrhs, c->L1, c->L2, CS, RS, ES, c->n3, ghat, tw, nb);
+            return 1;
+        }
+    }
+    return 0;
+}
+// LDS z pass for one work-buffer layout (ZBS, compile time), full or half table
 template <typename T, int LL, int TX, int ZBS>
 void launch_lds_z(Ctx* c, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES, const cpx<T>* ghat,
                   const cpx<T>* tw) {
@@ -651,27 +670,17 @@ int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<
     // grids take the LDS kernel
     const long long table = c->green_half ? (long long)L * L2 * (L1 / 2 + 1)
                                           : (long long)(L / 2 + 1) * (L2 / 2 + 1) * (L1 / 2 + 1);
-    const bool off32 = (16 * ES + seg_cols<T>()) * (long long)sizeof(cpx<T>) < (1LL << 32) &&
+    const bool off32 = (33 * ES + seg_cols<T>()) * (long long)sizeof(cpx<T>) < (1LL << 32) &&
                        table * 6 * (long long)sizeof(cpx<T>) < (1LL << 32);
     c->prof.begin(c->stream, LS_PNAME(T, "fft_z_green"));
     const bool fs = variant == 0 && use_fourstep() && off32;
     switch (L) {
 #define CASE(LL)                                                                                              \
     case LL: {                                                                                                \
-        if constexpr (fs_z_ok<T, LL>()) {                                                                     \
-            /* the register kernel needs 2^zbs to divide the threads per line */                              \
-            if (fs && (fs_threads<T, LL>() / seg_cols<T>()) % (1 << c->zbs) == 0) {                          \
-                constexpr int TX = seg_cols<T>();                                                             \
-                if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");           \
-                const long long nb = (long long)nrhs * (L1 / TX) * L2;                                        \
-                const unsigned nbl = (unsigned)((nb + 7) / 8 * 8);                                            \
-                if (c->zbs)                                                                                   \
-                    launch_fs_z<T, LL, TX, 3>(c, nbl, data, nrhs, CS, RS, ES, ghat, tw, nb);                  \
-                else                                                                                          \
-                    launch_fs_z<T, LL, TX, 0>(c, nbl, data, nrhs, CS, RS, ES, ghat, tw, nb);                  \
-                break;                                                                                        \
-            }                                                                                                 \
-        }                                                                                                     \
+        const int reg = c->green_half ? try_fs_z<T, LL, true>(c, fs, data, nrhs, CS, RS, ES, ghat, tw)       \
+                                      : try_fs_z<T, LL, false>(c, fs, data, nrhs, CS, RS, ES, ghat, tw);     \
+        if (reg < 0) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");                  \
+        if (reg > 0) break;                                                                                   \
         constexpr int TX = zpass_cols<T, LL>();                                                               \
         if (L1 % TX) return fail(LS_ERR_ARG, "x length not a multiple of the z-pass tile");                   \
         if (c->zbs)                                                                                           \

@@ -11,6 +11,8 @@
 // global accesses for a fixed element are TX consecutive values.
 #pragma once
 
+#include <type_traits>
+
 #include "fft_core.h"
 
 namespace ls {
@@ -145,6 +147,107 @@ __device__ __forceinline__ int spectral_index(int q, int i) {
     using F = FourStep<L>;
     const int s = i / F::N1, k1 = i % F::N1;
     return (q + F::N1 * s) + F::N2 * k1;
+}
+
+// Paired four-step: N1 = 2 N2 threads per line, N2 values each (the same natural layout: thread p holds
+// x[p + N1 j]).  It serves the z pass where the square split would hold 32 values of each of three
+// components per thread (512 = 32 x 16 instead of 16 x 32).  After the first DFT and the transpose,
+// thread p = 2 k2 + h holds the N2 inputs n1 = 2 m + h of the length-N1 DFT for k2 and transforms them;
+// the radix-2 step that joins the two halves exchanges values with the partner thread p ^ 1, TX lanes
+// away in the same wavefront.  Spectral layout: thread p holds X[k2 + N2 (i + N2 h)] at v[i].  Selections
+// between the halves are made per real component (sel): a select of whole structs kept them in scratch.
+template <int L>
+struct FourStepPair {
+    static constexpr int N2 = (L == 512) ? 16 : (L == 128) ? 8 : (L == 32) ? 4 : 0;
+    static constexpr int N1 = 2 * N2;
+    static_assert(N2 > 0 && N1 * N2 == L, "unsupported length");
+};
+template <typename T>
+__device__ __forceinline__ cpx<T> sel(bool h, cpx<T> a, cpx<T> b) { return {h ? a.x : b.x, h ? a.y : b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> lane_xor(cpx<T> a, int mask) { return {__shfl_xor(a.x, mask), __shfl_xor(a.y, mask)}; }
+template <typename T, int L, int TX, int SIGN, bool HALF = false>
+__device__ __forceinline__ void fsp_forward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int p) {
+    using F = FourStepPair<L>;
+    static_assert(2 * TX <= 64, "partner lanes must share a wavefront");
+    reg_dft<SIGN, F::N2, T, HALF>(v);
+#pragma unroll
+    for (int k2 = 1; k2 < F::N2; ++k2) v[k2] = v[k2] * tw_at<SIGN>(tw, p * k2);
+#pragma unroll
+    for (int k2 = 0; k2 < F::N2; ++k2) lds[(k2 * F::N1 + p) * TX + t] = v[k2];
+    __syncthreads();
+    const int k2 = p >> 1;
+    const bool h = p & 1;
+#pragma unroll
+    for (int m = 0; m < F::N2; ++m) v[m] = lds[(k2 * F::N1 + 2 * m + (int)h) * TX + t];
+    __syncthreads();
+    reg_dft<SIGN, F::N2, T>(v);
+#pragma unroll
+    for (int i = 0; i < F::N2; ++i) {
+        cpx<T> mine = v[i];
+        if (i > 0) mine = sel(h, mine * tw_at<SIGN>(tw, i * F::N2), mine);
+        const cpx<T> other = lane_xor(mine, TX);
+        v[i] = sel(h, other - mine, mine + other);
+    }
+}
+template <typename T, int L, int TX, int SIGN>
+__device__ __forceinline__ void fsp_backward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int p) {
+    using F = FourStepPair<L>;
+    const int k2 = p >> 1;
+    const bool h = p & 1;
+#pragma unroll
+    for (int i = 0; i < F::N2; ++i) {
+        const cpx<T> mine = v[i];
+        const cpx<T> other = lane_xor(mine, TX);
+        const cpx<T> d = other - mine;
+        const cpx<T> dw = (i > 0) ? d * tw_at<SIGN>(tw, i * F::N2) : d;
+        v[i] = sel(h, dw, mine + other);
+    }
+    reg_dft<SIGN, F::N2, T>(v);
+#pragma unroll
+    for (int m = 0; m < F::N2; ++m) {
+        const int n1 = 2 * m + (int)h;
+        lds[(n1 * F::N2 + k2) * TX + t] = v[m] * tw_at<SIGN>(tw, n1 * k2);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < F::N2; ++j) v[j] = lds[(p * F::N2 + j) * TX + t];
+    __syncthreads();
+    reg_dft<SIGN, F::N2, T>(v);
+}
+template <int L>
+__device__ __forceinline__ int pair_spectral_index(int p, int i) {
+    using F = FourStepPair<L>;
+    return (p >> 1) + F::N2 * (i + F::N2 * (p & 1));
+}
+// The split the z pass uses for length L and table layout: paired at 512 with the octant table (with the
+// half-space table the extra index work would spill, so that case keeps the square split).
+template <int L, bool HALF>
+constexpr bool z_paired() {
+    return L == 512 && !HALF;
+}
+template <int L, bool HALF>
+struct ZSplit : std::conditional_t<z_paired<L, HALF>(), FourStepPair<L>, FourStep<L>> {};
+template <typename T, int L, int TX, int SIGN, bool PAIRED, bool HALF_IN = false>
+__device__ __forceinline__ void z_forward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int q) {
+    if constexpr (PAIRED)
+        fsp_forward<T, L, TX, SIGN, HALF_IN>(v, lds, tw, t, q);
+    else
+        fs_forward<T, L, TX, SIGN, HALF_IN>(v, lds, tw, t, q);
+}
+template <typename T, int L, int TX, int SIGN, bool PAIRED>
+__device__ __forceinline__ void z_backward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int q) {
+    if constexpr (PAIRED)
+        fsp_backward<T, L, TX, SIGN>(v, lds, tw, t, q);
+    else
+        fs_backward<T, L, TX, SIGN>(v, lds, tw, t, q);
+}
+template <int L, bool PAIRED>
+__device__ __forceinline__ int z_spectral_index(int q, int i) {
+    if constexpr (PAIRED)
+        return pair_spectral_index<L>(q, i);
+    else
+        return spectral_index<L>(q, i);
 }
 
 // XCD-aware block order: hardware hands out workgroups round-robin over the 8 XCDs, so logical

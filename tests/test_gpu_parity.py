@@ -383,3 +383,25 @@ def test_blocked_work_layout_matches_oracle(shape, monkeypatch):
     got2 = to_np(ctx.apply(u2))
     assert rel(got2[0], want) < 1e-10 and rel(got2[1], P.apply_fft(to_np(u2[1]))) < 1e-10
     ctx.close()
+
+
+@pytest.mark.parametrize("zblock", ["0", "8"])
+def test_z_length_512_matches_oracle(zblock, monkeypatch):
+    """A z line of 512 padded points (8 x 8 x 256 cells): the paired register z pass (32 threads of 16
+    values per line) in both precisions, with the blocked and the plain work-buffer layout."""
+    monkeypatch.setenv("LS_ZBLOCK", zblock)
+    shape = (8, 8, 256)
+    m = models.random_medium(shape, seed=5, rel=0.1)
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, W15)
+    ctx = lsvie.context_from_model(m, omegas=[W15], precision="mixed", max_rhs=2)
+    u = models.random_field(shape, seed=6)
+    ut = torch.from_numpy(u)
+    want = P.apply_fft(u)
+    got = to_np(ctx.apply(ut))
+    got32 = to_np(ctx.apply(ut.to(torch.complex64)))
+    print("zblock", zblock, "c128", rel(got, want), "c64", rel(got32, want), ctx.kernel_variants, flush=True)
+    assert rel(got, want) < 1e-10 and rel(got32, want) < 1e-5
+    u2 = torch.stack([ut, torch.from_numpy(models.random_field(shape, seed=7))])
+    got2 = to_np(ctx.apply(u2.to(torch.complex64)))
+    assert rel(got2[1], P.apply_fft(to_np(u2[1]))) < 1e-5
+    ctx.close()
