@@ -422,7 +422,7 @@ __device__ __forceinline__ cpx<T> cdot3(cpx<T> g1, cpx<T> f1, cpx<T> g2, cpx<T> 
 // they cut the instructions as much but schedule worse (0.738 against 0.728 ms), so FP32 keeps the
 // plain forms.
 template <typename T, int L, int TX, bool HALF = false, int ZBS = 0>
-__global__ __launch_bounds__((TX * ZSplit<L, HALF>::N1), (sizeof(T) == 4 ? (z_paired<L, HALF>() ? 2 : 3) : 1)) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
+__global__ __launch_bounds__((TX * ZSplit<L, HALF>::N1), (sizeof(T) == 4 ? (z_paired<L, HALF>() ? 2 : (L >= 512 ? 1 : 3)) : 1)) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
                                                                     int n3, const cpx<T>* __restrict__ ghat,
                                                                     const cpx<T>* __restrict__ tw, long long nb_real) {
