@@ -422,12 +422,12 @@ __device__ __forceinline__ cpx<T> cdot3(cpx<T> g1, cpx<T> f1, cpx<T> g2, cpx<T> 
 // they cut the instructions as much but schedule worse (0.738 against 0.728 ms), so FP32 keeps the
 // plain forms.
 template <typename T, int L, int TX, bool HALF = false, int ZBS = 0>
-__global__ __launch_bounds__((TX * ZSplit<L, HALF>::N1), (sizeof(T) == 4 ? (z_paired<L, HALF>() ? 2 : (L >= 512 ? 1 : 3)) : 1)) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
+__global__ __launch_bounds__((TX * ZSplit<T, L, HALF>::N1), (sizeof(T) == 4 ? (z_paired<T, L, HALF>() ? 2 : (L >= 512 ? 1 : 3)) : 1)) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
                                                                     int n3, const cpx<T>* __restrict__ ghat,
                                                                     const cpx<T>* __restrict__ tw, long long nb_real) {
-    using F = ZSplit<L, HALF>;
-    constexpr bool PAIRED = z_paired<L, HALF>();
+    using F = ZSplit<T, L, HALF>;
+    constexpr bool PAIRED = z_paired<T, L, HALF>();
     constexpr int zbs = ZBS;   // work buffer layout (zplane_offset), fixed at compile time
     __shared__ cpx<T> lds[L * TX];
     __shared__ cpx<T> tws[L];
@@ -530,7 +530,7 @@ constexpr bool fs_z_ok() {
     if constexpr (!fs_ok<T, L>())
         return false;
     else
-        return 3 * ZSplit<L, HALF>::N2 * (int)sizeof(cpx<T>) <= 3 * 32 * 8;
+        return 3 * ZSplit<T, L, HALF>::N2 * (int)sizeof(cpx<T>) <= 3 * 32 * 8;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -622,7 +622,7 @@ int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long lon
 // threads per block of the register z pass
 template <typename T, int LL, bool HALF>
 constexpr int z_threads() {
-    return seg_cols<T>() * ZSplit<LL, HALF>::N1;
+    return seg_cols<T>() * ZSplit<T, LL, HALF>::N1;
 }
 // Register z pass for one table layout (HALF) and work-buffer layout (c->zbs): 1 if launched, 0 if the
 // register kernel does not apply (the caller takes the LDS kernel), -1 on a tile mismatch.
