@@ -151,11 +151,11 @@ int ls_set_contrast(ls_ctx* ctx, const double* dC, const double* drho);
 
 /* One LS matvec Au = u - Gconv B u at frequency omega[i_omega] (Eq 19-21), for n_rhs fields
  * (1 <= n_rhs <= max_rhs).  u, Au: device c128 arrays [n_rhs][3][N3][N2][N1]; they must not
- * overlap.  Asynchronous. */
+ * overlap (LS_ERR_ARG otherwise).  Asynchronous. */
 int ls_apply(ls_ctx* ctx, int i_omega, const void* u, void* Au, int n_rhs);
 
-/* The same matvec with the operator, its FFTs and Green's multiply in FP32 (c64 fields).
- * Needs a context built with LS_PREC_MIXED, else LS_ERR_STATE.  Asynchronous. */
+/* The same matvec with the operator, its FFTs and Green's multiply in FP32 (c64 fields; u and Au must
+ * not overlap).  Needs a context built with LS_PREC_MIXED, else LS_ERR_STATE.  Asynchronous. */
 int ls_apply_c64(ls_ctx* ctx, int i_omega, const void* u, void* Au, int n_rhs);
 
 /* Incident field of a moment tensor M at source cell src[3] = (i, j, k) with rupture time t0
@@ -174,6 +174,8 @@ int ls_rhs_force(ls_ctx* ctx, int i_omega, const double F[3], const int cell[3],
  * whose residual b - A u uses the FP64 operator; the stopping test is always the FP64 true
  * residual.  All n_rhs systems advance together through batched operator applications.
  *   x0     device c128 like b, or NULL for zero.   u_out device c128 like b.
+ *          b and u_out must not overlap; x0 is either u_out itself (an in-place warm start) or
+ *          disjoint from it (LS_ERR_ARG otherwise).
  *   info   host array of n_rhs entries (may be NULL).
  *   precision  LS_PREC_C128 or LS_PREC_MIXED (the latter needs a mixed context).
  * Returns LS_OK when every system met tol; LS_ERR_NOT_CONVERGED, LS_ERR_BREAKDOWN or
@@ -182,9 +184,12 @@ int ls_rhs_force(ls_ctx* ctx, int i_omega, const double F[3], const int cell[3],
 int ls_solve(ls_ctx* ctx, int i_omega, const void* b, int n_rhs, double tol, int maxit,
              int precision, const void* x0, void* u_out, ls_info* info);
 
-/* Convenience form for one moment-tensor source: builds b with ls_rhs_moment, then ls_solve. */
+/* The moment-tensor solve in the form the method states it (Eq 13-16, 21-22): the incident field of M at
+ * source cell src with rupture time t0 (ls_rhs_moment, into the context's own buffer), then ls_solve of
+ * that one system from the initial guess x0 (device c128 [3][N3][N2][N1] or NULL for zero; it may be
+ * u_out itself) to relative residual tol, the solution into u_out.  Same return codes as ls_solve. */
 int ls_solve_moment(ls_ctx* ctx, int i_omega, const double M[6], const int src[3], double t0,
-                    double tol, int maxit, int precision, void* u_out, ls_info* info);
+                    double tol, int maxit, int precision, const void* x0, void* u_out, ls_info* info);
 
 /* Convenience form for one unit point force: builds b with ls_rhs_force (F delta_cell / h^3,
  * Eq 6), then ls_solve.  Used for reciprocity checks and receiver-side Green's functions. */
@@ -234,7 +239,8 @@ int ls_sample(ls_ctx* ctx, const void* u, int n_rhs, const int* rec, int n_rec, 
 int ls_synthesize(ls_ctx* ctx, const void* spectra, const int* k, int n_freq, int n_trace, int nt, double dt,
                   double fp, double ts, double* traces);
 
-/* Voigt engineering strain of n_rhs fields (Eq 17-18): eps device c128 [n_rhs][6][N3][N2][N1]. */
+/* Voigt engineering strain of n_rhs fields (Eq 17-18): eps device c128 [n_rhs][6][N3][N2][N1], disjoint
+ * from u (LS_ERR_ARG otherwise). */
 int ls_strain(ls_ctx* ctx, const void* u, void* eps, int n_rhs);
 
 /* Adjoint side of the operator (for gradients of misfits through the solution of Eq 21).

@@ -1,7 +1,8 @@
 """Gradients of a receiver misfit through the LS solve, as a torch.autograd.Function.
 
 Forward: for every frequency, the incident fields of the moment-tensor sources (Eq 13-16) and one
-batched solve A u = u0 (Eq 21-22); the fields are kept per frequency (checkpoints) and the three
+batched solve A u = u0 (Eq 21-22); the fields are kept per frequency (checkpoints, held by the autograd
+node together with a copy of the medium, which backward restores on the context) and the three
 components at the receiver cells are returned, complex [n_freq, n_src, 3, n_rec].
 
 Backward (adjoint-state method): with g = dL/d(data) (PyTorch's convention: for L = 1/2 ||data - d||^2
@@ -66,13 +67,18 @@ class _LSData(torch.autograd.Function):
             out.append(setup.sample(u))
         setup.fields = fields
         setup.infos = infos
+        # the checkpoints and the medium belong to this node: another forward on the same setup before
+        # this node's backward must not change what its backward sees
         fctx.setup = setup
+        fctx.fields = fields
+        fctx.medium = (dc21.detach().clone(), drho.detach().clone())
         return torch.stack(out)
 
     @staticmethod
     def backward(fctx, g):
         setup = fctx.setup
         ctx = setup.ctx
+        ctx.set_contrast(*fctx.medium)   # the adjoint operator and the gradient need this node's medium
         g21 = torch.zeros((21,) + ctx.field_shape[1:], dtype=torch.float64, device=ctx.device)
         grho = torch.zeros(ctx.field_shape[1:], dtype=torch.float64, device=ctx.device)
         gM = torch.zeros((setup.n_src, 6), dtype=torch.float64, device=ctx.device)
@@ -85,7 +91,7 @@ class _LSData(torch.autograd.Function):
                                        accumulate=True)
             lam_bar, _ = ctx.solve_T(adj, i_omega=iw, tol=setup.tol, maxit=setup.maxit, precision=setup.precision)
             # one library call: mu = conj(Gconv lam_bar), then the dC, drho and moment-tensor gradients
-            _, _, gMw = ctx.grad(setup.fields[iw], lam_bar, i_omega=iw, src=setup.source_cells, t0=setup.t0,
+            _, _, gMw = ctx.grad(fctx.fields[iw], lam_bar, i_omega=iw, src=setup.source_cells, t0=setup.t0,
                                  g_dC=g21, g_drho=grho)
             gM += torch.from_numpy(gMw).to(gM.device)
         return g21, grho, gM.to(torch.float64), None

@@ -4,6 +4,7 @@
 #include <array>
 #include <cmath>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <new>
@@ -169,6 +170,29 @@ int check_cell(const ls_ctx* c, const int* cell) {
     const int n[3] = {c->n1, c->n2, c->n3};
     for (int a = 0; a < 3; ++a)
         if (cell[a] < 0 || cell[a] >= n[a]) return fail(LS_ERR_ARG, "cell index outside the grid");
+    return LS_OK;
+}
+
+// the byte ranges [a, a + na) and [b, b + nb) intersect
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return na > 0 && nb > 0 && x < y + nb && y < x + na;
+}
+
+// in and out of a field-to-field call (n_rhs fields of elem bytes per complex value) must be disjoint
+int check_disjoint(const ls_ctx* c, const void* in, const void* out, int n_rhs, size_t elem, const char* what) {
+    const size_t bytes = (size_t)n_rhs * c->field_elems() * elem;
+    if (overlaps(in, bytes, out, bytes)) return fail(LS_ERR_ARG, std::string(what) + ": input and output overlap");
+    return LS_OK;
+}
+
+// solves: b and u_out disjoint; x0 either u_out itself (an in-place warm start) or disjoint from it
+int check_solve_buffers(const ls_ctx* c, const void* b, const void* x0, const void* u_out, int n_rhs) {
+    int rc;
+    if ((rc = check_disjoint(c, b, u_out, n_rhs, sizeof(z128), "solve (b, u_out)"))) return rc;
+    if (x0 && x0 != u_out) {
+        if ((rc = check_disjoint(c, x0, u_out, n_rhs, sizeof(z128), "solve (x0, u_out)"))) return rc;
+    }
     return LS_OK;
 }
 
@@ -473,6 +497,7 @@ int ls_apply(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
     if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
     if (!u || !Au) return fail(LS_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    if ((rc = check_disjoint(c, u, Au, n_rhs, sizeof(z128), "ls_apply"))) return rc;
     return apply_op<double>(c, i_omega, (const z128*)u, (z128*)Au, n_rhs);
 }
 
@@ -482,6 +507,7 @@ int ls_apply_c64(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
     if (!c->mixed) return fail(LS_ERR_STATE, "the FP32 operator needs a context built with LS_PREC_MIXED");
     if (!u || !Au) return fail(LS_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    if ((rc = check_disjoint(c, u, Au, n_rhs, sizeof(z64), "ls_apply_c64"))) return rc;
     return apply_op<float>(c, i_omega, (const z64*)u, (z64*)Au, n_rhs);
 }
 
@@ -490,6 +516,7 @@ int ls_apply_T(ls_ctx* c, int i_omega, const void* y, void* ATy, int n_rhs) {
     if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
     if (!y || !ATy) return fail(LS_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    if ((rc = check_disjoint(c, y, ATy, n_rhs, sizeof(z128), "ls_apply_T"))) return rc;
     return apply_T_op<double>(c, i_omega, (const z128*)y, (z128*)ATy, n_rhs);
 }
 
@@ -512,6 +539,7 @@ int ls_solve_T(ls_ctx* c, int i_omega, const void* b, int n_rhs, double tol, int
     if (precision != LS_PREC_C128 && precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
     if (precision == LS_PREC_MIXED && !c->mixed)
         return fail(LS_ERR_STATE, "mixed precision needs a context built with LS_PREC_MIXED");
+    if ((rc = check_solve_buffers(c, b, x0, x_out, n_rhs))) return rc;
     return solve_systems(c, i_omega, (const z128*)b, n_rhs, tol, maxit, precision, (const z128*)x0, (z128*)x_out,
                          info, true);
 }
@@ -573,14 +601,15 @@ int ls_solve(ls_ctx* c, int i_omega, const void* b, int n_rhs, double tol, int m
     if (precision != LS_PREC_C128 && precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
     if (precision == LS_PREC_MIXED && !c->mixed)
         return fail(LS_ERR_STATE, "mixed precision needs a context built with LS_PREC_MIXED");
+    if ((rc = check_solve_buffers(c, b, x0, u_out, n_rhs))) return rc;
     return solve_systems(c, i_omega, (const z128*)b, n_rhs, tol, maxit, precision, (const z128*)x0, (z128*)u_out, info);
 }
 
 int ls_solve_moment(ls_ctx* c, int i_omega, const double M[6], const int src[3], double t0, double tol, int maxit,
-                    int precision, void* u_out, ls_info* info) {
+                    int precision, const void* x0, void* u_out, ls_info* info) {
     int rc = ls_rhs_moment(c, i_omega, M, src, t0, c ? (void*)c->bd : nullptr);
     if (rc) return rc;
-    return ls_solve(c, i_omega, c->bd, 1, tol, maxit, precision, nullptr, u_out, info);
+    return ls_solve(c, i_omega, c->bd, 1, tol, maxit, precision, x0, u_out, info);
 }
 
 int ls_solve_force(ls_ctx* c, int i_omega, const double F[3], const int cell[3], double tol, int maxit, int precision,
@@ -601,9 +630,19 @@ bool soft_failure(int rc) { return rc == LS_ERR_NOT_CONVERGED || rc == LS_ERR_BR
 int run_batch(Ctx* c, const ls_job* jobs, const std::vector<int>& idx, double tol, int maxit, int precision,
               ls_info* infos) {
     const size_t fe = c->field_elems();
-    if (!c->batch_b) {
-        LS_HIP(hipMalloc((void**)&c->batch_b, (size_t)c->max_rhs * fe * sizeof(z128)));
-        LS_HIP(hipMalloc((void**)&c->batch_x, (size_t)c->max_rhs * fe * sizeof(z128)));
+    if (!c->batch_b || !c->batch_x) {
+        int arc = dalloc(c, (void**)&c->batch_b, (size_t)c->max_rhs * fe * sizeof(z128));
+        if (arc == LS_OK) arc = dalloc(c, (void**)&c->batch_x, (size_t)c->max_rhs * fe * sizeof(z128));
+        if (arc != LS_OK) {   // leave neither half allocated, so the next call allocates both again
+            for (z128** q : {&c->batch_b, &c->batch_x}) {
+                if (*q) {
+                    (void)hipFree(*q);
+                    c->bytes -= (long long)((size_t)c->max_rhs * fe * sizeof(z128));
+                }
+                *q = nullptr;
+            }
+            return arc;
+        }
     }
     const int nr = (int)idx.size();
     const int iw = jobs[idx[0]].i_omega;
@@ -734,6 +773,8 @@ int ls_strain(ls_ctx* c, const void* u, void* eps, int n_rhs) {
     if ((rc = check_ctx(c))) return rc;
     if (!u || !eps) return fail(LS_ERR_ARG, "null field pointer");
     if (n_rhs < 1) return fail(LS_ERR_ARG, "n_rhs must be >= 1");
+    if (overlaps(u, (size_t)n_rhs * c->field_elems() * sizeof(z128), eps, 2 * (size_t)n_rhs * c->field_elems() * sizeof(z128)))
+        return fail(LS_ERR_ARG, "ls_strain: u and eps overlap");
     return strain_launch(c, (const z128*)u, (z128*)eps, n_rhs);
 }
 

@@ -105,7 +105,7 @@ def load():
         "ls_rhs_moment": (I, [P, I, dp, ip, D, P]),
         "ls_rhs_force": (I, [P, I, dp, ip, P]),
         "ls_solve": (I, [P, I, P, I, D, I, I, P, P, ctypes.POINTER(Info)]),
-        "ls_solve_moment": (I, [P, I, dp, ip, D, D, I, I, P, ctypes.POINTER(Info)]),
+        "ls_solve_moment": (I, [P, I, dp, ip, D, D, I, I, P, P, ctypes.POINTER(Info)]),
         "ls_strain": (I, [P, P, P, I]),
         "ls_apply_T": (I, [P, I, P, P, I]),
         "ls_convolve": (I, [P, I, P, P, I]),
@@ -151,6 +151,13 @@ def _int3(a):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def storage_overlaps(a, b):
+    """True when the memory of tensors a and b (contiguous) intersects."""
+    na, nb = a.numel() * a.element_size(), b.numel() * b.element_size()
+    x, y = a.data_ptr(), b.data_ptr()
+    return na > 0 and nb > 0 and x < y + nb and y < x + na
 
 
 def check_buffer(t, shape, dtype, device, name="out"):
@@ -224,12 +231,12 @@ def ls_solve(ctx, i_omega, b, n_rhs, tol, maxit, precision, x0, u_out, raise_on_
     return code, [i.as_dict() for i in infos]
 
 
-def ls_solve_moment(ctx, i_omega, M, src, t0, tol, maxit, precision, u_out, raise_on_error=True):
+def ls_solve_moment(ctx, i_omega, M, src, t0, tol, maxit, precision, x0, u_out, raise_on_error=True):
     m, mp = _dbl(M, 6)
     s, sp = _int3(src)
     info = Info()
     code = load().ls_solve_moment(ctx, int(i_omega), mp, sp, float(t0), float(tol), int(maxit), int(precision),
-                                  _ptr(u_out), ctypes.byref(info))
+                                  _ptr(x0), _ptr(u_out), ctypes.byref(info))
     if raise_on_error:
         _check(code)
     return code, info.as_dict()
@@ -431,10 +438,14 @@ class Context:
         return d if d.index is not None else self.torch.device(d.type, self.torch.cuda.current_device())
 
     def _out(self, out, like):
-        """A fresh output like the (already converted) input, or the caller's buffer once checked."""
+        """A fresh output like the (already converted) input, or the caller's buffer once checked (it must
+        not share memory with the input: the library reads the input while it writes the output)."""
         if out is None:
             return self.torch.empty_like(like)
-        return self._check(out, like.shape, like.dtype)
+        self._check(out, like.shape, like.dtype)
+        if storage_overlaps(out, like):
+            raise ValueError("out shares memory with the input")
+        return out
 
     def empty(self, nrhs=None, dtype=None):
         torch = self.torch
@@ -468,6 +479,17 @@ class Context:
         prec = LS_PREC_MIXED if (precision or ("mixed" if self.mixed else "c128")) == "mixed" else LS_PREC_C128
         code, infos = ls_solve(self.handle, i_omega, b, nrhs, tol, maxit, prec, x0, out, raise_on_error)
         return out, infos
+
+    def solve_moment(self, M, src, i_omega=0, t0=0.0, tol=1e-8, maxit=2000, precision=None, x0=None, out=None,
+                     raise_on_error=True):
+        """One moment-tensor source M (Voigt 6) at cell src: incident field and solve in one library call,
+        from the initial guess x0 (None for zero; it may be out itself)."""
+        out = self.empty() if out is None else self._check(out, self.field_shape, self.torch.complex128)
+        if x0 is not None and x0 is not out:
+            x0, _ = self._field(x0, self.torch.complex128)
+        prec = LS_PREC_MIXED if (precision or ("mixed" if self.mixed else "c128")) == "mixed" else LS_PREC_C128
+        code, info = ls_solve_moment(self.handle, i_omega, M, src, t0, tol, maxit, prec, x0, out, raise_on_error)
+        return out, info
 
     def apply_T(self, y, i_omega=0, out=None):
         y, nrhs = self._field(y, self.torch.complex128)

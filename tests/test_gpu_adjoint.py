@@ -163,3 +163,60 @@ def test_solve_force_matches_dense():
     assert info["status"] == 0 and info["rel_res_true"] <= 1e-12
     assert rel(to_np(x), want) < 1e-10
     ctx.close()
+
+
+def test_two_forwards_then_backward_of_the_first():
+    """Each autograd node keeps its own checkpoints and medium: L1 = misfit(a), then L2 = misfit(b) on the
+    same setup, then backward of L1 alone gives the gradient of a single forward at a (the oracle's)."""
+    m, omegas, sources, receivers, data = small_case()
+    probs = [op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, w) for w in omegas]
+    _, g21, grho, gM = oadj.misfit_gradient_dense(probs, sources, receivers, data)
+    ctx = lsvie.context_from_model(m, omegas=omegas, max_rhs=2)
+    setup = adjoint.MisfitSetup(ctx, [s for _, s, _ in sources], receivers, t0=[t for _, _, t in sources],
+                                tol=1e-12)
+    obs = torch.tensor(np.array(data), dtype=torch.complex128, device=ctx.device)
+    Ms = np.stack([s[0] for s in sources])
+    dc_a = torch.tensor(m.dc21, dtype=torch.float64, device=ctx.device, requires_grad=True)
+    dr_a = torch.tensor(m.drho, dtype=torch.float64, device=ctx.device, requires_grad=True)
+    M_a = torch.tensor(Ms, dtype=torch.float64, device=ctx.device, requires_grad=True)
+    L1 = adjoint.misfit(dc_a, dr_a, M_a, setup, obs)
+    # a second forward at another medium and source strength on the same setup
+    dc_b = torch.tensor(1.3 * m.dc21, dtype=torch.float64, device=ctx.device, requires_grad=True)
+    dr_b = torch.tensor(0.7 * m.drho, dtype=torch.float64, device=ctx.device, requires_grad=True)
+    M_b = torch.tensor(2.0 * Ms, dtype=torch.float64, device=ctx.device, requires_grad=True)
+    L2 = adjoint.misfit(dc_b, dr_b, M_b, setup, obs)
+    L1.backward()
+    print("g21", rel(to_np(dc_a.grad), g21), "grho", rel(to_np(dr_a.grad), grho), "gM", rel(to_np(M_a.grad), gM),
+          flush=True)
+    assert rel(to_np(dc_a.grad), g21) < 1e-8
+    assert rel(to_np(dr_a.grad), grho) < 1e-8
+    assert rel(to_np(M_a.grad), gM) < 1e-8
+    assert dc_b.grad is None and float(L2.detach()) != float(L1.detach())
+    ctx.close()
+
+
+def test_solve_moment_warm_start_and_overlap_rules():
+    """ls_solve_moment (incident field and solve in one call) from x0 = 0 against the dense solution; then
+    warm-started in place from its own solution it stops at the first half step; overlapping buffers are
+    rejected."""
+    m = models.random_medium((7, 6, 5), seed=6, rel=0.1, aniso_background=True)
+    ctx = lsvie.context_from_model(m, omegas=[W])
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, W)
+    M, src = models.double_couple(30, 60, 90), (3, 2, 2)
+    want = solve.solve_dense(P.dense_A(), P.rhs_moment(M, src, t0=0.002))
+    x, info = ctx.solve_moment(M, src, t0=0.002, tol=1e-12, maxit=1000)
+    assert info["status"] == 0 and rel(to_np(x), want) < 1e-10
+    x2, info2 = ctx.solve_moment(M, src, t0=0.002, tol=1e-10, maxit=1000, x0=x, out=x)
+    assert x2 is x and info2["status"] == 0 and info2["iters"] <= 1 and rel(to_np(x), want) < 1e-10
+    b = ctx.rhs_moment(M, src)
+    with pytest.raises(ValueError):
+        ctx.solve(b, out=b)
+    with pytest.raises(ValueError):
+        ctx.apply(b, out=b)
+    # through the C ABI directly: u_out overlapping b by one field
+    buf = ctx.empty(2)
+    buf[0].copy_(b)
+    with pytest.raises(lsvie.LsError) as e:
+        lsvie.ls_solve(ctx.handle, 0, buf[0], 1, 1e-8, 100, lsvie.LS_PREC_C128, None, buf.reshape(-1)[3:])
+    assert e.value.code == lsvie.LS_ERR_ARG
+    ctx.close()
