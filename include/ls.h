@@ -154,6 +154,16 @@ int ls_set_contrast(ls_ctx* ctx, const double* dC, const double* drho);
  * overlap (LS_ERR_ARG otherwise).  Asynchronous. */
 int ls_apply(ls_ctx* ctx, int i_omega, const void* u, void* Au, int n_rhs);
 
+/* For callers that cannot allocate device memory during the call (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): ls_apply with its padded FFT work buffer taken from a
+ * fixed 64 MiB device array that the library holds on each GPU it runs on until the process ends, instead
+ * of the context's workspace.  Same arguments, result (bitwise equal to ls_apply's) and errors as ls_apply;
+ * n_rhs x 3 N3 L2 L1 x 16 bytes (L_a the padded FFT lengths: 50 MB for one 64^3 field) must fit in the
+ * 64 MiB, else LS_ERR_ARG.  Allocates nothing and clears nothing (every value of the buffer that is read
+ * was written earlier in the same call).  Every call on a GPU uses that GPU's one array, so calls that
+ * overlap in time on one GPU (different streams or host threads) race; serialise them.  Asynchronous. */
+int ls_apply_noalloc(ls_ctx* ctx, int i_omega, const void* u, void* Au, int n_rhs);
+
 /* The same matvec with the operator, its FFTs and Green's multiply in FP32 (c64 fields; u and Au must
  * not overlap).  Needs a context built with LS_PREC_MIXED, else LS_ERR_STATE.  Asynchronous. */
 int ls_apply_c64(ls_ctx* ctx, int i_omega, const void* u, void* Au, int n_rhs);

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -115,11 +116,18 @@ static void release(Ctx* c) {
 // ------------------------------------------------------------------------------------------
 // the matvec
 
+// work: the padded FFT buffer (n_rhs x 3 N3 L2 L1 values); tau: the stress scratch of the split contrast.
+// Every value of work that a pass reads was written earlier in the same call, so it needs no clearing.
+template <typename T>
+int apply_op_in(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* Au, int nrhs, cpx<T>* work, cpx<T>* tau) {
+    int rc = contrast_to_work<T>(c, i_omega, u, work, tau, nrhs);
+    if (rc) return rc;
+    return fft_apply_passes<T>(c, i_omega, work, u, Au, nrhs, true);
+}
+
 template <typename T>
 int apply_op(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* Au, int nrhs) {
-    int rc = contrast_to_work<T>(c, i_omega, u, (cpx<T>*)c->work, (cpx<T>*)c->tau, nrhs);
-    if (rc) return rc;
-    return fft_apply_passes<T>(c, i_omega, (cpx<T>*)c->work, u, Au, nrhs, true);
+    return apply_op_in<T>(c, i_omega, u, Au, nrhs, (cpx<T>*)c->work, (cpx<T>*)c->tau);
 }
 
 template int apply_op<double>(Ctx*, int, const z128*, z128*, int);
@@ -148,6 +156,41 @@ int convolve_op(Ctx* c, int i_omega, const cpx<T>* f, cpx<T>* out, int nrhs) {
 template int apply_T_op<double>(Ctx*, int, const z128*, z128*, int);
 template int apply_T_op<float>(Ctx*, int, const z64*, z64*, int);
 template int convolve_op<double>(Ctx*, int, const z128*, z128*, int);
+
+// ------------------------------------------------------------------------------------------
+// Allocation-free apply (ls_apply_noalloc): its padded work buffer is this file-scope device array, of
+// which every GPU the library runs on holds its own copy until the process ends.  In host code the name
+// `scratch` is only a stand-in for the symbol: its device address is looked up once per device
+// (scratch_setup, called by ls_setup with the context's device current) and only that address is used.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Look up this device's copy of the array (once per device); the device must be current.
+int scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(LS_ERR_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return LS_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(LS_ERR_HIP, std::string("scratch address lookup failed: ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = ptr;
+    return LS_OK;
+}
+
+void* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    return g_scratch_ptr[device];
+}
 
 }  // namespace ls
 
@@ -375,6 +418,12 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
         }
         (void)hipGetLastError();
     }
+    if (scratch_setup(c->device) != LS_OK) {
+        const std::string msg = g_last_error;
+        delete static_cast<ls_ctx*>(c);
+        g_last_error = msg;
+        return LS_ERR_HIP;
+    }
     if (!c->stream) {
         // the legacy null stream cannot be captured into graphs: work on a private blocking stream,
         // which the runtime keeps ordered with the caller's work on the null stream
@@ -499,6 +548,24 @@ int ls_apply(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
     if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
     if ((rc = check_disjoint(c, u, Au, n_rhs, sizeof(z128), "ls_apply"))) return rc;
     return apply_op<double>(c, i_omega, (const z128*)u, (z128*)Au, n_rhs);
+}
+
+int ls_apply_noalloc(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!u || !Au) return fail(LS_ERR_ARG, "null field pointer");
+    if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    if ((rc = check_disjoint(c, u, Au, n_rhs, sizeof(z128), "ls_apply_noalloc"))) return rc;
+    const size_t work = (size_t)n_rhs * 3 * c->n3 * c->L2 * c->L1 * sizeof(z128);
+    const size_t tau = use_fused_contrast() ? 0 : (size_t)n_rhs * 6 * (size_t)c->ncell * sizeof(z128);
+    const size_t work_al = (work + 255) / 256 * 256;
+    if (work_al + tau > kScratchBytes)
+        return fail(LS_ERR_ARG, "ls_apply_noalloc: " + std::to_string(work_al + tau) + " bytes of work buffer exceed the " +
+                                    std::to_string(kScratchBytes) + "-byte scratch (3 N3 L2 L1 x 16 bytes per right-hand side)");
+    char* base = static_cast<char*>(scratch_address(c->device));
+    if (!base) return fail(LS_ERR_STATE, "scratch address not set up on the context's device");
+    return apply_op_in<double>(c, i_omega, (const z128*)u, (z128*)Au, n_rhs, (z128*)base,
+                               tau ? (z128*)(base + work_al) : nullptr);
 }
 
 int ls_apply_c64(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {

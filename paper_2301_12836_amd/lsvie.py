@@ -4,7 +4,7 @@ Every computation runs in the library's HIP kernels on the GPU; this module only
 torch tensors to device pointers and checks shapes.  If the shared library has not been built,
 loading fails loudly (there is no CPU fallback).
 
-The module-level functions carry the C names (``ls_setup``, ``ls_apply``, ``ls_apply_c64``,
+The module-level functions carry the C names (``ls_setup``, ``ls_apply``, ``ls_apply_noalloc``, ``ls_apply_c64``,
 ``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_moment``, ``ls_solve_force``,
 ``ls_solve_batch``, ``ls_strain``, ``ls_apply_T``, ``ls_convolve``, ``ls_solve_T``,
 ``ls_grad_contrast``, ``ls_grad``, ``ls_sample``, ``ls_synthesize``, ``ls_residual_history``, ``ls_profile``,
@@ -41,7 +41,7 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
                LS_ERR_BREAKDOWN: "LS_ERR_BREAKDOWN", LS_ERR_NOT_CONVERGED: "LS_ERR_NOT_CONVERGED",
                LS_ERR_NONFINITE: "LS_ERR_NONFINITE", LS_ERR_STATE: "LS_ERR_STATE"}
 
-EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
+EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_noalloc", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
             "ls_solve_moment", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve",
             "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch", "ls_sample", "ls_synthesize", "ls_residual_history",
             "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_last_error")
@@ -101,6 +101,7 @@ def load():
         "ls_destroy": (None, [P]),
         "ls_set_contrast": (I, [P, P, P]),
         "ls_apply": (I, [P, I, P, P, I]),
+        "ls_apply_noalloc": (I, [P, I, P, P, I]),
         "ls_apply_c64": (I, [P, I, P, P, I]),
         "ls_rhs_moment": (I, [P, I, dp, ip, D, P]),
         "ls_rhs_force": (I, [P, I, dp, ip, P]),
@@ -204,6 +205,10 @@ def ls_set_contrast(ctx, dC, drho):
 
 def ls_apply(ctx, i_omega, u, Au, n_rhs):
     return _check(load().ls_apply(ctx, int(i_omega), _ptr(u), _ptr(Au), int(n_rhs)))
+
+
+def ls_apply_noalloc(ctx, i_omega, u, Au, n_rhs):
+    return _check(load().ls_apply_noalloc(ctx, int(i_omega), _ptr(u), _ptr(Au), int(n_rhs)))
 
 
 def ls_apply_c64(ctx, i_omega, u, Au, n_rhs):
