@@ -7,16 +7,18 @@ stiffnesses, 4 % on density, correlation length 40 m, seed 2) over an isotropic 
 (3000, 1700, 2400); 6 elementary moment tensors x 8 frequencies 5-40 Hz at the centre cell;
 relative residual 1e-6 certified with the FP64 operator.
 
-One step = the whole hot path over that batch: for each frequency, the 6 moment-tensor incident
-fields, then one batched mixed-precision solve of the 6 systems (FP32 operator inside BiCGSTAB with
-FP64 inner products, FP64 iterative refinement with the FP64 operator, final FP64 true residual).
-The Green's tables for the 8 frequencies are built once before the timed region (set-up time is
-reported separately).  ``value`` is LS matvecs per second over the timed steps (every operator
-application of every right-hand side counts once, FP32 and FP64 alike).
+One step = the whole hot path over that batch in one library call (ls_solve_batch): the 48 moment-tensor
+incident fields, then one mixed-precision solve of all 48 systems, each at its own frequency, sharing every
+operator launch (FP32 operator inside Bi-CGSTAB with FP64 inner products, FP64 iterative refinement with
+the FP64 operator, final FP64 true residual); systems leave the launches as they converge.  The Green's
+tables for the 8 frequencies are built once before the timed region (set-up time is reported
+separately).  ``value`` is LS matvecs per second over the timed steps (every operator application of
+every right-hand side counts once, FP32 and FP64 alike); the timed steps replay captured graphs.
 
 Also reported: the operator alone (c128 and c64, 1 and 6 right-hand sides), the roofline of the
-dominant kernel measured with HIP events on the library's stream during the timed steps, and the
-CPU oracle's FFT-based apply timed on the host as a baseline.
+dominant kernel measured with HIP events on the library's stream during one extra untimed step, the same
+48 systems solved one at a time with the plain FP64 operator, and the CPU oracle's FFT-based apply timed
+on the host as a baseline.
 """
 
 import argparse
@@ -37,40 +39,48 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(fam, n1, n2, n3, L1, L2, L3, nrhs):
-    """Algorithmic HBM bytes of one launch of a kernel family (each array read or written once)."""
+def family_bytes(fam, n, L, sum_rhs, sum_tabs, count):
+    """Algorithmic HBM bytes of the recorded launches of one kernel family (each array read or written once):
+    a part per right-hand side the launches covered (sum_rhs), a part per launch (the contrast, read once
+    per launch whatever its width) and a part per distinct Green's table a launch read (sum_tabs)."""
     if "." not in fam:
         return None
     name, prec = fam.rsplit(".", 1)
     sc = 16 if prec == "c128" else 8      # complex element
     sr = sc // 2                          # real element
-    n = n1 * n2 * n3
-    R = nrhs
-    x_lines = 3 * R * n3 * n2             # data lines of the x passes
-    plane_cols = 3 * R * n3 * L1          # columns of the y passes
-    oct_ = (L1 // 2 + 1) * (L2 // 2 + 1) * (L3 // 2 + 1)
-    table = {
-        "contrast_strain_stress": (3 * R * n + 6 * R * n) * sc + 21 * n * sr,
-        "contrast_divergence": (6 * R * n + 3 * R * n + 3 * R * n) * sc + n * sr,
-        "contrast_fused": (3 * R * n + 3 * R * n) * sc + 22 * n * sr,
-        "contrast_fused_T": (3 * R * n + 3 * R * n + 3 * R * n) * sc + 22 * n * sr,
-        "fft_x_fwd": (x_lines * n1 + x_lines * L1) * sc,
-        "fft_y_fwd": (plane_cols * n2 + plane_cols * L2) * sc,
-        "fft_z_green": (2 * 3 * R * n3 * L2 * L1) * sc + 6 * oct_ * sc,
-        "fft_y_inv": (plane_cols * L2 + plane_cols * n2) * sc,
-        # inside the solver every other launch also reads r^ (the fused r^H v); t^H s needs no extra read
-        "fft_x_inv_epi": (x_lines * L1 + 2 * 3 * R * n + (3 * R * n) // 2) * sc,
+    N = n ** 3
+    xl = 3 * n * n                        # data lines of the x passes per right-hand side
+    yc = 3 * n * L                        # columns of the y passes per right-hand side
+    octant = (L // 2 + 1) ** 3
+    per_rhs = {
+        "contrast_fused": 6 * N * sc,             # u in, f out
+        "contrast_fused_T": 9 * N * sc,           # g in, y in, out
+        "contrast_strain_stress": 9 * N * sc,     # u in, tau out
+        "contrast_divergence": 12 * N * sc,       # tau, u in, f out
+        "fft_x_fwd": xl * (n + L) * sc,
+        "fft_y_fwd": yc * (n + L) * sc,
+        "fft_z_green": 2 * 3 * n * L * L * sc,
+        "fft_y_inv": yc * (L + n) * sc,
+        "fft_x_inv_epi": xl * (L + 2 * n) * sc,   # work in, u in, Au out
+        "fft_x_inv_rv": xl * (L + 3 * n) * sc,    # also r^ in (r^H v fused)
+        "fft_x_inv_ts": xl * (L + 2 * n) * sc,    # t^H s uses u = s, already read
+        "fft_x_inv_conv": xl * (L + n) * sc,
     }
-    return table.get(name)
+    per_launch = {"contrast_fused": 22 * N * sr, "contrast_fused_T": 22 * N * sr,
+                  "contrast_strain_stress": 21 * N * sr, "contrast_divergence": N * sr}
+    per_table = {"fft_z_green": 6 * octant * sc}
+    if name not in per_rhs:
+        return None
+    return per_rhs[name] * sum_rhs + per_launch.get(name, 0) * count + per_table.get(name, 0) * sum_tabs
 
 
 FP_VECTOR_PEAK_TFLOPS = 78.6   # 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz, FP32 without packed math, and FP64
 
 
 def kernel_flops(fam, n1, n2, n3, L1, L2, L3, nrhs):
-    """Algorithmic flops of one z-pass launch: per (k_x, k_y) column and right-hand side, a forward and an
-    inverse length-L3 FFT of three components at the conventional 5 L log2 L each, plus the complex 3 x 3
-    multiply (9 complex multiply-adds, 8 flops each) at every k_z."""
+    """Algorithmic flops of z-pass launches covering nrhs right-hand sides in all: per (k_x, k_y) column and
+    right-hand side, a forward and an inverse length-L3 FFT of three components at the conventional
+    5 L log2 L each, plus the complex 3 x 3 multiply (9 complex multiply-adds, 8 flops each) at every k_z."""
     if not fam.startswith("fft_z_green"):
         return None
     import math
@@ -84,10 +94,11 @@ def split_contrast():
 
 
 def apply_bytes(n, prec, nrhs):
-    """Algorithmic bytes of one LS matvec for nrhs right-hand sides (L = 2N): the sum over its kernels."""
+    """Algorithmic bytes of one LS matvec of nrhs right-hand sides at one frequency (L = 2N): the sum over
+    its kernels."""
     L = 2 * n
     contrast = ("contrast_strain_stress", "contrast_divergence") if split_contrast() else ("contrast_fused",)
-    return sum(kernel_bytes(f + "." + prec, n, n, n, L, L, L, nrhs) for f in
+    return sum(family_bytes(f + "." + prec, n, L, nrhs, 1, 1) for f in
                contrast + ("fft_x_fwd", "fft_y_fwd", "fft_z_green", "fft_y_inv", "fft_x_inv_epi"))
 
 
@@ -103,22 +114,29 @@ def file_hash(name):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(family):
-    """HBM bytes per launch of a kernel family from the committed rocprofv3 counter summary, or None when
-    any source the family is compiled from differs from the one the counters were taken with."""
+def measured_traffic(family, n, L, rhs_per_launch, R=6):
+    """HBM bytes per launch of a kernel family, from the committed rocprofv3 counter summary of R-right-hand-
+    side applies at one frequency: the counters' ratio to that launch's algorithmic bytes, times the
+    algorithmic bytes of a launch of the given average width.  (None, reason) when the summary is missing
+    or any source the family is compiled from differs from the one the counters were taken with."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_config3_apply.txt")
     srcs = next((v for k, v in FAMILY_SOURCES.items() if family.startswith(k)), None)
     if srcs is None or not os.path.exists(path):
-        return None
+        return None, "no counter summary for this family"
     lines = open(path).read().splitlines()
     recorded = {p[1]: p[2] for p in (ln.split() for ln in lines) if len(p) == 3 and p[0] == "file_sha256"}
     if any(recorded.get(f) != file_hash(f) for f in srcs):
-        return None
+        return None, "the kernel sources changed since the counters were taken"
     for ln in lines:
         parts = ln.split()
         if len(parts) == 3 and parts[0] == "traffic" and parts[1] == family:
-            return float(parts[2])
-    return None
+            counted = float(parts[2])
+            alg = family_bytes(family, n, L, R, 1, 1)
+            per_launch = family_bytes(family, n, L, rhs_per_launch, 1, 1)
+            return round(counted / alg * per_launch), (
+                f"FETCH_SIZE + WRITE_SIZE of a {R}-right-hand-side launch: {counted:.4g} B against {alg:.4g} B "
+                f"algorithmic (ratio {counted / alg:.3f}), scaled to {rhs_per_launch:.2f} right-hand sides per launch")
+    return None, "family not in the counter summary"
 
 
 def time_applies(torch, ctx, u, reps, warmup=5):
@@ -207,8 +225,9 @@ def main():
                     help="skip timing the same 48 systems as sequential single-source plain c128 solves")
     ap.add_argument("--bicgstab-l", type=int, default=1,
                     help="Krylov method: 1 Bi-CGSTAB (the paper's), 2..4 BiCGSTAB(l)")
-    ap.add_argument("--mode", choices=["bench", "apply-profile"], default="bench",
-                    help="apply-profile: only a few batched applies plus a copy of known size, for counter runs")
+    ap.add_argument("--mode", choices=["bench", "steps", "apply-profile"], default="bench",
+                    help="steps: only the warmup and timed steps (for rocprofv3 kernel traces of the solve); "
+                         "apply-profile: only a few batched applies plus a copy of known size, for counter runs")
     args = ap.parse_args()
     if args.mode == "apply-profile":
         return apply_profile(args)
@@ -228,30 +247,31 @@ def main():
     n = args.n
     L = 2 * n
     nrhs = len(model.sources)
+    nfreq = len(model.omegas)
+    nsys = nrhs * nfreq
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx = lsvie.context_from_model(model, precision="mixed", max_rhs=nrhs, bicgstab_l=args.bicgstab_l)
+    ctx = lsvie.context_from_model(model, precision="mixed", max_rhs=nsys, bicgstab_l=args.bicgstab_l)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"context set up in {setup_s:.2f} s ({ctx.device_bytes / 2**30:.2f} GiB on the device)")
 
-    out = [ctx.empty(nrhs) for _ in model.omegas]
-    bufs = [ctx.empty(nrhs) for _ in model.omegas]
+    # the 48 systems: every moment tensor at every frequency, frequency-major
+    jobs = [(0, iw, M, src, 0.0) for iw in range(nfreq) for M, src in model.sources]
+    out = ctx.empty(nsys)
+    outs = [out[k] for k in range(nsys)]
 
     def step():
-        mv = 0
-        its = []
-        res = []
-        for iw in range(len(model.omegas)):
-            for J, (M, src) in enumerate(model.sources):
-                ctx.rhs_moment(M, src, i_omega=iw, out=bufs[iw][J])
-            x, infos = ctx.solve(bufs[iw], i_omega=iw, tol=model.tol, maxit=args.maxit, precision="mixed",
-                                 out=out[iw])
-            mv += sum(i["matvecs"] for i in infos)
-            its.append([i["iters"] for i in infos])
-            res.append(max(i["rel_res_true"] for i in infos))
-            log(f"  {model.freqs[iw]:.0f} Hz: iterations {its[-1]}, refinements "
-                f"{[i['refinements'] for i in infos]}, worst residual {res[-1]:.2e}")
+        """One ls_solve_batch call: the 48 incident fields, then one mixed-precision solve of all 48 systems
+        (each at its own frequency) in shared launches."""
+        _, infos = lsvie.solve_batch([ctx], jobs, tol=model.tol, maxit=args.maxit, precision="mixed", outs=outs)
+        mv = sum(i["matvecs"] for i in infos)
+        its = [[infos[iw * nrhs + J]["iters"] for J in range(nrhs)] for iw in range(nfreq)]
+        res = [max(infos[iw * nrhs + J]["rel_res_true"] for J in range(nrhs)) for iw in range(nfreq)]
+        refs = [[infos[iw * nrhs + J]["refinements"] for J in range(nrhs)] for iw in range(nfreq)]
+        for iw in range(nfreq):
+            log(f"  {model.freqs[iw]:.0f} Hz: iterations {its[iw]}, refinements {refs[iw]}, "
+                f"worst residual {res[iw]:.2e}")
         return mv, its, res
 
     for w in range(args.warmup):
@@ -275,6 +295,11 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = total_mv / elapsed
     log(f"timed {args.steps} steps: {ms_per_step:.1f} ms per step, {value:.1f} matvecs/s")
+    if args.mode == "steps":
+        ctx.close()
+        print(json.dumps({"mode": "steps", "ms_per_step": round(ms_per_step, 2), "matvecs_per_s": round(value, 1)}),
+              flush=True)
+        return
 
     # one more step, untimed, with a HIP event pair recorded around every kernel launch on the library's
     # stream (ls_profile; the iterations then run as separate launches instead of graph replays): the
@@ -291,46 +316,53 @@ def main():
 
     # error of every mixed-precision result (last timed step) against FP64 solves of the same systems to a
     # relative residual of 1e-10 (the FP64 path is the one held to the oracle at 1e-10 in the parity tests)
-    ref = ctx.empty(nrhs)
-    errs = []
-    for iw in range(len(model.omegas)):
-        ctx.solve(bufs[iw], i_omega=iw, tol=1e-10, maxit=args.maxit, precision="c128", out=ref)
-        d = (torch.linalg.vector_norm((out[iw] - ref).reshape(nrhs, -1), dim=1)
-             / torch.linalg.vector_norm(ref.reshape(nrhs, -1), dim=1))
-        errs.append([float(v) for v in d.cpu()])
-    del ref
+    b_all = ctx.empty(nsys)
+    for k, (_, iw, M, src, t0_) in enumerate(jobs):
+        ctx.rhs_moment(M, src, i_omega=iw, t0=t0_, out=b_all[k])
+    ref, _ = ctx.solve(b_all, i_omega=[j[1] for j in jobs], tol=1e-10, maxit=args.maxit, precision="c128")
+    d = (torch.linalg.vector_norm((out - ref).reshape(nsys, -1), dim=1)
+         / torch.linalg.vector_norm(ref.reshape(nsys, -1), dim=1)).cpu().numpy()
+    errs = [[float(d[iw * nrhs + J]) for J in range(nrhs)] for iw in range(nfreq)]
+    del ref, b_all
     accuracy = {"reference": "FP64 solves of the same 48 systems to relative residual 1e-10",
                 "max_rel_err": max(max(e) for e in errs),
                 "per_frequency_max": [float(f"{max(e):.3g}") for e in errs]}
     log(f"mixed vs FP64 per-result relative error: max {accuracy['max_rel_err']:.2e}, per frequency "
         f"{accuracy['per_frequency_max']}")
 
-    # roofline of the dominant kernel family during the timed steps
+    # roofline of the dominant kernel family during the profiled step: algorithmic bytes of its launches
+    # (each launch's own width and tables) over their summed event time
     fam_rows = []
-    for fam, d in prof.items():
-        b = kernel_bytes(fam, n, n, n, L, L, L, nrhs)
-        if b is None or d["count"] == 0:
+    for fam, d_ in prof.items():
+        if d_["count"] == 0:
             continue
-        avg_ms = d["ms"] / d["count"]
-        fam_rows.append((d["ms"], fam, d["count"], avg_ms, b))
+        b_ = family_bytes(fam, n, L, d_["rhs"], d_["tables"], d_["count"])
+        if b_ is None:
+            continue
+        fam_rows.append((d_["ms"], fam, d_["count"], b_, d_["rhs"]))
     fam_rows.sort(reverse=True)
-    total_prof_ms = sum(d["ms"] for d in prof.values())
-    kernels = {f: {"launches": c, "avg_ms": round(a, 4), "share": round(ms / total_prof_ms, 3),
-                   "GBps": round(b / (a * 1e-3) / 1e9, 1)} for ms, f, c, a, b in fam_rows}
-    _, dom, dom_count, dom_ms, dom_bytes = fam_rows[0]
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom)
+    total_prof_ms = sum(d_["ms"] for d_ in prof.values())
+    kernels = {f: {"launches": c, "avg_ms": round(ms / c, 4), "rhs_per_launch": round(r / c, 2),
+                   "share": round(ms / total_prof_ms, 3), "GBps": round(b_ / (ms * 1e-3) / 1e9, 1)}
+               for ms, f, c, b_, r in fam_rows}
+    dom_total_ms, dom, dom_count, dom_bytes_total, dom_rhs = fam_rows[0]
+    dom_ms = dom_total_ms / dom_count
+    dom_bytes = dom_bytes_total / dom_count
+    achieved = dom_bytes_total / (dom_total_ms * 1e-3) / 1e9
+    traffic, traffic_note = measured_traffic(dom, n, L, dom_rhs / dom_count)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "bytes_per_launch": dom_bytes, "avg_launch_ms": round(dom_ms, 4), "launches": dom_count}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_note": traffic_note,
+                "bytes_per_launch": round(dom_bytes), "avg_launch_ms": round(dom_ms, 4), "launches": dom_count,
+                "rhs_per_launch": round(dom_rhs / dom_count, 2)}
     log(f"dominant kernel {dom}: {dom_ms:.3f} ms avg over {dom_count} launches, {achieved:.0f} GB/s")
     # the same kernel against the vector-arithmetic peak: it is bound by its FP32 instructions, not by HBM
     roofline_alu = None
-    fl = kernel_flops(dom, n, n, n, L, L, L, nrhs)
+    fl = kernel_flops(dom, n, n, n, L, L, L, dom_rhs)
     if fl is not None:
-        tf = fl / (dom_ms * 1e-3) / 1e12
+        tf = fl / (dom_total_ms * 1e-3) / 1e12
         roofline_alu = {"kernel": dom, "bound": "alu", "achieved": round(tf, 2), "peak": FP_VECTOR_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(tf / FP_VECTOR_PEAK_TFLOPS, 4), "flops_per_launch": fl}
+                        "unit": "TFLOP/s", "frac": round(tf / FP_VECTOR_PEAK_TFLOPS, 4),
+                        "flops_per_launch": fl / dom_count}
         log(f"  {tf:.1f} TFLOP/s algorithmic ({tf / FP_VECTOR_PEAK_TFLOPS:.2f} of the vector peak)")
 
     # the operator alone
@@ -346,7 +378,7 @@ def main():
             del u
     log(f"apply rates: {json.dumps(rates)}")
     ctx.close()
-    del out, bufs
+    del out, outs
 
     seq = None
     if not args.no_compare_c128:

@@ -194,6 +194,16 @@ int ls_rhs_force(ls_ctx* ctx, int i_omega, const double F[3], const int cell[3],
 int ls_solve(ls_ctx* ctx, int i_omega, const void* b, int n_rhs, double tol, int maxit,
              int precision, const void* x0, void* u_out, ls_info* info);
 
+/* ls_solve with each system at its own frequency: system q solves A(omega[i_omega[q]]) u_q = b_q (the
+ * paper solves one system per frequency and source, Eq 21-22, and notes that frequencies can be solved
+ * simultaneously).  i_omega: host int [n_rhs].  The systems share every operator launch and every
+ * Bi-CGSTAB vector kernel; a launch covers only the systems still iterating (converged ones drop out),
+ * and every decision (inner tolerance, stopping, refinement) is taken per system, so each result is
+ * bitwise the one ls_solve returns for that system alone.  Arguments, buffers and return codes otherwise
+ * as ls_solve.  Synchronises the stream. */
+int ls_solve_multi(ls_ctx* ctx, const int* i_omega, const void* b, int n_rhs, double tol, int maxit,
+                   int precision, const void* x0, void* u_out, ls_info* info);
+
 /* The moment-tensor solve in the form the method states it (Eq 13-16, 21-22): the incident field of M at
  * source cell src with rupture time t0 (ls_rhs_moment, into the context's own buffer), then ls_solve of
  * that one system from the initial guess x0 (device c128 [3][N3][N2][N1] or NULL for zero; it may be
@@ -219,11 +229,12 @@ typedef struct ls_job {
 } ls_job;
 
 /* Solve every job of a batch over several contexts, whose grids may differ (the paper treats each
- * frequency and source as an independent system, Eq 21-22).  Per context the jobs are grouped by
- * frequency and solved max_rhs at a time as one multi-right-hand-side solve (ls_solve with the given
- * precision), so device residency stays within what the contexts were built for; contexts are
- * driven concurrently, one host thread and the context's own stream each (contexts must be
- * distinct and are used exclusively for the duration of the call).  The first call on a context
+ * frequency and source as an independent system, Eq 21-22).  Per context the jobs are ordered by
+ * frequency and solved max_rhs at a time as one multi-right-hand-side solve whose systems may sit at
+ * different frequencies (ls_solve_multi with the given precision), so device residency stays within
+ * what the contexts were built for; contexts are driven concurrently, one host thread and the
+ * context's own stream each (contexts must be distinct and are used exclusively for the duration of
+ * the call).  The first call on a context
  * allocates two [max_rhs][3][N3][N2][N1] c128 batch buffers that it keeps until ls_destroy.
  * infos: host array of n_jobs entries (may be NULL).  All arguments are checked before any work.
  * Returns LS_OK when every job met tol; a hard error (LS_ERR_HIP, LS_ERR_OOM) of any context stops
@@ -296,13 +307,17 @@ int ls_grad(ls_ctx* ctx, int i_omega, const void* u, const void* lam_bar, int n_
 int ls_residual_history(ls_ctx* ctx, int rhs, double* hist, int max_len);
 
 /* Per-kernel timing of the library's own launches.  ls_profile(ctx, 1) starts recording a
- * HIP event pair around every kernel launch on the context's stream (at most a fixed number
- * of launches; later ones are not recorded); ls_profile(ctx, 0) stops.  ls_profile_read
- * synchronises, then for each kernel family k < n_max writes its name (NUL-terminated, at
- * most 63 chars) into names + 64 k, its launch count into counts[k] and the summed event time
- * in milliseconds into ms[k]; returns the number of families, and clears the record. */
+ * HIP event pair around every kernel launch on the context's stream (at most 16384 launches;
+ * later ones are not recorded); while it is on, Bi-CGSTAB iterations run as separate launches
+ * instead of graph replays.  ls_profile(ctx, 0) stops.  ls_profile_read synchronises, then for
+ * each kernel family k < n_max writes its name (NUL-terminated, at most 63 chars) into
+ * names + 64 k, its launch count into counts[k], the summed event time in milliseconds into
+ * ms[k] and, when units is not NULL, the summed right-hand sides the launches covered into
+ * units[2 k] and the summed number of distinct Green's tables they read into units[2 k + 1]
+ * (the quantities a launch's algorithmic bytes depend on); returns the number of families,
+ * and clears the record.  Any of names, counts, ms, units may be NULL. */
 int ls_profile(ls_ctx* ctx, int enable);
-int ls_profile_read(ls_ctx* ctx, char* names, int* counts, double* ms, int n_max);
+int ls_profile_read(ls_ctx* ctx, char* names, int* counts, double* ms, long long* units, int n_max);
 
 /* Bytes of device memory the context holds. */
 long long ls_device_bytes(const ls_ctx* ctx);

@@ -46,10 +46,12 @@ int Profiler::family(const char* name) {
     return (int)names.size() - 1;
 }
 
-void Profiler::begin(hipStream_t s, const char* name) {
+void Profiler::begin(hipStream_t s, const char* name, int nrhs, int ntab) {
     open_family = -1;
     if (!on || n >= kMax) return;
     open_family = family(name);
+    open_rhs = nrhs;
+    open_tabs = ntab;
     (void)hipEventRecord(ev[2 * n], s);
 }
 
@@ -57,6 +59,8 @@ void Profiler::end(hipStream_t s) {
     if (open_family < 0) return;
     (void)hipEventRecord(ev[2 * n + 1], s);
     fam[n] = open_family;
+    rhs[n] = open_rhs;
+    tabs[n] = open_tabs;
     ++n;
     open_family = -1;
 }
@@ -116,46 +120,46 @@ static void release(Ctx* c) {
 // ------------------------------------------------------------------------------------------
 // the matvec
 
-// work: the padded FFT buffer (n_rhs x 3 N3 L2 L1 values); tau: the stress scratch of the split contrast.
+// work: the padded FFT buffer (set.n x 3 N3 L2 L1 values); tau: the stress scratch of the split contrast.
 // Every value of work that a pass reads was written earlier in the same call, so it needs no clearing.
 template <typename T>
-int apply_op_in(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* Au, int nrhs, cpx<T>* work, cpx<T>* tau) {
-    int rc = contrast_to_work<T>(c, i_omega, u, work, tau, nrhs);
+int apply_op_in(Ctx* c, const RhsSet& set, const cpx<T>* u, cpx<T>* Au, cpx<T>* work, cpx<T>* tau) {
+    int rc = contrast_to_work<T>(c, set, u, work, tau);
     if (rc) return rc;
-    return fft_apply_passes<T>(c, i_omega, work, u, Au, nrhs, true);
+    return fft_apply_passes<T>(c, set, work, u, Au, true);
 }
 
 template <typename T>
-int apply_op(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* Au, int nrhs) {
-    return apply_op_in<T>(c, i_omega, u, Au, nrhs, (cpx<T>*)c->work, (cpx<T>*)c->tau);
+int apply_op(Ctx* c, const RhsSet& set, const cpx<T>* u, cpx<T>* Au) {
+    return apply_op_in<T>(c, set, u, Au, (cpx<T>*)c->work, (cpx<T>*)c->tau);
 }
 
-template int apply_op<double>(Ctx*, int, const z128*, z128*, int);
-template int apply_op<float>(Ctx*, int, const z64*, z64*, int);
+template int apply_op<double>(Ctx*, const RhsSet&, const z128*, z128*);
+template int apply_op<float>(Ctx*, const RhsSet&, const z64*, z64*);
 
 // A^T y = y - B (Gconv y): Gconv and B are both symmetric, so the transpose applies the Green's
 // convolution first and the contrast second
 template <typename T>
-int apply_T_op(Ctx* c, int i_omega, const cpx<T>* y, cpx<T>* ATy, int nrhs) {
+int apply_T_op(Ctx* c, const RhsSet& set, const cpx<T>* y, cpx<T>* ATy) {
     cpx<T>* work = (cpx<T>*)c->work;
     cpx<T>* g = (cpx<T>*)c->gs;
-    int rc = to_work<T>(c, y, work, nrhs);
+    int rc = to_work<T>(c, set, y, work);
     if (rc) return rc;
-    rc = fft_apply_passes<T>(c, i_omega, work, nullptr, g, nrhs, false);
+    rc = fft_apply_passes<T>(c, set, work, nullptr, g, false);
     if (rc) return rc;
-    return contrast_transposed_epilogue<T>(c, i_omega, g, y, ATy, (cpx<T>*)c->tau, nrhs);
+    return contrast_transposed_epilogue<T>(c, set, g, y, ATy, (cpx<T>*)c->tau);
 }
 
 template <typename T>
-int convolve_op(Ctx* c, int i_omega, const cpx<T>* f, cpx<T>* out, int nrhs) {
-    int rc = to_work<T>(c, f, (cpx<T>*)c->work, nrhs);
+int convolve_op(Ctx* c, const RhsSet& set, const cpx<T>* f, cpx<T>* out) {
+    int rc = to_work<T>(c, set, f, (cpx<T>*)c->work);
     if (rc) return rc;
-    return fft_apply_passes<T>(c, i_omega, (cpx<T>*)c->work, nullptr, out, nrhs, false);
+    return fft_apply_passes<T>(c, set, (cpx<T>*)c->work, nullptr, out, false);
 }
 
-template int apply_T_op<double>(Ctx*, int, const z128*, z128*, int);
-template int apply_T_op<float>(Ctx*, int, const z64*, z64*, int);
-template int convolve_op<double>(Ctx*, int, const z128*, z128*, int);
+template int apply_T_op<double>(Ctx*, const RhsSet&, const z128*, z128*);
+template int apply_T_op<float>(Ctx*, const RhsSet&, const z64*, z64*);
+template int convolve_op<double>(Ctx*, const RhsSet&, const z128*, z128*);
 
 // ------------------------------------------------------------------------------------------
 // Allocation-free apply (ls_apply_noalloc): its padded work buffer is this file-scope device array, of
@@ -394,6 +398,17 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
         const bool off = e && std::strcmp(e, "0") == 0, force = e && std::strcmp(e, "8") == 0;
         c->zbs = (!off && (force || c->L3 >= 512) && c->n3 % 8 == 0) ? 3 : 0;
     }
+    {
+        // Operator launches inside a solve cover at most about 1.25 GiB of FP32 padded work buffer (6 systems
+        // at 128^3, 1 at 256^3, all of a batch at 64^3): per system the apply costs the same from 6 systems a
+        // launch upward, but in a 128^3 solve launches of 6 ran 2 % faster than launches of 48 (the passes
+        // reread less of the previous pass's output from the Infinity Cache when the buffer is larger).
+        // LS_LAUNCH_RHS in the environment overrides it (0: no cap).
+        const long long per = 3LL * c->n3 * supported_fft_length(c->n2) * supported_fft_length(c->n1) * 8;
+        c->launch_rhs = (int)std::max(1LL, (5LL << 28) / std::max(1LL, per));
+        const char* e = std::getenv("LS_LAUNCH_RHS");
+        if (e) c->launch_rhs = std::max(0, std::atoi(e));
+    }
     c->ncell = (long long)c->n1 * c->n2 * c->n3;
     c->h = grid->h;
     c->mixed = o.precision == LS_PREC_MIXED;
@@ -475,7 +490,9 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     // fused inner products: at most 3 N3 N2 / 8 epilogue blocks per right-hand side (c128 tiles of 8 lines)
     A((void**)&c->dparts, (size_t)c->max_rhs * kRedSlots * (3 * (size_t)c->n3 * c->n2 / 8 + 1) * sizeof(double));
     A((void**)&c->state, (size_t)c->max_rhs * kStateLen * sizeof(double));
-    A((void**)&c->red, 4 * kRedBlocks * sizeof(double));
+    // reductions: [0, 2 kRedBlocks) residual norms by slot, then per-slot scales, BiCGSTAB(l) coefficients and
+    // per-slot squared tolerances, kRedBlocks doubles each
+    A((void**)&c->red, 5 * kRedBlocks * sizeof(double));
     A(&c->stage, 8192);
     if (rc == LS_OK && c->bicgstab_l > 1) rc = krylov_setup(c);
     if (rc == LS_OK) {
@@ -547,7 +564,7 @@ int ls_apply(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
     if (!u || !Au) return fail(LS_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
     if ((rc = check_disjoint(c, u, Au, n_rhs, sizeof(z128), "ls_apply"))) return rc;
-    return apply_op<double>(c, i_omega, (const z128*)u, (z128*)Au, n_rhs);
+    return apply_op<double>(c, RhsSet::uniform(n_rhs, i_omega), (const z128*)u, (z128*)Au);
 }
 
 int ls_apply_noalloc(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
@@ -564,7 +581,7 @@ int ls_apply_noalloc(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs)
                                     std::to_string(kScratchBytes) + "-byte scratch (3 N3 L2 L1 x 16 bytes per right-hand side)");
     char* base = static_cast<char*>(scratch_address(c->device));
     if (!base) return fail(LS_ERR_STATE, "scratch address not set up on the context's device");
-    return apply_op_in<double>(c, i_omega, (const z128*)u, (z128*)Au, n_rhs, (z128*)base,
+    return apply_op_in<double>(c, RhsSet::uniform(n_rhs, i_omega), (const z128*)u, (z128*)Au, (z128*)base,
                                tau ? (z128*)(base + work_al) : nullptr);
 }
 
@@ -575,7 +592,7 @@ int ls_apply_c64(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {
     if (!u || !Au) return fail(LS_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
     if ((rc = check_disjoint(c, u, Au, n_rhs, sizeof(z64), "ls_apply_c64"))) return rc;
-    return apply_op<float>(c, i_omega, (const z64*)u, (z64*)Au, n_rhs);
+    return apply_op<float>(c, RhsSet::uniform(n_rhs, i_omega), (const z64*)u, (z64*)Au);
 }
 
 int ls_apply_T(ls_ctx* c, int i_omega, const void* y, void* ATy, int n_rhs) {
@@ -584,7 +601,7 @@ int ls_apply_T(ls_ctx* c, int i_omega, const void* y, void* ATy, int n_rhs) {
     if (!y || !ATy) return fail(LS_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
     if ((rc = check_disjoint(c, y, ATy, n_rhs, sizeof(z128), "ls_apply_T"))) return rc;
-    return apply_T_op<double>(c, i_omega, (const z128*)y, (z128*)ATy, n_rhs);
+    return apply_T_op<double>(c, RhsSet::uniform(n_rhs, i_omega), (const z128*)y, (z128*)ATy);
 }
 
 int ls_convolve(ls_ctx* c, int i_omega, const void* f, void* out, int n_rhs) {
@@ -592,7 +609,7 @@ int ls_convolve(ls_ctx* c, int i_omega, const void* f, void* out, int n_rhs) {
     if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
     if (!f || !out) return fail(LS_ERR_ARG, "null field pointer");
     if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
-    return convolve_op<double>(c, i_omega, (const z128*)f, (z128*)out, n_rhs);
+    return convolve_op<double>(c, RhsSet::uniform(n_rhs, i_omega), (const z128*)f, (z128*)out);
 }
 
 int ls_solve_T(ls_ctx* c, int i_omega, const void* b, int n_rhs, double tol, int maxit, int precision,
@@ -607,7 +624,8 @@ int ls_solve_T(ls_ctx* c, int i_omega, const void* b, int n_rhs, double tol, int
     if (precision == LS_PREC_MIXED && !c->mixed)
         return fail(LS_ERR_STATE, "mixed precision needs a context built with LS_PREC_MIXED");
     if ((rc = check_solve_buffers(c, b, x0, x_out, n_rhs))) return rc;
-    return solve_systems(c, i_omega, (const z128*)b, n_rhs, tol, maxit, precision, (const z128*)x0, (z128*)x_out,
+    const std::vector<int> freq(n_rhs, i_omega);
+    return solve_systems(c, freq.data(), (const z128*)b, n_rhs, tol, maxit, precision, (const z128*)x0, (z128*)x_out,
                          info, true);
 }
 
@@ -633,7 +651,7 @@ int ls_grad(ls_ctx* c, int i_omega, const void* u, const void* lam_bar, int n_rh
         }
     }
     z128* mu = (z128*)c->gs;  // mu = conj(Gconv lam_bar), in the workspace of the transposed operator
-    if ((rc = convolve_op<double>(c, i_omega, (const z128*)lam_bar, mu, n_rhs))) return rc;
+    if ((rc = convolve_op<double>(c, RhsSet::uniform(n_rhs, i_omega), (const z128*)lam_bar, mu))) return rc;
     if ((rc = conj_launch(c, mu, 3 * c->ncell * n_rhs))) return rc;
     if ((rc = grad_contrast_launch(c, i_omega, (const z128*)u, mu, n_rhs, g_dC, g_drho))) return rc;
     if (g_M) return grad_moment_launch(c, i_omega, mu, n_rhs, src, t0, g_M);
@@ -669,7 +687,27 @@ int ls_solve(ls_ctx* c, int i_omega, const void* b, int n_rhs, double tol, int m
     if (precision == LS_PREC_MIXED && !c->mixed)
         return fail(LS_ERR_STATE, "mixed precision needs a context built with LS_PREC_MIXED");
     if ((rc = check_solve_buffers(c, b, x0, u_out, n_rhs))) return rc;
-    return solve_systems(c, i_omega, (const z128*)b, n_rhs, tol, maxit, precision, (const z128*)x0, (z128*)u_out, info);
+    const std::vector<int> freq(n_rhs, i_omega);
+    return solve_systems(c, freq.data(), (const z128*)b, n_rhs, tol, maxit, precision, (const z128*)x0, (z128*)u_out,
+                         info);
+}
+
+int ls_solve_multi(ls_ctx* c, const int* i_omega, const void* b, int n_rhs, double tol, int maxit, int precision,
+                   const void* x0, void* u_out, ls_info* info) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if (!i_omega || !b || !u_out) return fail(LS_ERR_ARG, "null argument");
+    if (n_rhs < 1 || n_rhs > c->max_rhs) return fail(LS_ERR_ARG, "n_rhs outside [1, max_rhs]");
+    for (int q = 0; q < n_rhs; ++q)
+        if ((rc = check_omega(c, i_omega[q]))) return rc;
+    if (!(tol > 0) || !(tol < 1)) return fail(LS_ERR_ARG, "tol must be in (0, 1)");
+    if (maxit < 1) return fail(LS_ERR_ARG, "maxit must be >= 1");
+    if (precision != LS_PREC_C128 && precision != LS_PREC_MIXED) return fail(LS_ERR_ARG, "bad precision");
+    if (precision == LS_PREC_MIXED && !c->mixed)
+        return fail(LS_ERR_STATE, "mixed precision needs a context built with LS_PREC_MIXED");
+    if ((rc = check_solve_buffers(c, b, x0, u_out, n_rhs))) return rc;
+    return solve_systems(c, i_omega, (const z128*)b, n_rhs, tol, maxit, precision, (const z128*)x0, (z128*)u_out,
+                         info);
 }
 
 int ls_solve_moment(ls_ctx* c, int i_omega, const double M[6], const int src[3], double t0, double tol, int maxit,
@@ -692,8 +730,9 @@ namespace {
 
 bool soft_failure(int rc) { return rc == LS_ERR_NOT_CONVERGED || rc == LS_ERR_BREAKDOWN || rc == LS_ERR_NONFINITE; }
 
-// One multi-right-hand-side solve of the jobs idx (all of context c and one frequency): incident
-// fields into the context's batch buffer, the batched solve, then each solution copied to its job.
+// One multi-right-hand-side solve of the jobs idx (all of context c, at any frequencies): incident fields
+// into the context's batch buffer, one batched solve with each system at its own frequency, then each
+// solution copied to its job.
 int run_batch(Ctx* c, const ls_job* jobs, const std::vector<int>& idx, double tol, int maxit, int precision,
               ls_info* infos) {
     const size_t fe = c->field_elems();
@@ -712,14 +751,15 @@ int run_batch(Ctx* c, const ls_job* jobs, const std::vector<int>& idx, double to
         }
     }
     const int nr = (int)idx.size();
-    const int iw = jobs[idx[0]].i_omega;
+    std::vector<int> freq(nr);
     int rc;
     for (int r = 0; r < nr; ++r) {
         const ls_job& j = jobs[idx[r]];
-        if ((rc = rhs_moment_into(c, iw, j.M, j.src, j.t0, c->batch_b + r * fe))) return rc;
+        freq[r] = j.i_omega;
+        if ((rc = rhs_moment_into(c, j.i_omega, j.M, j.src, j.t0, c->batch_b + r * fe))) return rc;
     }
     std::vector<ls_info> inf(nr);
-    rc = solve_systems(c, iw, c->batch_b, nr, tol, maxit, precision, nullptr, c->batch_x, inf.data());
+    rc = solve_systems(c, freq.data(), c->batch_b, nr, tol, maxit, precision, nullptr, c->batch_x, inf.data());
     if (rc != LS_OK && !soft_failure(rc)) return rc;
     for (int r = 0; r < nr; ++r) {
         LS_HIP(hipMemcpyAsync(jobs[idx[r]].u_out, c->batch_x + r * fe, fe * sizeof(z128), hipMemcpyDeviceToDevice,
@@ -753,25 +793,16 @@ int ls_solve_batch(ls_ctx* const* ctxs, int n_ctx, const ls_job* jobs, int n_job
         if ((rc = check_moment(ctxs[jobs[j].ctx], jobs[j].i_omega, jobs[j].M, jobs[j].src, jobs[j].t0))) return rc;
         if (!jobs[j].u_out) return fail(LS_ERR_ARG, "null job output");
     }
-    // plan: per context, its jobs grouped by frequency (in order of first appearance), in chunks of max_rhs
+    // plan: per context, its jobs ordered by frequency (stable within a frequency), in chunks of max_rhs;
+    // a chunk mixes frequencies, each system at its own
     std::vector<std::vector<std::vector<int>>> plan(n_ctx);
     for (int i = 0; i < n_ctx; ++i) {
-        std::vector<int> freqs;
+        std::vector<int> mine;
         for (int j = 0; j < n_jobs; ++j)
-            if (jobs[j].ctx == i && std::find(freqs.begin(), freqs.end(), jobs[j].i_omega) == freqs.end())
-                freqs.push_back(jobs[j].i_omega);
-        for (int w : freqs) {
-            std::vector<int> chunk;
-            for (int j = 0; j < n_jobs; ++j) {
-                if (jobs[j].ctx != i || jobs[j].i_omega != w) continue;
-                chunk.push_back(j);
-                if ((int)chunk.size() == ctxs[i]->max_rhs) {
-                    plan[i].push_back(chunk);
-                    chunk.clear();
-                }
-            }
-            if (!chunk.empty()) plan[i].push_back(chunk);
-        }
+            if (jobs[j].ctx == i) mine.push_back(j);
+        std::stable_sort(mine.begin(), mine.end(), [&](int a, int b) { return jobs[a].i_omega < jobs[b].i_omega; });
+        for (size_t k = 0; k < mine.size(); k += (size_t)ctxs[i]->max_rhs)
+            plan[i].emplace_back(mine.begin() + k, mine.begin() + std::min(mine.size(), k + (size_t)ctxs[i]->max_rhs));
     }
     // one worker per context with work, each driving its context's stream (the solves synchronise
     // for their convergence tests, so contexts on different streams overlap on the device)
@@ -862,26 +893,32 @@ int ls_profile(ls_ctx* c, int enable) {
     if (enable && P.ev.empty()) {
         P.ev.resize(2 * Profiler::kMax);
         P.fam.resize(Profiler::kMax);
+        P.rhs.resize(Profiler::kMax);
+        P.tabs.resize(Profiler::kMax);
         for (auto& e : P.ev) LS_HIP(hipEventCreate(&e));
     }
     P.on = enable != 0;
     return LS_OK;
 }
 
-int ls_profile_read(ls_ctx* c, char* names, int* counts, double* ms, int n_max) {
+int ls_profile_read(ls_ctx* c, char* names, int* counts, double* ms, long long* units, int n_max) {
     int rc;
     if ((rc = check_ctx(c))) return rc;
     Profiler& P = c->prof;
     LS_HIP(hipStreamSynchronize(c->stream));
-    std::vector<double> sum(P.names.size(), 0.0);
-    std::vector<int> cnt(P.names.size(), 0);
+    const size_t nf_ = P.names.size();
+    std::vector<double> sum(nf_, 0.0);
+    std::vector<int> cnt(nf_, 0);
+    std::vector<long long> rsum(nf_, 0), tsum(nf_, 0);
     for (int i = 0; i < P.n; ++i) {
         float t = 0;
         LS_HIP(hipEventElapsedTime(&t, P.ev[2 * i], P.ev[2 * i + 1]));
         sum[P.fam[i]] += t;
         cnt[P.fam[i]] += 1;
+        rsum[P.fam[i]] += P.rhs[i];
+        tsum[P.fam[i]] += P.tabs[i];
     }
-    const int nf = (int)P.names.size();
+    const int nf = (int)nf_;
     for (int k = 0; k < nf && k < n_max; ++k) {
         if (names) {
             std::strncpy(names + 64 * k, P.names[k].c_str(), 63);
@@ -889,6 +926,10 @@ int ls_profile_read(ls_ctx* c, char* names, int* counts, double* ms, int n_max) 
         }
         if (counts) counts[k] = cnt[k];
         if (ms) ms[k] = sum[k];
+        if (units) {
+            units[2 * k] = rsum[k];
+            units[2 * k + 1] = tsum[k];
+        }
     }
     P.n = 0;
     return nf;

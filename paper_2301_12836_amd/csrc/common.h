@@ -64,6 +64,55 @@ __host__ __device__ __forceinline__ long long zrow_offset(int y, int zbs, int L1
 }
 
 // ------------------------------------------------------------------------------------------
+// right-hand sides of one launch
+
+constexpr int kMaxRhs = 64;   // largest batch of right-hand sides a context carries (ls_options.max_rhs)
+
+// The systems one operator launch covers: launch position r (0 <= r < n) works on field slot slot[r] (the
+// index into [.][3][N3][N2][N1] field arrays: fields, Krylov vectors, caller buffers) at frequency index
+// freq[r]; the padded work buffer holds the positions contiguously.  One launch can so cover any subset
+// of a batch (the systems still iterating) at any mix of frequencies, each position computing exactly
+// what a launch of it alone computes.
+struct RhsSet {
+    int n = 0;
+    int slot[kMaxRhs] = {};
+    int freq[kMaxRhs] = {};
+    // positions 0..n-1 on slots 0..n-1, all at one frequency
+    static RhsSet uniform(int n, int freq) {
+        RhsSet s;
+        s.n = n;
+        for (int r = 0; r < n && r < kMaxRhs; ++r) s.slot[r] = r, s.freq[r] = freq;
+        return s;
+    }
+};
+
+// per-position data handed to kernels by value (a captured graph records it with the launch)
+struct SlotMap {
+    int slot[kMaxRhs];
+};
+template <typename T>
+struct SlotW2 {      // field slot and w^2 of each position (contrast kernels)
+    int slot[kMaxRhs];
+    T w2[kMaxRhs];
+};
+
+inline int distinct_freqs(const RhsSet& s) {
+    int d = 0;
+    for (int r = 0; r < s.n; ++r) {
+        bool seen = false;
+        for (int k = 0; k < r && !seen; ++k) seen = s.freq[k] == s.freq[r];
+        d += seen ? 0 : 1;
+    }
+    return d;
+}
+
+inline SlotMap slot_map(const RhsSet& s) {
+    SlotMap m{};
+    for (int r = 0; r < s.n; ++r) m.slot[r] = s.slot[r];
+    return m;
+}
+
+// ------------------------------------------------------------------------------------------
 // error reporting
 
 void set_error(const std::string& msg);
@@ -82,15 +131,16 @@ int hip_fail(hipError_t e, const char* what);
 
 struct Profiler {
     bool on = false;
-    static constexpr int kMax = 8192;
+    static constexpr int kMax = 16384;
     std::vector<hipEvent_t> ev;      // 2 per record
     std::vector<int> fam;            // family index per record
+    std::vector<int> rhs, tabs;      // per record: right-hand sides the launch covers, distinct Green's tables it reads
     std::vector<std::string> names;  // family names
     int n = 0;
     int family(const char* name);
-    void begin(hipStream_t s, const char* name);
+    void begin(hipStream_t s, const char* name, int nrhs = 0, int ntab = 0);
     void end(hipStream_t s);
-    int open_family = -1;
+    int open_family = -1, open_rhs = 0, open_tabs = 0;
     ~Profiler();
 };
 
@@ -119,6 +169,7 @@ struct Ctx {
     int num_cu = 256;  // compute units of the device (block-count heuristics)
     int device = 0;    // the HIP device the context was set up on
     int taper = 0;     // absorbing-layer thickness in cells (0: off)
+    int launch_rhs = 0;  // most systems one operator launch of a solve covers (0: all of them)
     // FFT kernel variant per pass and precision: 0 register four-step, 1 LDS Stockham
     // passes: 0 x forward, 1 y forward, 2 z with Green multiply, 3 y inverse, 4 x inverse
     int variant[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
@@ -190,10 +241,9 @@ int dalloc(Ctx* c, void** p, size_t bytes);
 // ------------------------------------------------------------------------------------------
 // host launchers (each returns LS_OK or an error code)
 
-// FFT passes over the padded buffer; see fft.hip
+// FFT passes over the padded buffer (positions of the set) ending in the compact fields Au (slots); see fft.hip
 template <typename T>
-int fft_apply_passes(Ctx* c, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, int nrhs,
-                     bool subtract_from_u);
+int fft_apply_passes(Ctx* c, const RhsSet& set, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, bool subtract_from_u);
 template <typename T>
 int fft_full_3d_forward(Ctx* c, cpx<T>* buf);
 template <typename T>
@@ -202,14 +252,14 @@ template <typename T>
 int autotune_passes(Ctx* c);
 int supported_fft_length(int n);
 
-// contrast kernels; see contrast.hip
+// contrast kernels; see contrast.hip (fields indexed by slot, work and tau by position)
 template <typename T>
-int contrast_to_work(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* work, cpx<T>* tau, int nrhs);
+int contrast_to_work(Ctx* c, const RhsSet& set, const cpx<T>* u, cpx<T>* work, cpx<T>* tau);
 template <typename T>
-int contrast_transposed_epilogue(Ctx* c, int i_omega, const cpx<T>* g, const cpx<T>* y, cpx<T>* out, cpx<T>* tau,
-                                 int nrhs);
+int contrast_transposed_epilogue(Ctx* c, const RhsSet& set, const cpx<T>* g, const cpx<T>* y, cpx<T>* out,
+                                 cpx<T>* tau);
 template <typename T>
-int to_work(Ctx* c, const cpx<T>* f, cpx<T>* work, int nrhs);
+int to_work(Ctx* c, const RhsSet& set, const cpx<T>* f, cpx<T>* work);
 int grad_contrast_launch(Ctx* c, int i_omega, const z128* u, const z128* mu, int nrhs, double* g21, double* grho);
 int fold_background(Ctx* c, const double* dc_in, const double* drho_in, const double fold21[21]);
 bool use_fused_contrast();  // false under LS_CONTRAST=split (the two-kernel contrast, which needs tau)
@@ -226,17 +276,19 @@ int build_green_tables(Ctx* c);
 int rhs_points_launch(Ctx* c, int i_omega, const int* cells, const double* forces, int npts, double t0,
                       z128* b);
 
-// the LS matvec Au = u - Gconv B u, its transpose A^T y = y - B Gconv y, and Gconv f; see capi.hip
+// the LS matvec Au = u - Gconv B u, its transpose A^T y = y - B Gconv y, and Gconv f, for the systems of a
+// set (fields indexed by slot); see capi.hip
 template <typename T>
-int apply_op(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* Au, int nrhs);
+int apply_op(Ctx* c, const RhsSet& set, const cpx<T>* u, cpx<T>* Au);
 template <typename T>
-int apply_T_op(Ctx* c, int i_omega, const cpx<T>* y, cpx<T>* ATy, int nrhs);
+int apply_T_op(Ctx* c, const RhsSet& set, const cpx<T>* y, cpx<T>* ATy);
 template <typename T>
-int convolve_op(Ctx* c, int i_omega, const cpx<T>* f, cpx<T>* out, int nrhs);
+int convolve_op(Ctx* c, const RhsSet& set, const cpx<T>* f, cpx<T>* out);
 
-// solver (BiCGSTAB, mixed-precision refinement); see solver.hip
+// solver (BiCGSTAB, mixed-precision refinement); see solver.hip.  System q (0 <= q < nrhs) is slot q of b,
+// x0 and u_out, at frequency index freq[q].
 int krylov_setup(Ctx* c);  // allocates what BiCGSTAB(l) needs beyond Bi-CGSTAB (called by ls_setup)
-int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int maxit, int precision,
+int solve_systems(Ctx* c, const int* freq, const z128* b, int nrhs, double tol, int maxit, int precision,
                   const z128* x0, z128* u_out, ls_info* info, bool transposed = false);
 
 constexpr int kRedBlocks = 1024;  // fixed partial count: reductions are deterministic

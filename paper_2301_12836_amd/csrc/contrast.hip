@@ -84,11 +84,11 @@ __device__ __forceinline__ void strain_at(const cpx<T>* __restrict__ u, long lon
     eps[5] = deriv(u0, p, sy, j, N2, inv_h) + deriv(u1, p, sx, i, N1, inv_h);
 }
 
-// tau[r][6][n] = dC(p) eps(u_r)(p)
+// tau[r][6][n] = dC(p) eps(u at slot sm.slot[r])(p)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_strain_stress(const cpx<T>* __restrict__ u, cpx<T>* __restrict__ tau,
-                                                            const T* __restrict__ dc, int nrhs, int N1, int N2,
-                                                            int N3, T inv_h) {
+                                                            const T* __restrict__ dc, SlotMap sm, int nrhs, int N1,
+                                                            int N2, int N3, T inv_h) {
     const long long n = (long long)N1 * N2 * N3;
     const long long lb = xcd_logical_block(blockIdx.x, (n + kThreads - 1) / kThreads);
     const long long p = lb * kThreads + threadIdx.x;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_strain_stress(const cpx<T>* __rest
     for (int q = 0; q < 21; ++q) C[q] = dc[q * n + p];
     for (int r = 0; r < nrhs; ++r) {
         cpx<T> eps[6];
-        strain_at(u + (long long)r * 3 * n, n, p, i, j, k, N1, N2, N3, inv_h, eps);
+        strain_at(u + (long long)sm.slot[r] * 3 * n, n, p, i, j, k, N1, N2, N3, inv_h, eps);
         cpx<T>* tr = tau + (long long)r * 6 * n;
 #pragma unroll
         for (int I = 0; I < 6; ++I) {
@@ -113,14 +113,16 @@ __global__ __launch_bounds__(kThreads) void k_strain_stress(const cpx<T>* __rest
     }
 }
 
-// f_c(p) = -sum_a (D_a^T tau_{V(a,c)})(p) + w^2 drho(p) u_c(p).
-// OUT 0: f written to the padded work buffer (layout of zplane_offset; component pitch N3 L2 L1).
-// OUT 1: the transposed operator's epilogue, work[compact] = y - f (work is then a compact field array).
+// f_c(p) = -sum_a (D_a^T tau_{V(a,c)})(p) + w^2 drho(p) u_c(p), for position r (tau[r]) on field slot
+// sw.slot[r] at w^2 = sw.w2[r].
+// OUT 0: f written to the padded work buffer at position r (layout of zplane_offset; component pitch N3 L2 L1).
+// OUT 1: the transposed operator's epilogue, work[compact] = y - f (work is then a compact field array,
+// indexed by slot like y).
 template <typename T, int OUT>
 __global__ __launch_bounds__(kThreads) void k_divergence(const cpx<T>* __restrict__ tau, const cpx<T>* __restrict__ u,
                                                          const T* __restrict__ drho, cpx<T>* __restrict__ work,
-                                                         int nrhs, int N1, int N2, int N3, int L1, int L2, T inv_h,
-                                                         T w2, const cpx<T>* __restrict__ y, int zbs) {
+                                                         SlotW2<T> sw, int nrhs, int N1, int N2, int N3, int L1,
+                                                         int L2, T inv_h, const cpx<T>* __restrict__ y, int zbs) {
     const long long n = (long long)N1 * N2 * N3;
     const long long lb = xcd_logical_block(blockIdx.x, (n + kThreads - 1) / kThreads);
     const long long p = lb * kThreads + threadIdx.x;
@@ -129,12 +131,14 @@ __global__ __launch_bounds__(kThreads) void k_divergence(const cpx<T>* __restric
     const int j = (int)((p / N1) % N2);
     const int k = (int)(p / ((long long)N1 * N2));
     const long long sx = 1, sy = N1, sz = (long long)N1 * N2;
-    const T wr = w2 * drho[p];
+    const T dr = drho[p];
     const long long cpitch = (long long)N3 * L2 * L1;
     const long long wpos = zplane_offset(k, zbs, L2, L1) + zrow_offset(j, zbs, L1) + i;
     for (int r = 0; r < nrhs; ++r) {
+        const T wr = sw.w2[r] * dr;
+        const long long so = (long long)sw.slot[r] * 3 * n;
         const cpx<T>* t = tau + (long long)r * 6 * n;
-        const cpx<T>* ur = u + (long long)r * 3 * n;
+        const cpx<T>* ur = u + so;
         // Voigt index of the pair (a, c): 11->0, 22->1, 33->2, 23->3, 13->4, 12->5
         const cpx<T> f0 = deriv_t(t + 0 * n, p, sx, i, N1, inv_h) + deriv_t(t + 5 * n, p, sy, j, N2, inv_h) +
                           deriv_t(t + 4 * n, p, sz, k, N3, inv_h);
@@ -148,8 +152,8 @@ __global__ __launch_bounds__(kThreads) void k_divergence(const cpx<T>* __restric
             wr_[cpitch] = wr * ur[n + p] - f1;
             wr_[2 * cpitch] = wr * ur[2 * n + p] - f2;
         } else {
-            const cpx<T>* yr = y + (long long)r * 3 * n;
-            cpx<T>* o = work + (long long)r * 3 * n;
+            const cpx<T>* yr = y + so;
+            cpx<T>* o = work + so;
             o[p] = yr[p] - (wr * ur[p] - f0);
             o[n + p] = yr[n + p] - (wr * ur[n + p] - f1);
             o[2 * n + p] = yr[2 * n + p] - (wr * ur[2 * n + p] - f2);
@@ -201,11 +205,13 @@ __device__ __forceinline__ cpx<T> w3(const W3<T>& w, cpx<T> fm, cpx<T> f0, cpx<T
 // boundary): every LDS value they touch is finite, since u planes are stored whole (zeros outside the
 // grid) and the tau planes start zeroed and only ever receive finite values.
 // OUT 0: f into the padded work buffer; OUT 1: out = y - f (the transposed operator's epilogue).
+// Launch position rhs works on field slot sw.slot[rhs] of u (and y, out for OUT 1) at w^2 = sw.w2[rhs]; OUT 0
+// writes position rhs of the work buffer.
 template <typename T, int BX, int BY, int NT, int MINB, bool DB, int OUT>
 __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     const cpx<T>* __restrict__ u, const T* __restrict__ dc, const T* __restrict__ drho, cpx<T>* __restrict__ out,
-    const cpx<T>* __restrict__ y, int nrhs, int N1, int N2, int N3, int L1, int L2, T inv_h, T w2, int tx, int ty,
-    int nzc, long long nb_real, int zbs) {
+    const cpx<T>* __restrict__ y, SlotW2<T> sw, int nrhs, int N1, int N2, int N3, int L1, int L2, T inv_h, int tx,
+    int ty, int nzc, long long nb_real, int zbs) {
     constexpr int NOWN = BX * BY;
     constexpr int UX = BX + 4, UY = BY + 4, UP = UX * UY;  // u plane (halo 2)
     constexpr int SX = BX + 2, SY = BY + 2, SP = SX * SY;  // tau plane (halo 1)
@@ -227,7 +233,9 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     const int zend = min(z0 + nzc, N3);
     const long long n = (long long)N1 * N2 * N3;
     const long long plane = (long long)N1 * N2;
-    const cpx<T>* ur = u + (long long)rhs * 3 * n;
+    const long long so = (long long)sw.slot[rhs] * 3 * n;   // this position's field slot
+    const T w2 = sw.w2[rhs];
+    const cpx<T>* ur = u + so;
 
     // role: 0 owned cell, 1 y-face halo cell, 2 x-face halo cell, 3 idle; (lx, ly) in plane coordinates
     int role, lx, ly;
@@ -413,8 +421,8 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
                 store_nt(&w_[cpitch], g1);
                 store_nt(&w_[2 * cpitch], g2);
             } else {
-                const cpx<T>* yr = y + (long long)rhs * 3 * n;
-                cpx<T>* o_ = out + (long long)rhs * 3 * n;
+                const cpx<T>* yr = y + so;
+                cpx<T>* o_ = out + so;
                 o_[p] = yr[p] - g0;
                 o_[n + p] = yr[n + p] - g1;
                 o_[2 * n + p] = yr[2 * n + p] - g2;
@@ -440,10 +448,11 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     }
 }
 
-// compact field f[r][c][n] -> zero-padded work buffer (layout of zplane_offset; data cells only)
+// compact field f[slot][c][n] -> zero-padded work buffer at position r (layout of zplane_offset; data cells only)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_to_work(const cpx<T>* __restrict__ f, cpx<T>* __restrict__ work,
-                                                      int nrhs, int N1, int N2, int N3, int L1, int L2, int zbs) {
+                                                      SlotMap sm, int nrhs, int N1, int N2, int N3, int L1, int L2,
+                                                      int zbs) {
     const long long n = (long long)N1 * N2 * N3;
     const long long p = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (p >= n) return;
@@ -452,7 +461,8 @@ __global__ __launch_bounds__(kThreads) void k_to_work(const cpx<T>* __restrict__
     const int k = (int)(p / ((long long)N1 * N2));
     const long long cpitch = (long long)N3 * L2 * L1;
     const long long wpos = zplane_offset(k, zbs, L2, L1) + zrow_offset(j, zbs, L1) + i;
-    for (int r = 0; r < 3 * nrhs; ++r) work[r * cpitch + wpos] = f[r * n + p];
+    for (int r = 0; r < nrhs; ++r)
+        for (int c = 0; c < 3; ++c) work[(3LL * r + c) * cpitch + wpos] = f[(3LL * sm.slot[r] + c) * n + p];
 }
 
 // Absorbing-layer weight of cell (i, j, k) (Eq 23-25): 1 - exp(-l^2 / (N_a h^2)) within d cells of a face,
@@ -636,93 +646,103 @@ struct FusedShape<double> {
     static constexpr bool DB = false;
 };
 
+template <typename T>
+SlotW2<T> slot_w2(const Ctx* c, const RhsSet& set) {
+    SlotW2<T> sw{};
+    for (int r = 0; r < set.n; ++r) {
+        const double w = c->omega[set.freq[r]];
+        sw.slot[r] = set.slot[r];
+        sw.w2[r] = T(w * w);
+    }
+    return sw;
+}
+
 template <typename T, int OUT>
-int launch_fused(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* out, const cpx<T>* y, int nrhs) {
+int launch_fused(Ctx* c, const RhsSet& set, const cpx<T>* u, cpx<T>* out, const cpx<T>* y) {
     using S = FusedShape<T>;
+    const int nrhs = set.n;
     const int tx = (c->n1 + S::BX - 1) / S::BX, ty = (c->n2 + S::BY - 1) / S::BY;
     const long long cols = (long long)tx * ty * nrhs;
     const int nzc = fused_z_chunk(c->n3, cols, (long long)c->num_cu * S::PER_CU);
     const long long nb = cols * ((c->n3 + nzc - 1) / nzc);
     const unsigned nbl = (unsigned)((nb + 7) / 8 * 8);
-    const double w = c->omega[i_omega];
-    c->prof.begin(c->stream, OUT == 0 ? LS_PNAME(T, "contrast_fused") : LS_PNAME(T, "contrast_fused_T"));
+    c->prof.begin(c->stream, OUT == 0 ? LS_PNAME(T, "contrast_fused") : LS_PNAME(T, "contrast_fused_T"), nrhs);
     hipLaunchKernelGGL((k_contrast_zmarch<T, S::BX, S::BY, S::NT, S::PER_CU, S::DB, OUT>), dim3(nbl), dim3(S::NT), 0,
-                       c->stream, u, contrast_of<T>(c), density_of<T>(c), out, y, nrhs, c->n1, c->n2, c->n3, c->L1,
-                       c->L2, T(1.0 / c->h), T(w * w), tx, ty, nzc, nb, c->zbs);
+                       c->stream, u, contrast_of<T>(c), density_of<T>(c), out, y, slot_w2<T>(c, set), nrhs, c->n1,
+                       c->n2, c->n3, c->L1, c->L2, T(1.0 / c->h), tx, ty, nzc, nb, c->zbs);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
 }
 
 template <typename T>
-int contrast_to_work(Ctx* c, int i_omega, const cpx<T>* u, cpx<T>* work, cpx<T>* tau, int nrhs) {
-    if (use_fused_contrast()) return launch_fused<T, 0>(c, i_omega, u, work, nullptr, nrhs);
+int contrast_to_work(Ctx* c, const RhsSet& set, const cpx<T>* u, cpx<T>* work, cpx<T>* tau) {
+    if (use_fused_contrast()) return launch_fused<T, 0>(c, set, u, work, nullptr);
     const long long n = c->ncell;
     // XCD-aware order: grid padded to a multiple of 8, neighbouring cells share an L2
     const unsigned nb = (unsigned)(((n + kThreads - 1) / kThreads + 7) / 8 * 8);
     const T inv_h = T(1.0 / c->h);
-    const double w = c->omega[i_omega];
-    c->prof.begin(c->stream, LS_PNAME(T, "contrast_strain_stress"));
-    hipLaunchKernelGGL((k_strain_stress<T>), dim3(nb), dim3(kThreads), 0, c->stream, u, tau, contrast_of<T>(c), nrhs,
-                       c->n1, c->n2, c->n3, inv_h);
+    const SlotW2<T> sw = slot_w2<T>(c, set);
+    c->prof.begin(c->stream, LS_PNAME(T, "contrast_strain_stress"), set.n);
+    hipLaunchKernelGGL((k_strain_stress<T>), dim3(nb), dim3(kThreads), 0, c->stream, u, tau, contrast_of<T>(c),
+                       slot_map(set), set.n, c->n1, c->n2, c->n3, inv_h);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
-    c->prof.begin(c->stream, LS_PNAME(T, "contrast_divergence"));
+    c->prof.begin(c->stream, LS_PNAME(T, "contrast_divergence"), set.n);
     hipLaunchKernelGGL((k_divergence<T, 0>), dim3(nb), dim3(kThreads), 0, c->stream, tau, u, density_of<T>(c), work,
-                       nrhs, c->n1, c->n2, c->n3, c->L1, c->L2, inv_h, T(w * w), nullptr, c->zbs);
+                       sw, set.n, c->n1, c->n2, c->n3, c->L1, c->L2, inv_h, nullptr, c->zbs);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
 }
 
-template int contrast_to_work<double>(Ctx*, int, const z128*, z128*, z128*, int);
-template int contrast_to_work<float>(Ctx*, int, const z64*, z64*, z64*, int);
+template int contrast_to_work<double>(Ctx*, const RhsSet&, const z128*, z128*, z128*);
+template int contrast_to_work<float>(Ctx*, const RhsSet&, const z64*, z64*, z64*);
 
 // out = y - B g  (the last step of the transposed operator A^T y = y - B Gconv y, with g = Gconv y)
 template <typename T>
-int contrast_transposed_epilogue(Ctx* c, int i_omega, const cpx<T>* g, const cpx<T>* y, cpx<T>* out, cpx<T>* tau,
-                                 int nrhs) {
-    if (use_fused_contrast()) return launch_fused<T, 1>(c, i_omega, g, out, y, nrhs);
+int contrast_transposed_epilogue(Ctx* c, const RhsSet& set, const cpx<T>* g, const cpx<T>* y, cpx<T>* out,
+                                 cpx<T>* tau) {
+    if (use_fused_contrast()) return launch_fused<T, 1>(c, set, g, out, y);
     const long long n = c->ncell;
     const unsigned nb = (unsigned)(((n + kThreads - 1) / kThreads + 7) / 8 * 8);
     const T inv_h = T(1.0 / c->h);
-    const double w = c->omega[i_omega];
-    c->prof.begin(c->stream, LS_PNAME(T, "contrast_strain_stress"));
-    hipLaunchKernelGGL((k_strain_stress<T>), dim3(nb), dim3(kThreads), 0, c->stream, g, tau, contrast_of<T>(c), nrhs,
-                       c->n1, c->n2, c->n3, inv_h);
+    c->prof.begin(c->stream, LS_PNAME(T, "contrast_strain_stress"), set.n);
+    hipLaunchKernelGGL((k_strain_stress<T>), dim3(nb), dim3(kThreads), 0, c->stream, g, tau, contrast_of<T>(c),
+                       slot_map(set), set.n, c->n1, c->n2, c->n3, inv_h);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
-    c->prof.begin(c->stream, LS_PNAME(T, "contrast_divergence_T"));
+    c->prof.begin(c->stream, LS_PNAME(T, "contrast_divergence_T"), set.n);
     hipLaunchKernelGGL((k_divergence<T, 1>), dim3(nb), dim3(kThreads), 0, c->stream, tau, g, density_of<T>(c), out,
-                       nrhs, c->n1, c->n2, c->n3, c->L1, c->L2, inv_h, T(w * w), y, c->zbs);
+                       slot_w2<T>(c, set), set.n, c->n1, c->n2, c->n3, c->L1, c->L2, inv_h, y, c->zbs);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
 }
 
-template int contrast_transposed_epilogue<double>(Ctx*, int, const z128*, const z128*, z128*, z128*, int);
-template int contrast_transposed_epilogue<float>(Ctx*, int, const z64*, const z64*, z64*, z64*, int);
+template int contrast_transposed_epilogue<double>(Ctx*, const RhsSet&, const z128*, const z128*, z128*, z128*);
+template int contrast_transposed_epilogue<float>(Ctx*, const RhsSet&, const z64*, const z64*, z64*, z64*);
 
 template <typename T>
-int to_work(Ctx* c, const cpx<T>* f, cpx<T>* work, int nrhs) {
+int to_work(Ctx* c, const RhsSet& set, const cpx<T>* f, cpx<T>* work) {
     const long long n = c->ncell;
     const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
-    c->prof.begin(c->stream, LS_PNAME(T, "to_work"));
-    hipLaunchKernelGGL((k_to_work<T>), dim3(nb), dim3(kThreads), 0, c->stream, f, work, nrhs, c->n1, c->n2, c->n3,
-                       c->L1, c->L2, c->zbs);
+    c->prof.begin(c->stream, LS_PNAME(T, "to_work"), set.n);
+    hipLaunchKernelGGL((k_to_work<T>), dim3(nb), dim3(kThreads), 0, c->stream, f, work, slot_map(set), set.n, c->n1,
+                       c->n2, c->n3, c->L1, c->L2, c->zbs);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
 }
 
-template int to_work<double>(Ctx*, const z128*, z128*, int);
-template int to_work<float>(Ctx*, const z64*, z64*, int);
+template int to_work<double>(Ctx*, const RhsSet&, const z128*, z128*);
+template int to_work<float>(Ctx*, const RhsSet&, const z64*, z64*);
 
 int grad_contrast_launch(Ctx* c, int i_omega, const z128* u, const z128* mu, int nrhs, double* g21, double* grho) {
     const long long n = c->ncell;
     const unsigned nb = (unsigned)((n + kThreads - 1) / kThreads);
     const double w = c->omega[i_omega];
-    c->prof.begin(c->stream, "grad_contrast.c128");
+    c->prof.begin(c->stream, "grad_contrast.c128", nrhs);
     hipLaunchKernelGGL(k_grad_contrast, dim3(nb), dim3(kThreads), 0, c->stream, u, mu, g21, grho, nrhs, c->n1, c->n2,
                        c->n3, 1.0 / c->h, w * w, c->taper);
     c->prof.end(c->stream);

@@ -49,13 +49,33 @@ __device__ __forceinline__ long long compact_row(long long line, int D2, int zbs
     return g * D2 + (rem & ((1 << zbs) - 1)) * (D2 >> zbs) + (rem >> zbs);
 }
 
-// MODE 0: in place into data; 1: out = u - v (compact); 2: out = v (compact)
+// k-space Green's table of each launch position (z passes), by value
+template <typename T>
+struct GreenTabs {
+    const cpx<T>* g[kMaxRhs];
+};
+
+// Row of the compact field arrays (indexed by slot) that x line `line` of the work buffer (indexed by
+// position) ends in: lines run over positions in blocks of lpr = 3 N3 N2 lines (a multiple of D2).  rr is
+// the line's position; line counts stay below 2^31 (at most 3 x 64 x 256 x 256 lines).
+__device__ __forceinline__ long long slot_row(long long line, long long lpr, unsigned rr, const SlotMap& sm, int D2,
+                                              int zbs) {
+    return (long long)sm.slot[rr] * lpr + compact_row(line - (long long)rr * lpr, D2, zbs);
+}
+// position of a line: block-uniform (scalar) when every block of TY lines lies in one position
+template <int TY>
+__device__ __forceinline__ unsigned line_position(long long line, long long lpr) {
+    if (lpr % TY == 0) return (unsigned)(((unsigned)blockIdx.x * (unsigned)TY) / (unsigned)lpr);
+    return (unsigned)line / (unsigned)lpr;
+}
+
+// MODE 0: in place into data; 1: out = u - v (compact, slot rows); 2: out = v (compact, slot rows)
 template <typename T, int L, int TY, int SIGN, int MODE>
 __global__ __launch_bounds__(kThreads) void k_fft_contig(cpx<T>* __restrict__ data, long long nlines, int D2,
                                                          long long S1, long long S2, int n_in, int n_out,
                                                          const cpx<T>* __restrict__ tw,
                                                          const cpx<T>* __restrict__ u, cpx<T>* __restrict__ out,
-                                                         int zbs) {
+                                                         int zbs, SlotMap sm, long long lpr) {
     constexpr int LDP = TY + 1;
     __shared__ cpx<T> s[L * LDP];
     const int tid = threadIdx.x;
@@ -81,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_contig(cpx<T>* __restrict__ da
                 const long long o1 = line / D2, o2 = line - o1 * D2;
                 data[o1 * S1 + o2 * S2 + e] = v;
             } else {
-                const long long q = compact_row(line, D2, zbs) * n_out + e;   // compact [.. rows ..][n_out]
+                const long long q = slot_row(line, lpr, line_position<TY>(line, lpr), sm, D2, zbs) * n_out + e;
                 if constexpr (MODE == 1)
                     out[q] = u[q] - v;
                 else
@@ -148,8 +168,7 @@ __device__ __forceinline__ void load_g6(const z128* __restrict__ ghat, long long
 template <typename T, int L, int TX, bool HALF = false, int ZBS = 0>
 __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1, int L2,
                                                          long long CS, long long RS, long long ES, int n3,
-                                                         const cpx<T>* __restrict__ ghat,
-                                                         const cpx<T>* __restrict__ tw) {
+                                                         GreenTabs<T> gt, const cpx<T>* __restrict__ tw) {
     constexpr int zbs = ZBS;   // work buffer layout (zplane_offset), fixed at compile time
     constexpr int NL = 3 * TX;
     __shared__ cpx<T> s[L * NL];
@@ -157,6 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_zgreen(cpx<T>* __restrict__ da
     const int rhs = blockIdx.x % nrhs;
     const int x0 = (blockIdx.x / nrhs) * TX;
     const int y = paired_row(blockIdx.y, L2);
+    const cpx<T>* __restrict__ ghat = gt.g[rhs];
     (void)ES;   // the plane pitch: element offsets follow zplane_offset
     cpx<T>* base = data + (long long)rhs * RS + zrow_offset(y, zbs, L1) + x0;
     for (int idx = tid; idx < L * NL; idx += kThreads) {
@@ -297,10 +317,10 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
                                                                     int n_out, const cpx<T>* __restrict__ tw,
                                                                     const cpx<T>* __restrict__ u,
                                                                     cpx<T>* __restrict__ out,
-                                                                    const cpx<T>* __restrict__ dot_a = nullptr,
-                                                                    double* __restrict__ dot_parts = nullptr,
-                                                                    long long dot_lines = 1, int dot_nparts = 0,
-                                                                    int zbs = 0) {
+                                                                    const cpx<T>* __restrict__ dot_a,
+                                                                    double* __restrict__ dot_parts,
+                                                                    long long dot_lines, int dot_nparts,
+                                                                    int zbs, SlotMap sm, long long lpr) {
     using F = FourStep<L>;
     constexpr int LDP = TY + 1;
     __shared__ cpx<T> lds[L * LDP];
@@ -309,6 +329,8 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
     stage_twiddles<T, L>(tws, tw, tid, TY * F::N1);
     const long long line = (long long)blockIdx.x * TY + ln;
     const bool valid = line < nlines;
+    // compact output row of this thread's line (MODE 1, 2), computed once
+    const long long orow = (MODE == 0 || !valid) ? 0 : slot_row(line, lpr, line_position<TY>(line, lpr), sm, D2, zbs);
     const long long o1 = line / D2, o2 = line - o1 * D2;
     cpx<T>* base = data + o1 * S1 + o2 * S2;
     cpx<T> v[F::N2];
@@ -341,7 +363,7 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
             for (int j = 0; j < F::N2; ++j) {
                 const int e = q + F::N1 * j;
                 if (!half_slot<L, PRUNE>(j) && e < n_out) {
-                    const long long qq = compact_row(line, D2, zbs) * n_out + e;
+                    const long long qq = orow * n_out + e;
                     if constexpr (MODE == 1) {
                         const cpx<T> uu = load_nt(&u[qq]);
                         const cpx<T> o = uu - v[j];
@@ -379,7 +401,7 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
                 for (int w = 0; w < NW; ++w) x += red[w][tid];
                 const long long l0 = (long long)blockIdx.x * TY;
                 const long long rr = l0 / dot_lines, blk = (l0 - rr * dot_lines) / TY;
-                dot_parts[(rr * kRedSlots + tid) * dot_nparts + blk] = x;
+                dot_parts[((long long)sm.slot[rr] * kRedSlots + tid) * dot_nparts + blk] = x;
             }
         }
     }
@@ -424,7 +446,7 @@ __device__ __forceinline__ cpx<T> cdot3(cpx<T> g1, cpx<T> f1, cpx<T> g2, cpx<T> 
 template <typename T, int L, int TX, bool HALF = false, int ZBS = 0>
 __global__ __launch_bounds__((TX * ZSplit<T, L, HALF>::N1), (sizeof(T) == 4 ? (z_paired<T, L, HALF>() ? 2 : (L >= 512 ? 1 : 3)) : 1)) void k_fs_zgreen(cpx<T>* __restrict__ data, int nrhs, int L1,
                                                                     int L2, long long CS, long long RS, long long ES,
-                                                                    int n3, const cpx<T>* __restrict__ ghat,
+                                                                    int n3, GreenTabs<T> gt,
                                                                     const cpx<T>* __restrict__ tw, long long nb_real) {
     using F = ZSplit<T, L, HALF>;
     constexpr bool PAIRED = z_paired<T, L, HALF>();
@@ -437,6 +459,7 @@ __global__ __launch_bounds__((TX * ZSplit<T, L, HALF>::N1), (sizeof(T) == 4 ? (z
     stage_twiddles<T, L>(tws, tw, tid, TX * F::N1);
     const int ntx = L1 / TX;
     const int rhs = (int)(lb % nrhs);
+    const cpx<T>* __restrict__ ghat = gt.g[rhs];   // this position's frequency
     const int xt = paired_row((int)((lb / nrhs) % ntx), ntx);
     const int y = paired_row((int)(lb / ((long long)nrhs * ntx)), L2);
     const int kx0 = xt * TX + t;
@@ -548,11 +571,12 @@ bool use_fourstep() {
     return fs;
 }
 
+// sm, lpr: the slot of each position and the lines per position, for the compact outputs of MODE 1 and 2
 template <typename T, int SIGN, int MODE, bool PRUNE, int DOT = 0>
 int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long long S1, long long S2, int n_in,
                   int n_out, const cpx<T>* tw, const cpx<T>* u, cpx<T>* out, const char* name, int variant = 0,
-                  int zbs = 0) {
-    c->prof.begin(c->stream, name);
+                  int zbs = 0, const SlotMap& sm = SlotMap{}, long long lpr = 1, int nrhs = 0) {
+    c->prof.begin(c->stream, name, nrhs);
     const bool fs = variant == 0 && use_fourstep();
     if (DOT != 0 && !fs) return fail(LS_ERR_STATE, "fused inner products need the register four-step x pass");
     switch (L) {
@@ -565,7 +589,7 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
                 hipLaunchKernelGGL((k_fs_contig<T, LL, TY, SIGN, MODE, PRUNE, DOT>), dim3((unsigned)nb),             \
                                    dim3(fs_threads<T, LL>()), 0, c->stream, data, nlines, D2, S1, S2, n_in,  \
                                    n_out, tw, u, out, (const cpx<T>*)c->dot.a, c->dot.parts, c->dot.lines,   \
-                                   c->dot.nparts, zbs);                                                      \
+                                   c->dot.nparts, zbs, sm, lpr);                                             \
                 break;                                                                                       \
             }                                                                                                \
         }                                                                                                    \
@@ -573,7 +597,7 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
         constexpr int TY = contig_lines<T, LL>();                                                            \
         const long long nb = (nlines + TY - 1) / TY;                                                         \
         hipLaunchKernelGGL((k_fft_contig<T, LL, TY, SIGN, MODE>), dim3((unsigned)nb), dim3(kThreads), 0,     \
-                           c->stream, data, nlines, D2, S1, S2, n_in, n_out, tw, u, out, zbs);               \
+                           c->stream, data, nlines, D2, S1, S2, n_in, n_out, tw, u, out, zbs, sm, lpr);      \
         break;                                                                                               \
     }
         LS_FOR_LENGTHS(CASE)
@@ -588,11 +612,11 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
 
 template <typename T, int SIGN, bool PRUNE>
 int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long long S1, long long S2, long long ES,
-                   int n_in, int n_out, const cpx<T>* tw, const char* name, int variant = 0) {
+                   int n_in, int n_out, const cpx<T>* tw, const char* name, int variant = 0, int nrhs = 0) {
     constexpr int TX = strided_cols<T>();
     static_assert(TX == seg_cols<T>(), "both strided kernels use 128-byte column tiles");
     if (NX % TX) return fail(LS_ERR_ARG, "x length not a multiple of the column tile");
-    c->prof.begin(c->stream, name);
+    c->prof.begin(c->stream, name, nrhs);
     const bool fs = variant == 0 && use_fourstep();
     switch (L) {
 #define CASE(LL)                                                                                             \
@@ -627,7 +651,7 @@ constexpr int z_threads() {
 // Register z pass for one table layout (HALF) and work-buffer layout (c->zbs): 1 if launched, 0 if the
 // register kernel does not apply (the caller takes the LDS kernel), -1 on a tile mismatch.
 template <typename T, int LL, bool HALF>
-int try_fs_z(Ctx* c, bool fs, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES, const cpx<T>* ghat,
+int try_fs_z(Ctx* c, bool fs, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES, const GreenTabs<T>& ghat,
              const cpx<T>* tw) {
     if constexpr (fs_z_ok<T, LL, HALF>()) {
         // the register kernel needs 2^zbs to divide the threads per line
@@ -649,7 +673,7 @@ int try_fs_z(Ctx* c, bool fs, cpx<T>* data, int nrhs, long long CS, long long RS
 }
 // LDS z pass for one work-buffer layout (ZBS, compile time), full or half table
 template <typename T, int LL, int TX, int ZBS>
-void launch_lds_z(Ctx* c, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES, const cpx<T>* ghat,
+void launch_lds_z(Ctx* c, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES, const GreenTabs<T>& ghat,
                   const cpx<T>* tw) {
     const dim3 grid(nrhs * (c->L1 / TX), c->L2, 1);
     if (c->green_half)
@@ -661,7 +685,8 @@ void launch_lds_z(Ctx* c, cpx<T>* data, int nrhs, long long CS, long long RS, lo
 }
 
 template <typename T>
-int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<T>* tw, int variant = 0) {
+int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const GreenTabs<T>& ghat, const cpx<T>* tw, int variant = 0,
+                  int ntab = 1) {
     const int L1 = c->L1, L2 = c->L2, L = c->L3;
     const long long CS = (long long)c->n3 * L2 * L1;
     const long long RS = 3 * CS;
@@ -672,7 +697,7 @@ int launch_zgreen(Ctx* c, cpx<T>* data, int nrhs, const cpx<T>* ghat, const cpx<
                                           : (long long)(L / 2 + 1) * (L2 / 2 + 1) * (L1 / 2 + 1);
     const bool off32 = (33 * ES + seg_cols<T>()) * (long long)sizeof(cpx<T>) < (1LL << 32) &&
                        table * 6 * (long long)sizeof(cpx<T>) < (1LL << 32);
-    c->prof.begin(c->stream, LS_PNAME(T, "fft_z_green"));
+    c->prof.begin(c->stream, LS_PNAME(T, "fft_z_green"), nrhs, ntab);
     const bool fs = variant == 0 && use_fourstep() && off32;
     switch (L) {
 #define CASE(LL)                                                                                              \
@@ -713,6 +738,13 @@ const z128* green_table<double>(const Ctx* c, int i) { return c->ghat[i]; }
 template <>
 const z64* green_table<float>(const Ctx* c, int i) { return c->ghat32[i]; }
 
+template <typename T>
+GreenTabs<T> green_tabs(const Ctx* c, const RhsSet& set) {
+    GreenTabs<T> g{};
+    for (int r = 0; r < set.n; ++r) g.g[r] = green_table<T>(c, set.freq[r]);
+    return g;
+}
+
 }  // namespace
 
 // the smallest supported length (2^a or 3 * 2^a, 16..512) that holds the linear convolution of n cells
@@ -726,10 +758,12 @@ int supported_fft_length(int n) {
 // One pass of the apply (0 x forward, 1 y forward, 2 z with the Green multiply, 3 y inverse,
 // 4 x inverse with the epilogue) with kernel variant 0 (register four-step) or 1 (LDS Stockham).
 template <typename T>
-int run_pass(Ctx* c, int pass, int variant, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, int nrhs,
+int run_pass(Ctx* c, int pass, int variant, const RhsSet& set, cpx<T>* work, const cpx<T>* u, cpx<T>* Au,
              bool subtract_from_u) {
     const int N1 = c->n1, N2 = c->n2, N3 = c->n3, L1 = c->L1, L2 = c->L2, L3 = c->L3;
+    const int nrhs = set.n;
     const long long rc = 3LL * nrhs;
+    const long long lpr = 3LL * N3 * N2;   // x lines per position
     const long long plane = (long long)L2 * L1;
     // work buffer layout (zplane_offset): x lines run over z blocks (stride plane B) and the N2 B data rows of
     // a block (stride L1); y lines over z blocks and the B planes of a block, with elements B L1 apart
@@ -739,40 +773,43 @@ int run_pass(Ctx* c, int pass, int variant, int i_omega, cpx<T>* work, const cpx
         case 0:  // x forward on the N2 x N3 data lines
             return launch_contig<T, -1, 0, true>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, N1, L1,
                                                  twiddles<T>(c, L1), nullptr, nullptr, LS_PNAME(T, "fft_x_fwd"), variant,
-                                                 zbs);
+                                                 zbs, SlotMap{}, 1, nrhs);
         case 1:  // y forward on all L1 columns of the N3 data planes
             return launch_strided<T, -1, true>(c, L2, work, L1, B, (int)((rc * N3) >> zbs), zblock, L1, (long long)L1 * B,
-                                               N2, L2, twiddles<T>(c, L2), LS_PNAME(T, "fft_y_fwd"), variant);
+                                               N2, L2, twiddles<T>(c, L2), LS_PNAME(T, "fft_y_fwd"), variant, nrhs);
         case 2:
-            return launch_zgreen<T>(c, work, nrhs, green_table<T>(c, i_omega), twiddles<T>(c, L3), variant);
+            return launch_zgreen<T>(c, work, nrhs, green_tabs<T>(c, set), twiddles<T>(c, L3), variant,
+                                    distinct_freqs(set));
         case 3:
             return launch_strided<T, +1, true>(c, L2, work, L1, B, (int)((rc * N3) >> zbs), zblock, L1, (long long)L1 * B,
-                                               L2, N2, twiddles<T>(c, L2), LS_PNAME(T, "fft_y_inv"), variant);
-        default:
+                                               L2, N2, twiddles<T>(c, L2), LS_PNAME(T, "fft_y_inv"), variant, nrhs);
+        default: {
+            const SlotMap sm = slot_map(set);
             if (subtract_from_u && c->dot.mode == 1)
                 return launch_contig<T, +1, 1, true, 1>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, L1, N1,
-                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant,
-                                                        zbs);
+                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_rv"), variant,
+                                                        zbs, sm, lpr, nrhs);
             if (subtract_from_u && c->dot.mode == 2)
                 return launch_contig<T, +1, 1, true, 2>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, L1, N1,
-                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant,
-                                                        zbs);
+                                                        twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_ts"), variant,
+                                                        zbs, sm, lpr, nrhs);
             if (subtract_from_u)
                 return launch_contig<T, +1, 1, true>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, L1, N1,
                                                      twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant,
-                                                     zbs);
+                                                     zbs, sm, lpr, nrhs);
             return launch_contig<T, +1, 2, true>(c, L1, work, rc * N3 * N2, N2 * B, zblock, L1, L1, N1,
-                                                 twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_epi"), variant, zbs);
+                                                 twiddles<T>(c, L1), u, Au, LS_PNAME(T, "fft_x_inv_conv"), variant, zbs,
+                                                 sm, lpr, nrhs);
+        }
     }
 }
 
 // Au = u - Gconv(f) (subtract_from_u) or Au = Gconv(f), where f already sits in work.
 template <typename T>
-int fft_apply_passes(Ctx* c, int i_omega, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, int nrhs,
-                     bool subtract_from_u) {
+int fft_apply_passes(Ctx* c, const RhsSet& set, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, bool subtract_from_u) {
     const int prec = sizeof(T) == 8 ? 0 : 1;
     for (int pass = 0; pass < 5; ++pass) {
-        const int rc_ = run_pass<T>(c, pass, c->variant[prec][pass], i_omega, work, u, Au, nrhs, subtract_from_u);
+        const int rc_ = run_pass<T>(c, pass, c->variant[prec][pass], set, work, u, Au, subtract_from_u);
         if (rc_) return rc_;
     }
     return LS_OK;
@@ -785,7 +822,7 @@ int autotune_passes(Ctx* c) {
     const int prec = sizeof(T) == 8 ? 0 : 1;
     cpx<T>* work = (cpx<T>*)c->work;
     cpx<T>* out = (cpx<T>*)c->gs;
-    const int nrhs = c->max_rhs;
+    const RhsSet set = RhsSet::uniform(c->max_rhs, 0);
     hipEvent_t a, b;
     LS_HIP(hipEventCreate(&a));
     LS_HIP(hipEventCreate(&b));
@@ -793,11 +830,11 @@ int autotune_passes(Ctx* c) {
     for (int pass = 0; pass < 5 && rc_ == LS_OK; ++pass) {
         float best = 0.f;
         for (int variant = 0; variant < 2 && rc_ == LS_OK; ++variant) {
-            rc_ = run_pass<T>(c, pass, variant, 0, work, out, out, nrhs, false);  // warm-up
+            rc_ = run_pass<T>(c, pass, variant, set, work, out, out, false);  // warm-up
             if (rc_) break;
             if (hipEventRecord(a, c->stream) != hipSuccess) rc_ = fail(LS_ERR_HIP, "autotune event");
             for (int k = 0; k < 3 && rc_ == LS_OK; ++k)
-                rc_ = run_pass<T>(c, pass, variant, 0, work, out, out, nrhs, false);
+                rc_ = run_pass<T>(c, pass, variant, set, work, out, out, false);
             if (rc_) break;
             float ms = 0.f;
             if (hipEventRecord(b, c->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
@@ -859,8 +896,8 @@ int fused_dot_blocks(const Ctx* c) {
 template int fused_dot_blocks<double>(const Ctx*);
 template int fused_dot_blocks<float>(const Ctx*);
 
-template int fft_apply_passes<double>(Ctx*, int, z128*, const z128*, z128*, int, bool);
-template int fft_apply_passes<float>(Ctx*, int, z64*, const z64*, z64*, int, bool);
+template int fft_apply_passes<double>(Ctx*, const RhsSet&, z128*, const z128*, z128*, bool);
+template int fft_apply_passes<float>(Ctx*, const RhsSet&, z64*, const z64*, z64*, bool);
 template int fft_full_3d_forward<double>(Ctx*, z128*);
 
 }  // namespace ls

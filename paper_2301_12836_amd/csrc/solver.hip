@@ -10,6 +10,9 @@
 // the right-hand side's scalars and its active flag, so an iteration is a fixed sequence of
 // stream-ordered launches; the host only reads the flags to decide when to stop.  Reductions
 // use a fixed number of blocks and a fixed tree, so results are bitwise reproducible.
+// Every kernel covers the systems of a slot map (grid dimension y, or x for the one-block kernels): the
+// systems still iterating, at any mix of frequencies, so a system computes the same iterates whichever
+// other systems share its launches, and converged systems drop out of the launches.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -67,7 +70,8 @@ __device__ __forceinline__ cpx<double> wide(cpx<T> a) {
     return {(double)a.x, (double)a.y};
 }
 
-// Loop helper: element indices of this thread for one right-hand side of length m.
+// Loop helper: element indices of this thread for one right-hand side of length m; the system is
+// rr = sm.slot[blockIdx.y].
 #define LS_FOR_ELEMS(m) for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < (m); e += (long long)kRedBlocks * kThreads)
 
 // The Bi-CGSTAB updates stream their vectors once: non-temporal access (about 1 % per solve step).
@@ -77,9 +81,9 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_init(const cpx<T>* __restrict__ b, const cpx<T>* __restrict__ ax,
                                                    cpx<T>* __restrict__ r, cpx<T>* __restrict__ rhat,
                                                    cpx<T>* __restrict__ p, cpx<T>* __restrict__ v, long long m,
-                                                   double* partials) {
+                                                   double* partials, SlotMap sm) {
     __shared__ double sh[2 * kThreads];
-    const int rr = blockIdx.y;
+    const int rr = sm.slot[blockIdx.y];
     const long long off = (long long)rr * m;
     double bb = 0, nr = 0;
     LS_FOR_ELEMS(m) {
@@ -99,8 +103,8 @@ __global__ __launch_bounds__(kThreads) void k_init(const cpx<T>* __restrict__ b,
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update_p(const cpx<T>* __restrict__ r, cpx<T>* __restrict__ p,
                                                        const cpx<T>* __restrict__ v, long long m,
-                                                       const double* __restrict__ state) {
-    const int rr = blockIdx.y;
+                                                       const double* __restrict__ state, SlotMap sm) {
+    const int rr = sm.slot[blockIdx.y];
     const double* st = state + rr * kStateLen;
     if (st[S_ACTIVE] == 0.0) return;
     const cpx<T> beta = {(T)st[S_BETA], (T)st[S_BETA + 1]};
@@ -115,9 +119,10 @@ __global__ __launch_bounds__(kThreads) void k_update_p(const cpx<T>* __restrict_
 // partials: r^H v (complex)
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dot(const cpx<T>* __restrict__ a, const cpx<T>* __restrict__ b,
-                                                  long long m, const double* __restrict__ state, double* partials) {
+                                                  long long m, const double* __restrict__ state, double* partials,
+                                                  SlotMap sm) {
     __shared__ double sh[2 * kThreads];
-    const int rr = blockIdx.y;
+    const int rr = sm.slot[blockIdx.y];
     if (state[rr * kStateLen + S_ACTIVE] == 0.0) return;
     const long long off = (long long)rr * m;
     double re = 0, im = 0;
@@ -133,9 +138,10 @@ __global__ __launch_bounds__(kThreads) void k_dot(const cpx<T>* __restrict__ a, 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_update_s(const cpx<T>* __restrict__ r, const cpx<T>* __restrict__ v,
                                                        cpx<T>* __restrict__ s, long long m,
-                                                       const double* __restrict__ state, double* partials) {
+                                                       const double* __restrict__ state, double* partials,
+                                                       SlotMap sm) {
     __shared__ double sh[2 * kThreads];
-    const int rr = blockIdx.y;
+    const int rr = sm.slot[blockIdx.y];
     const double* st = state + rr * kStateLen;
     if (st[S_ACTIVE] == 0.0) return;
     const cpx<T> al = {(T)st[S_ALPHA], (T)st[S_ALPHA + 1]};
@@ -152,8 +158,8 @@ __global__ __launch_bounds__(kThreads) void k_update_s(const cpx<T>* __restrict_
 // x += alpha p for the systems that converged at the half step
 template <typename T, typename X>
 __global__ __launch_bounds__(kThreads) void k_update_x_half(cpx<X>* __restrict__ x, const cpx<T>* __restrict__ p,
-                                                            long long m, double* __restrict__ state) {
-    const int rr = blockIdx.y;
+                                                            long long m, double* __restrict__ state, SlotMap sm) {
+    const int rr = sm.slot[blockIdx.y];
     const double* st = state + rr * kStateLen;
     if (st[S_FLAG] != 1.0) return;
     const cpx<X> al = {(X)st[S_ALPHA], (X)st[S_ALPHA + 1]};
@@ -168,9 +174,9 @@ __global__ __launch_bounds__(kThreads) void k_update_x_half(cpx<X>* __restrict__
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_dot_ts(const cpx<T>* __restrict__ t, const cpx<T>* __restrict__ s,
                                                      long long m, const double* __restrict__ state,
-                                                     double* partials) {
+                                                     double* partials, SlotMap sm) {
     __shared__ double sh[2 * kThreads];
-    const int rr = blockIdx.y;
+    const int rr = sm.slot[blockIdx.y];
     if (state[rr * kStateLen + S_ACTIVE] == 0.0) return;
     const long long off = (long long)rr * m;
     double re = 0, im = 0, tt = 0;
@@ -191,9 +197,9 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(cpx<X>* __restrict__ x, 
                                                         const cpx<T>* __restrict__ s, const cpx<T>* __restrict__ t,
                                                         cpx<T>* __restrict__ r, const cpx<T>* __restrict__ rhat,
                                                         long long m, const double* __restrict__ state,
-                                                        double* partials) {
+                                                        double* partials, SlotMap sm) {
     __shared__ double sh[2 * kThreads];
-    const int rr = blockIdx.y;
+    const int rr = sm.slot[blockIdx.y];
     const double* st = state + rr * kStateLen;
     if (st[S_ACTIVE] == 0.0) return;
     const cpx<X> alx = {(X)st[S_ALPHA], (X)st[S_ALPHA + 1]};
@@ -219,9 +225,10 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(cpx<X>* __restrict__ x, 
 
 // r = b - ax; partials ||r||^2, ||b||^2   (FP64 true residual)
 __global__ __launch_bounds__(kThreads) void k_residual(const z128* __restrict__ b, const z128* __restrict__ ax,
-                                                       z128* __restrict__ r, long long m, double* partials) {
+                                                       z128* __restrict__ r, long long m, double* partials,
+                                                       SlotMap sm) {
     __shared__ double sh[2 * kThreads];
-    const int rr = blockIdx.y;
+    const int rr = sm.slot[blockIdx.y];
     const long long off = (long long)rr * m;
     double nr = 0, bb = 0;
     LS_FOR_ELEMS(m) {
@@ -236,8 +243,9 @@ __global__ __launch_bounds__(kThreads) void k_residual(const z128* __restrict__ 
 
 // out = scale_r * in (FP64 -> FP32), optionally zero a second buffer
 __global__ __launch_bounds__(kThreads) void k_to32(const z128* __restrict__ in, z64* __restrict__ out, long long m,
-                                                   const double* __restrict__ scale, z64* __restrict__ zero_out) {
-    const int rr = blockIdx.y;
+                                                   const double* __restrict__ scale, z64* __restrict__ zero_out,
+                                                   SlotMap sm) {
+    const int rr = sm.slot[blockIdx.y];
     const double sc = scale[rr];
     const long long off = (long long)rr * m;
     LS_FOR_ELEMS(m) {
@@ -249,8 +257,8 @@ __global__ __launch_bounds__(kThreads) void k_to32(const z128* __restrict__ in, 
 
 // x += scale_r * d (FP32 correction into the FP64 iterate)
 __global__ __launch_bounds__(kThreads) void k_add32(z128* __restrict__ x, const z64* __restrict__ d, long long m,
-                                                    const double* __restrict__ scale) {
-    const int rr = blockIdx.y;
+                                                    const double* __restrict__ scale, SlotMap sm) {
+    const int rr = sm.slot[blockIdx.y];
     const double sc = scale[rr];
     if (sc == 0.0) return;
     const long long off = (long long)rr * m;
@@ -260,20 +268,23 @@ __global__ __launch_bounds__(kThreads) void k_add32(z128* __restrict__ x, const 
     }
 }
 
-__global__ void k_copy(const z128* __restrict__ a, z128* __restrict__ b, long long m) {
-    LS_FOR_ELEMS(m) { b[(long long)blockIdx.y * m + e] = a[(long long)blockIdx.y * m + e]; }
+__global__ void k_copy(const z128* __restrict__ a, z128* __restrict__ b, long long m, SlotMap sm) {
+    const long long off = (long long)sm.slot[blockIdx.y] * m;
+    LS_FOR_ELEMS(m) { b[off + e] = a[off + e]; }
 }
 
 // Sum the kRedBlocks partials of each slot in a fixed order, then advance the scalars.
 enum Phase { PH_INIT = 0, PH_ALPHA = 1, PH_S = 2, PH_OMEGA = 3, PH_RHO = 4, PH_RESID = 5 };
 
 // partials: [rhs][kRedSlots][nparts] (nparts = kRedBlocks, or the x-inverse epilogue's blocks per right-hand
-// side for the inner products fused there)
+// side for the inner products fused there).  PH_INIT: tolerance tol2v[rr] (squared) per system, or tol2.
+// PH_RESID: out[rr] and out[kRedBlocks + rr] by slot.
 __global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict__ partials, int nparts,
                                                        double* __restrict__ state, int phase, int nslots, double tol2,
-                                                       double* __restrict__ out) {
+                                                       double* __restrict__ out, const double* __restrict__ tol2v,
+                                                       SlotMap sm) {
     __shared__ double sh[kRedSlots][kThreads];
-    const int rr = blockIdx.x;
+    const int rr = sm.slot[blockIdx.x];
     double* st = state + rr * kStateLen;
     const int tid = threadIdx.x;
     if (phase != PH_INIT && phase != PH_RESID && st[S_ACTIVE] == 0.0) return;
@@ -294,6 +305,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict_
     auto bad = [](double x) { return !(fabs(x) <= 1.7e308); };
     switch (phase) {
         case PH_INIT: {  // v = (||b||^2, ||r||^2)
+            if (tol2v) tol2 = tol2v[rr];
             st[S_BNORM2] = v[0];
             st[S_RNORM2] = v[1];
             st[S_RHO] = v[1];
@@ -393,9 +405,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const double* __restrict_
     }
 }
 
-__global__ void k_clear_half(double* state, int nrhs) {
-    const int rr = threadIdx.x;
-    if (rr < nrhs && state[rr * kStateLen + S_FLAG] == 1.0) state[rr * kStateLen + S_FLAG] = 0.0;
+__global__ void k_clear_half(double* state, int n, SlotMap sm) {
+    if ((int)threadIdx.x >= n) return;
+    const int rr = sm.slot[threadIdx.x];
+    if (state[rr * kStateLen + S_FLAG] == 1.0) state[rr * kStateLen + S_FLAG] = 0.0;
 }
 
 struct Vecs64 {
@@ -407,12 +420,38 @@ struct Vecs32 {
 
 dim3 vgrid(int nrhs) { return dim3(kRedBlocks, nrhs); }
 
-int finalize(Ctx* c, int phase, int nslots, int nrhs, double tol2 = 0.0, double* out = nullptr,
-             const double* parts = nullptr, int nparts = kRedBlocks) {
-    hipLaunchKernelGGL(k_finalize, dim3(nrhs), dim3(kThreads), 0, c->stream, parts ? parts : c->partials, nparts,
-                       c->state, phase, nslots, tol2, out);
+int finalize(Ctx* c, const RhsSet& set, int phase, int nslots, double tol2 = 0.0, double* out = nullptr,
+             const double* parts = nullptr, int nparts = kRedBlocks, const double* tol2v = nullptr) {
+    hipLaunchKernelGGL(k_finalize, dim3(set.n), dim3(kThreads), 0, c->stream, parts ? parts : c->partials, nparts,
+                       c->state, phase, nslots, tol2, out, tol2v, slot_map(set));
     LS_HIP(hipGetLastError());
     return LS_OK;
+}
+
+// the systems of `all` whose state says they are still iterating (host copy of the state)
+RhsSet active_subset(const RhsSet& all, const double* host_state) {
+    RhsSet a;
+    for (int r = 0; r < all.n; ++r)
+        if (host_state[(size_t)all.slot[r] * kStateLen + S_ACTIVE] != 0.0) {
+            a.slot[a.n] = all.slot[r];
+            a.freq[a.n] = all.freq[r];
+            ++a.n;
+        }
+    return a;
+}
+
+bool same_set(const RhsSet& a, const RhsSet& b) {
+    if (a.n != b.n) return false;
+    for (int r = 0; r < a.n; ++r)
+        if (a.slot[r] != b.slot[r] || a.freq[r] != b.freq[r]) return false;
+    return true;
+}
+
+RhsSet one_slot(int q) {
+    RhsSet s;
+    s.n = 1;
+    s.slot[0] = q;
+    return s;
 }
 
 // The iterate with the smallest recursive residual seen, saved whenever that residual halves (so at most
@@ -421,14 +460,14 @@ struct BestIterate {
     z128* x = nullptr;           // [nrhs][3 ncell]
     std::vector<double> r2;      // residual norm^2 of the saved iterate, per system
     int save(Ctx* c, const z128* from, int q, long long m) {
-        hipLaunchKernelGGL(k_copy, dim3(kRedBlocks, 1), dim3(kThreads), 0, c->stream, from + (long long)q * m,
-                           x + (long long)q * m, m);
+        hipLaunchKernelGGL(k_copy, dim3(kRedBlocks, 1), dim3(kThreads), 0, c->stream, from, x, m,
+                           slot_map(one_slot(q)));
         LS_HIP(hipGetLastError());
         return LS_OK;
     }
     int restore(Ctx* c, z128* to, int q, long long m) {
-        hipLaunchKernelGGL(k_copy, dim3(kRedBlocks, 1), dim3(kThreads), 0, c->stream, (const z128*)x + (long long)q * m,
-                           to + (long long)q * m, m);
+        hipLaunchKernelGGL(k_copy, dim3(kRedBlocks, 1), dim3(kThreads), 0, c->stream, (const z128*)x, to, m,
+                           slot_map(one_slot(q)));
         LS_HIP(hipGetLastError());
         return LS_OK;
     }
@@ -439,86 +478,105 @@ struct BestIterate {
 // near), 300 above that, where hard systems (high frequency, many wavelengths) cross long plateaus.
 inline int stall_window(double r2, double b2) { return r2 < 1e-8 * b2 ? 30 : 300; }
 
-// Generic BiCGSTAB.  T: vector precision, X: iterate precision (x is cpx<X>), ApplyFn(in, out).
+// Generic BiCGSTAB over the systems of `all` (their slots in every vector).  T: vector precision, X: iterate
+// precision (x is cpx<X>), ApplyFn(set, in, out) applies the operator to the systems of a set.  tol2v:
+// device array of each slot's squared relative tolerance.  Every iteration covers only the systems still
+// iterating; the iteration over a given set is captured once into a graph and replayed until the set
+// shrinks.  iters: per slot.
 template <typename T, typename X, typename ApplyFn>
-int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, cpx<T>* rhat, cpx<T>* p, cpx<T>* v,
-             cpx<T>* s, cpx<T>* t, int nrhs, double tol, int maxit, ApplyFn apply, std::vector<int>& iters,
-             const double* hscale = nullptr, BestIterate* keep = nullptr, bool fuse = false) {
+int bicgstab(Ctx* c, const RhsSet& all, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, cpx<T>* rhat,
+             cpx<T>* p, cpx<T>* v, cpx<T>* s, cpx<T>* t, const double* tol2v, int maxit, ApplyFn apply,
+             std::vector<int>& iters, const double* hscale = nullptr, BestIterate* keep = nullptr, bool fuse = false) {
     const long long m = (long long)c->field_elems();
-    const dim3 g = vgrid(nrhs);
+    int ns = 0;   // slots spanned by the set (state entries read back)
+    for (int q = 0; q < all.n; ++q) ns = std::max(ns, all.slot[q] + 1);
     // r^H v and (t^H s, t^H t) come from the x-inverse epilogue of the operator call that writes v and t,
     // when it can compute them (forward operator, register four-step x pass)
     const int fblocks = fuse ? fused_dot_blocks<T>(c) : 0;
     const long long flines = 3LL * c->n3 * c->n2;
-    hipLaunchKernelGGL((k_init<T>), g, dim3(kThreads), 0, c->stream, b, ax0, r, rhat, p, v, m, c->partials);
+    hipLaunchKernelGGL((k_init<T>), dim3(kRedBlocks, all.n), dim3(kThreads), 0, c->stream, b, ax0, r, rhat, p, v, m,
+                       c->partials, slot_map(all));
     LS_HIP(hipGetLastError());
-    int rc = finalize(c, PH_INIT, 2, nrhs, tol * tol);
+    int rc = finalize(c, all, PH_INIT, 2, 0.0, nullptr, nullptr, kRedBlocks, tol2v);
     if (rc) return rc;
+    auto read_state = [&]() -> int {
+        LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * ns * kStateLen, hipMemcpyDeviceToHost,
+                              c->stream));
+        LS_HIP(hipStreamSynchronize(c->stream));
+        return LS_OK;
+    };
+    if ((rc = read_state())) return rc;
     if constexpr (sizeof(X) == 8) {
         if (keep && keep->r2.empty()) {
-            LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * nrhs * kStateLen, hipMemcpyDeviceToHost,
-                                  c->stream));
-            LS_HIP(hipStreamSynchronize(c->stream));
-            keep->r2.resize(nrhs);
-            for (int q = 0; q < nrhs; ++q) keep->r2[q] = c->red_host[q * kStateLen + S_RNORM2];
-            hipLaunchKernelGGL(k_copy, g, dim3(kThreads), 0, c->stream, (const z128*)x, keep->x, m);
+            keep->r2.assign(ns, std::numeric_limits<double>::infinity());
+            for (int q = 0; q < all.n; ++q) keep->r2[all.slot[q]] = c->red_host[all.slot[q] * kStateLen + S_RNORM2];
+            hipLaunchKernelGGL(k_copy, dim3(kRedBlocks, all.n), dim3(kThreads), 0, c->stream, (const z128*)x, keep->x,
+                               m, slot_map(all));
             LS_HIP(hipGetLastError());
         }
     }
-    // One iteration is a fixed sequence of launches whose scalars live on the device, so it is
-    // captured once into a graph and replayed; the host only reads the active flags in between.
-    auto body = [&]() -> int {
+    // One iteration over the systems of `cur` is a fixed sequence of launches whose scalars live on the
+    // device, so it is captured once into a graph and replayed; the host only reads the active flags in
+    // between.
+    auto body = [&](const RhsSet& cur) -> int {
         int brc;
-        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
-        hipLaunchKernelGGL((k_update_p<T>), g, dim3(kThreads), 0, c->stream, r, p, v, m, c->state);
+        const dim3 g(kRedBlocks, cur.n);
+        const SlotMap sm = slot_map(cur);
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"), cur.n);
+        hipLaunchKernelGGL((k_update_p<T>), g, dim3(kThreads), 0, c->stream, r, p, v, m, c->state, sm);
         c->prof.end(c->stream);
         if (fblocks) c->dot = {1, rhat, c->dparts, flines, fblocks};
-        brc = apply(p, v);
+        brc = apply(cur, p, v);
         c->dot = {};
         if (brc) return brc;
         if (fblocks) {
-            if ((brc = finalize(c, PH_ALPHA, 2, nrhs, 0.0, nullptr, c->dparts, fblocks))) return brc;
+            if ((brc = finalize(c, cur, PH_ALPHA, 2, 0.0, nullptr, c->dparts, fblocks))) return brc;
         } else {
-            c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
-            hipLaunchKernelGGL((k_dot<T>), g, dim3(kThreads), 0, c->stream, rhat, v, m, c->state, c->partials);
+            c->prof.begin(c->stream, LS_PNAME(T, "blas1"), cur.n);
+            hipLaunchKernelGGL((k_dot<T>), g, dim3(kThreads), 0, c->stream, rhat, v, m, c->state, c->partials, sm);
             c->prof.end(c->stream);
-            if ((brc = finalize(c, PH_ALPHA, 2, nrhs))) return brc;
+            if ((brc = finalize(c, cur, PH_ALPHA, 2))) return brc;
         }
-        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
-        hipLaunchKernelGGL((k_update_s<T>), g, dim3(kThreads), 0, c->stream, r, v, s, m, c->state, c->partials);
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"), cur.n);
+        hipLaunchKernelGGL((k_update_s<T>), g, dim3(kThreads), 0, c->stream, r, v, s, m, c->state, c->partials, sm);
         c->prof.end(c->stream);
-        if ((brc = finalize(c, PH_S, 1, nrhs))) return brc;
-        hipLaunchKernelGGL((k_update_x_half<T, X>), g, dim3(kThreads), 0, c->stream, x, p, m, c->state);
-        hipLaunchKernelGGL(k_clear_half, dim3(1), dim3(64), 0, c->stream, c->state, nrhs);
+        if ((brc = finalize(c, cur, PH_S, 1))) return brc;
+        hipLaunchKernelGGL((k_update_x_half<T, X>), g, dim3(kThreads), 0, c->stream, x, p, m, c->state, sm);
+        hipLaunchKernelGGL(k_clear_half, dim3(1), dim3(kMaxRhs), 0, c->stream, c->state, cur.n, sm);
         if (fblocks) c->dot = {2, nullptr, c->dparts, flines, fblocks};
-        brc = apply(s, t);
+        brc = apply(cur, s, t);
         c->dot = {};
         if (brc) return brc;
         if (fblocks) {
-            if ((brc = finalize(c, PH_OMEGA, 3, nrhs, 0.0, nullptr, c->dparts, fblocks))) return brc;
+            if ((brc = finalize(c, cur, PH_OMEGA, 3, 0.0, nullptr, c->dparts, fblocks))) return brc;
         } else {
-            c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
-            hipLaunchKernelGGL((k_dot_ts<T>), g, dim3(kThreads), 0, c->stream, t, s, m, c->state, c->partials);
+            c->prof.begin(c->stream, LS_PNAME(T, "blas1"), cur.n);
+            hipLaunchKernelGGL((k_dot_ts<T>), g, dim3(kThreads), 0, c->stream, t, s, m, c->state, c->partials, sm);
             c->prof.end(c->stream);
-            if ((brc = finalize(c, PH_OMEGA, 3, nrhs))) return brc;
+            if ((brc = finalize(c, cur, PH_OMEGA, 3))) return brc;
         }
-        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"), cur.n);
         hipLaunchKernelGGL((k_update_xr<T, X>), g, dim3(kThreads), 0, c->stream, x, p, s, t, r, rhat, m, c->state,
-                           c->partials);
+                           c->partials, sm);
         c->prof.end(c->stream);
-        if ((brc = finalize(c, PH_RHO, 4, nrhs))) return brc;
+        if ((brc = finalize(c, cur, PH_RHO, 4))) return brc;
         LS_HIP(hipGetLastError());
         return LS_OK;
     };
     struct GraphGuard {
         hipGraphExec_t exec = nullptr;
-        ~GraphGuard() {
+        RhsSet set;   // the systems the captured iteration covers
+        void reset() {
             if (exec) (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
         }
+        ~GraphGuard() { reset(); }
     } guard;
-    if (!(c->flags & LS_FLAG_NO_GRAPH) && !c->prof.on && c->stream != nullptr) {
+    const bool graphs = !(c->flags & LS_FLAG_NO_GRAPH) && !c->prof.on && c->stream != nullptr;
+    auto capture = [&](const RhsSet& cur) -> int {
+        guard.reset();
         LS_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        const int brc = body();
+        const int brc = body(cur);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(c->stream, &graph);
         if (brc) {
@@ -532,25 +590,28 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
             guard.exec = nullptr;
             return hip_fail(e2, "BiCGSTAB iteration graph instantiation");
         }
-    }
+        guard.set = cur;
+        return LS_OK;
+    };
     // FP32 inner solves stop a right-hand side whose residual has not improved on its best by 10 % for
     // a stall window of iterations (see stall_window; the FP64 refinement restarts from the true
     // residual).  FP64 solves run to tol or maxit.
-    std::vector<double> best(nrhs, std::numeric_limits<double>::infinity());
-    std::vector<int> since(nrhs, 0), last_it(nrhs, 0);
+    std::vector<double> best(ns, std::numeric_limits<double>::infinity());
+    std::vector<int> since(ns, 0), last_it(ns, 0);
     static const double zero = 0.0;
-    for (int it = 0; it < maxit; ++it) {
-        if (guard.exec) {
+    RhsSet cur = active_subset(all, c->red_host);
+    for (int it = 0; it < maxit && cur.n > 0; ++it) {
+        if (graphs) {
+            if (!guard.exec || !same_set(cur, guard.set))
+                if ((rc = capture(cur))) return rc;
             LS_HIP(hipGraphLaunch(guard.exec, c->stream));
-        } else if ((rc = body())) {
+        } else if ((rc = body(cur))) {
             return rc;
         }
-        LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * nrhs * kStateLen, hipMemcpyDeviceToHost,
-                              c->stream));
-        LS_HIP(hipStreamSynchronize(c->stream));
-        bool any = false;
-        for (int q = 0; q < nrhs; ++q) {
-            const double* sq = &c->red_host[q * kStateLen];
+        if ((rc = read_state())) return rc;
+        for (int r = 0; r < cur.n; ++r) {
+            const int q = cur.slot[r];
+            double* sq = &c->red_host[q * kStateLen];
             // relative residual of each completed iteration (scaled to the caller's system)
             if ((int)sq[S_ITERS] > last_it[q] && sq[S_BNORM2] > 0.0 && (size_t)q < c->history.size()) {
                 last_it[q] = (int)sq[S_ITERS];
@@ -570,17 +631,15 @@ int bicgstab(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, c
                 } else if (++since[q] >= stall_window(sq[S_RNORM2], sq[S_BNORM2])) {
                     LS_HIP(hipMemcpyAsync(c->state + q * kStateLen + S_ACTIVE, &zero, sizeof(double),
                                           hipMemcpyHostToDevice, c->stream));
-                    continue;
+                    sq[S_ACTIVE] = 0.0;
                 }
             }
-            any = true;
         }
-        if (!any) break;
+        cur = active_subset(cur, c->red_host);
     }
-    LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * nrhs * kStateLen, hipMemcpyDeviceToHost, c->stream));
-    LS_HIP(hipStreamSynchronize(c->stream));
-    iters.resize(nrhs);
-    for (int q = 0; q < nrhs; ++q) iters[q] = (int)c->red_host[q * kStateLen + S_ITERS];
+    if ((rc = read_state())) return rc;
+    iters.assign(ns, 0);
+    for (int q = 0; q < all.n; ++q) iters[all.slot[q]] = (int)c->red_host[all.slot[q] * kStateLen + S_ITERS];
     return LS_OK;
 }
 
@@ -831,11 +890,12 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
     std::vector<double> hc((size_t)nrhs * kCoef, 0.0);
     std::vector<int> stale(nrhs, 0);
     st.assign(nrhs, LState());
-    // r_0 = b - A x0, rhat = r_0, u_0 = 0
+    // r_0 = b - A x0, rhat = r_0, u_0 = 0 (systems 0..nrhs-1 on slots 0..nrhs-1)
+    const RhsSet ids = RhsSet::uniform(nrhs, 0);
     hipLaunchKernelGGL((k_init<T>), g, dim3(kThreads), 0, c->stream, b, ax0, R.v[0], rhat, U.v[0], U.v[1], m,
-                       c->partials);
+                       c->partials, slot_map(ids));
     LS_HIP(hipGetLastError());
-    int rc = finalize(c, PH_INIT, 2, nrhs, tol * tol);
+    int rc = finalize(c, ids, PH_INIT, 2, tol * tol);
     if (rc) return rc;
     LS_HIP(hipMemcpyAsync(c->red_host, c->state, sizeof(double) * nrhs * kStateLen, hipMemcpyDeviceToHost, c->stream));
     LS_HIP(hipStreamSynchronize(c->stream));
@@ -844,7 +904,7 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
         if (best) {
             best->r2.resize(nrhs);
             for (int q = 0; q < nrhs; ++q) best->r2[q] = c->red_host[q * kStateLen + S_RNORM2];
-            hipLaunchKernelGGL(k_copy, g, dim3(kThreads), 0, c->stream, (const z128*)x, best->x, m);
+            hipLaunchKernelGGL(k_copy, g, dim3(kThreads), 0, c->stream, (const z128*)x, best->x, m, slot_map(ids));
             LS_HIP(hipGetLastError());
         }
     }
@@ -946,7 +1006,7 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
             if (!any_active()) break;
             // u_i = r_i - beta u_i;  u_{j+1} = A u_j
             if ((rc = push())) return rc;
-            c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+            c->prof.begin(c->stream, LS_PNAME(T, "blas1"), nrhs);
             hipLaunchKernelGGL((k_bicg_u<T>), g, dim3(kThreads), 0, c->stream, R, U, j, m, coef);
             c->prof.end(c->stream);
             LS_HIP(hipGetLastError());
@@ -972,7 +1032,7 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
             if (!any_active()) break;
             // r_i -= alpha u_{i+1};  x += alpha u_0;  ||r_0||^2
             if ((rc = push())) return rc;
-            c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+            c->prof.begin(c->stream, LS_PNAME(T, "blas1"), nrhs);
             hipLaunchKernelGGL((k_bicg_r<T, X>), g, dim3(kThreads), 0, c->stream, R, U, j, x, m, coef, c->gpart);
             c->prof.end(c->stream);
             LS_HIP(hipGetLastError());
@@ -994,7 +1054,7 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
         // minimal-residual part: the Gram matrix of r_0 .. r_l, the normal equations on the host
         const int nq = (l + 1) * (l + 2);
         if ((rc = push())) return rc;
-        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"), nrhs);
         switch (l) {
             case 2: hipLaunchKernelGGL((k_gram<T, 2>), g, dim3(kThreads), 0, c->stream, R, m, coef, c->gpart); break;
             case 3: hipLaunchKernelGGL((k_gram<T, 3>), g, dim3(kThreads), 0, c->stream, R, m, coef, c->gpart); break;
@@ -1019,7 +1079,7 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
         }
         if (!any_active()) break;
         if ((rc = push())) return rc;
-        c->prof.begin(c->stream, LS_PNAME(T, "blas1"));
+        c->prof.begin(c->stream, LS_PNAME(T, "blas1"), nrhs);
         switch (l) {
             case 2: hipLaunchKernelGGL((k_mr<T, X, 2>), g, dim3(kThreads), 0, c->stream, R, U, x, m, coef); break;
             case 3: hipLaunchKernelGGL((k_mr<T, X, 3>), g, dim3(kThreads), 0, c->stream, R, U, x, m, coef); break;
@@ -1054,25 +1114,41 @@ int bicgstab_l(Ctx* c, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* co
     return save_rc;
 }
 
-// ||b - A x|| / ||b|| per system with the FP64 operator; writes r = b - A x if r != null.
-// the operator or its transpose
+// the operator or its transpose over the systems of a set, in launches of at most c->launch_rhs systems
+// (0: one launch for the whole set)
 template <typename T>
-int op_apply(Ctx* c, int i_omega, const cpx<T>* in, cpx<T>* out, int nrhs, bool transposed) {
-    return transposed ? apply_T_op<T>(c, i_omega, in, out, nrhs) : apply_op<T>(c, i_omega, in, out, nrhs);
+int op_apply(Ctx* c, const RhsSet& set, const cpx<T>* in, cpx<T>* out, bool transposed) {
+    const int w = c->launch_rhs > 0 ? c->launch_rhs : set.n;
+    for (int r0 = 0; r0 < set.n; r0 += w) {
+        RhsSet sub;
+        sub.n = std::min(w, set.n - r0);
+        for (int r = 0; r < sub.n; ++r) sub.slot[r] = set.slot[r0 + r], sub.freq[r] = set.freq[r0 + r];
+        const int rc = transposed ? apply_T_op<T>(c, sub, in, out) : apply_op<T>(c, sub, in, out);
+        if (rc) return rc;
+    }
+    return LS_OK;
 }
 
-int true_residual(Ctx* c, int i_omega, const z128* b, const z128* x, z128* ax, z128* r, int nrhs,
-                  std::vector<double>& rel, std::vector<double>& abs_, bool transposed) {
-    int rc = op_apply<double>(c, i_omega, x, ax, nrhs, transposed);
+// ||b - A x|| / ||b|| (rel) and ||b - A x|| (abs_) of the systems of a set with the FP64 operator, into the
+// entries of their slots; writes r = b - A x if r != null.
+int true_residual(Ctx* c, const RhsSet& set, const z128* b, const z128* x, z128* ax, z128* r, std::vector<double>& rel,
+                  std::vector<double>& abs_, bool transposed) {
+    int rc = op_apply<double>(c, set, x, ax, transposed);
     if (rc) return rc;
     const long long m = (long long)c->field_elems();
-    hipLaunchKernelGGL(k_residual, vgrid(nrhs), dim3(kThreads), 0, c->stream, b, ax, r, m, c->partials);
+    hipLaunchKernelGGL(k_residual, dim3(kRedBlocks, set.n), dim3(kThreads), 0, c->stream, b, ax, r, m, c->partials,
+                       slot_map(set));
     LS_HIP(hipGetLastError());
-    if ((rc = finalize(c, PH_RESID, 2, nrhs, 0.0, c->red))) return rc;
+    if ((rc = finalize(c, set, PH_RESID, 2, 0.0, c->red))) return rc;
     LS_HIP(hipMemcpyAsync(c->red_host, c->red, sizeof(double) * 2 * kRedBlocks, hipMemcpyDeviceToHost, c->stream));
     LS_HIP(hipStreamSynchronize(c->stream));
-    rel.assign(c->red_host, c->red_host + nrhs);
-    abs_.assign(c->red_host + kRedBlocks, c->red_host + kRedBlocks + nrhs);
+    for (int i = 0; i < set.n; ++i) {
+        const int q = set.slot[i];
+        if ((size_t)q >= rel.size()) rel.resize(q + 1, 0.0);
+        if ((size_t)q >= abs_.size()) abs_.resize(q + 1, 0.0);
+        rel[q] = c->red_host[q];
+        abs_[q] = c->red_host[kRedBlocks + q];
+    }
     return LS_OK;
 }
 
@@ -1112,24 +1188,37 @@ int krylov_setup(Ctx* c) {
     return rc;
 }
 
-int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int maxit, int precision, const z128* x0,
+int solve_systems(Ctx* c, const int* freq, const z128* b, int nrhs, double tol, int maxit, int precision, const z128* x0,
                   z128* u_out, ls_info* info, bool transposed) {
     const long long m = (long long)c->field_elems();
+    RhsSet all;   // system q on slot q at frequency freq[q]
+    all.n = nrhs;
+    for (int q = 0; q < nrhs; ++q) all.slot[q] = q, all.freq[q] = freq[q];
+    const dim3 gall(kRedBlocks, nrhs);
     std::vector<ls_info> inf(nrhs);
     for (auto& q : inf) q = ls_info{0, 0, 0, LS_OK, 0.0, 0.0};
     c->history.assign(nrhs, std::vector<double>());
     // x = x0 or 0
     if (x0) {
-        hipLaunchKernelGGL(k_copy, vgrid(nrhs), dim3(kThreads), 0, c->stream, x0, u_out, m);
-        LS_HIP(hipGetLastError());
+        if (x0 != u_out) {
+            hipLaunchKernelGGL(k_copy, gall, dim3(kThreads), 0, c->stream, x0, u_out, m, slot_map(all));
+            LS_HIP(hipGetLastError());
+        }
     } else {
         LS_HIP(hipMemsetAsync(u_out, 0, sizeof(z128) * m * nrhs, c->stream));
     }
-    std::vector<double> rel, nrm;
+    // each slot's squared relative tolerance for the Bi-CGSTAB initialisation
+    double* tol2v = c->red + 4 * kRedBlocks;
+    std::vector<double> t2(nrhs, tol * tol);
+    auto push_tol2 = [&]() -> int {
+        LS_HIP(hipMemcpyAsync(tol2v, t2.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
+        return LS_OK;
+    };
+    std::vector<double> rel(nrhs, 0.0), nrm(nrhs, 0.0);
     std::vector<int> iters;
     int rc = LS_OK;
     if (precision == LS_PREC_C128 && c->bicgstab_l > 1) {
-        auto apply = [&](const z128* in, z128* out) { return op_apply<double>(c, i_omega, in, out, nrhs, transposed); };
+        auto apply = [&](const z128* in, z128* out) { return op_apply<double>(c, all, in, out, transposed); };
         const std::vector<z128*> vec = krylov_vectors<double>(c);
         const z128* ax0 = nullptr;
         if (x0) {
@@ -1146,7 +1235,7 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 if ((rc = best.restore(c, u_out, q, m))) return rc;
                 ls[q].rnorm2 = best.r2[q];
             }
-        if ((rc = true_residual(c, i_omega, b, u_out, c->v, nullptr, nrhs, rel, nrm, transposed))) return rc;
+        if ((rc = true_residual(c, all, b, u_out, c->v, nullptr, rel, nrm, transposed))) return rc;
         for (int q = 0; q < nrhs; ++q) {
             inf[q].iters = ls[q].iters;
             inf[q].matvecs = ls[q].matvecs + (x0 ? 1 : 0) + 1;
@@ -1160,32 +1249,38 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 inf[q].status = LS_ERR_NOT_CONVERGED;
         }
     } else if (precision == LS_PREC_C128) {
-        auto apply = [&](const z128* in, z128* out) { return op_apply<double>(c, i_omega, in, out, nrhs, transposed); };
+        auto apply = [&](const RhsSet& set, const z128* in, z128* out) {
+            return op_apply<double>(c, set, in, out, transposed);
+        };
+        if ((rc = push_tol2())) return rc;
         // A breakdown (rho = 0 or rhat^H v = 0) restarts once from the current iterate, which re-seeds the
-        // shadow residual with the current residual; systems already within tol take no further iteration.
-        std::vector<double> st;
+        // shadow residual with the current residual; only the systems that broke down take the restart.
+        std::vector<double> st((size_t)nrhs * kStateLen, 0.0);
         std::vector<int> total(nrhs, 0), extra(nrhs, 0);
         BestIterate best{c->xbest, {}};
-        for (int attempt = 0; attempt < 2; ++attempt) {
+        RhsSet todo = all;
+        for (int attempt = 0; attempt < 2 && todo.n > 0; ++attempt) {
             const z128* ax0 = nullptr;
             if (x0 || attempt > 0) {
-                if ((rc = op_apply<double>(c, i_omega, u_out, c->t, nrhs, transposed))) return rc;
+                if ((rc = op_apply<double>(c, todo, u_out, c->t, transposed))) return rc;
                 ax0 = c->t;
-                for (int q = 0; q < nrhs; ++q) extra[q] += 1;
+                for (int i = 0; i < todo.n; ++i) extra[todo.slot[i]] += 1;
             }
-            rc = bicgstab<double, double>(c, b, u_out, ax0, c->r, c->rhat, c->p, c->v, c->s, c->t, nrhs, tol, maxit,
+            rc = bicgstab<double, double>(c, todo, b, u_out, ax0, c->r, c->rhat, c->p, c->v, c->s, c->t, tol2v, maxit,
                                           apply, iters, nullptr, &best, !transposed);
             if (rc) return rc;
-            st.assign(c->red_host, c->red_host + (size_t)nrhs * kStateLen);
-            bool broke = false;
-            for (int q = 0; q < nrhs; ++q) {
+            RhsSet broken;
+            for (int i = 0; i < todo.n; ++i) {
+                const int q = todo.slot[i];
+                std::copy(c->red_host + (size_t)q * kStateLen, c->red_host + (size_t)(q + 1) * kStateLen,
+                          st.begin() + (size_t)q * kStateLen);
                 const double* sq = &st[(size_t)q * kStateLen];
                 const bool half = sq[S_DONE] == 1.0 && sq[S_SNORM2] == sq[S_RNORM2];
                 total[q] += iters[q];
                 extra[q] += 2 * iters[q] - (half ? 1 : 0);
-                broke = broke || sq[S_FLAG] == 2.0;
+                if (sq[S_FLAG] == 2.0) broken.slot[broken.n] = q, broken.freq[broken.n++] = freq[q];
             }
-            if (!broke) break;
+            todo = broken;
         }
         // a system that stopped short of tol returns its best iterate
         for (int q = 0; q < nrhs; ++q) {
@@ -1195,7 +1290,7 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 sq[S_RNORM2] = best.r2[q];
             }
         }
-        if ((rc = true_residual(c, i_omega, b, u_out, c->v, nullptr, nrhs, rel, nrm, transposed))) return rc;
+        if ((rc = true_residual(c, all, b, u_out, c->v, nullptr, rel, nrm, transposed))) return rc;
         for (int q = 0; q < nrhs; ++q) {
             const double* sq = &st[(size_t)q * kStateLen];
             inf[q].iters = total[q];
@@ -1214,33 +1309,45 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
         // outer FP64 refinement: r = b - A x (FP64), inner FP32 BiCGSTAB on A d = r / ||r||.  A correction
         // that does not lower the FP64 true residual is taken back and ends that system's refinement (the
         // iterate stays the best one found); one that lowers it by less than 10 % is kept and ends it too.
+        // Every decision is per system, so a system's result does not depend on the others in the batch.
         const int max_outer = 30;
         std::vector<double> scale(nrhs), inv(nrhs), prev(nrhs, 0.0), undo(nrhs, 0.0);
         std::vector<int> active(nrhs, 1), stopped(nrhs, 0);
         int outer = 0;
         double* dscale = c->red + 2 * kRedBlocks;
+        auto subset = [&](const std::vector<int>& pick) {
+            RhsSet s_;
+            for (int q = 0; q < nrhs; ++q)
+                if (pick[q]) s_.slot[s_.n] = q, s_.freq[s_.n++] = freq[q];
+            return s_;
+        };
         for (; outer <= max_outer; ++outer) {
             if (outer == 0 && !x0) {
                 // x = 0, so A x = 0 and r = b
                 LS_HIP(hipMemsetAsync(c->v, 0, sizeof(z128) * m * nrhs, c->stream));
-                hipLaunchKernelGGL(k_residual, vgrid(nrhs), dim3(kThreads), 0, c->stream, b, c->v, c->r, m,
-                                   c->partials);
+                hipLaunchKernelGGL(k_residual, gall, dim3(kThreads), 0, c->stream, b, c->v, c->r, m, c->partials,
+                                   slot_map(all));
                 LS_HIP(hipGetLastError());
-                if ((rc = finalize(c, PH_RESID, 2, nrhs, 0.0, c->red))) return rc;
+                if ((rc = finalize(c, all, PH_RESID, 2, 0.0, c->red))) return rc;
                 LS_HIP(hipMemcpyAsync(c->red_host, c->red, sizeof(double) * 2 * kRedBlocks, hipMemcpyDeviceToHost,
                                       c->stream));
                 LS_HIP(hipStreamSynchronize(c->stream));
                 rel.assign(c->red_host, c->red_host + nrhs);
                 nrm.assign(c->red_host + kRedBlocks, c->red_host + kRedBlocks + nrhs);
             } else {
-                if ((rc = true_residual(c, i_omega, b, u_out, c->v, c->r, nrhs, rel, nrm, transposed))) return rc;
+                // the true residual of every system still refining (all of them at the first step)
+                const RhsSet rs = outer == 0 ? all : subset(active);
+                if ((rc = true_residual(c, rs, b, u_out, c->v, c->r, rel, nrm, transposed))) return rc;
+                std::vector<int> to_undo(nrhs, 0);
                 bool any_undo = false;
-                for (int q = 0; q < nrhs; ++q) {
+                for (int i = 0; i < rs.n; ++i) {
+                    const int q = rs.slot[i];
                     inf[q].matvecs += 1;
                     undo[q] = 0.0;
-                    if (outer == 0 || !active[q] || !std::isfinite(rel[q])) continue;
+                    if (outer == 0 || !std::isfinite(rel[q])) continue;
                     if (!(rel[q] < prev[q])) {
                         undo[q] = -inv[q];
+                        to_undo[q] = 1;
                         any_undo = true;
                         rel[q] = prev[q];
                         stopped[q] = 1;
@@ -1250,38 +1357,49 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 }
                 if (any_undo) {
                     // x -= d for the systems whose last correction raised the true residual (x32 still holds d)
+                    const RhsSet us = subset(to_undo);
                     LS_HIP(hipMemcpyAsync(dscale, undo.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice,
                                           c->stream));
-                    hipLaunchKernelGGL(k_add32, vgrid(nrhs), dim3(kThreads), 0, c->stream, u_out, c->x32, m, dscale);
+                    hipLaunchKernelGGL(k_add32, dim3(kRedBlocks, us.n), dim3(kThreads), 0, c->stream, u_out, c->x32,
+                                       m, dscale, slot_map(us));
                     LS_HIP(hipGetLastError());
                     LS_HIP(hipStreamSynchronize(c->stream));
                 }
             }
             bool any = false;
-            double worst = 0.0;
             for (int q = 0; q < nrhs; ++q) {
                 prev[q] = rel[q];
-                active[q] = !stopped[q] && rel[q] > tol && std::isfinite(rel[q]) && nrm[q] > 0.0;
+                active[q] = active[q] && !stopped[q] && rel[q] > tol && std::isfinite(rel[q]) && nrm[q] > 0.0;
                 any = any || active[q];
-                if (active[q]) worst = std::max(worst, rel[q]);
             }
             if (!any || outer == max_outer) break;
-            // inner tolerance: the reduction that reaches 0.3 tol, capped at 0.1 and floored at 1e-7 (near
-            // the FP32 operator's relative accuracy; a stagnating inner solve is stopped early anyway)
-            const double eta = std::min(1e-1, std::max(1e-7, 0.3 * tol / worst));
+            // inner tolerance per system: the reduction that reaches 0.3 tol, capped at 0.1 and floored at 1e-7
+            // (near the FP32 operator's relative accuracy; a stagnating inner solve is stopped early anyway)
             for (int q = 0; q < nrhs; ++q) {
+                const double eta = active[q] ? std::min(1e-1, std::max(1e-7, 0.3 * tol / rel[q])) : 1e-1;
+                t2[q] = eta * eta;
                 scale[q] = active[q] ? 1.0 / nrm[q] : 0.0;
                 inv[q] = active[q] ? nrm[q] : 0.0;
             }
+            const RhsSet inner = subset(active);
+            if ((rc = push_tol2())) return rc;
             LS_HIP(hipMemcpyAsync(dscale, scale.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-            hipLaunchKernelGGL(k_to32, vgrid(nrhs), dim3(kThreads), 0, c->stream, c->r, c->b32, m, dscale, c->x32);
+            hipLaunchKernelGGL(k_to32, dim3(kRedBlocks, inner.n), dim3(kThreads), 0, c->stream, c->r, c->b32, m, dscale,
+                               c->x32, slot_map(inner));
             LS_HIP(hipGetLastError());
-            auto apply32 = [&](const z64* in, z64* out) {
-                return op_apply<float>(c, i_omega, in, out, nrhs, transposed);
-            };
             if (c->bicgstab_l > 1) {
+                // BiCGSTAB(l) runs over slots 0..n-1 with host-side activity flags; inactive systems' FP32
+                // right-hand sides are zero (scale 0), so they finish at once
+                hipLaunchKernelGGL(k_to32, gall, dim3(kThreads), 0, c->stream, c->r, c->b32, m, dscale, c->x32,
+                                   slot_map(all));
+                LS_HIP(hipGetLastError());
+                auto apply32 = [&](const z64* in, z64* out) { return op_apply<float>(c, all, in, out, transposed); };
                 const std::vector<z64*> vec = krylov_vectors<float>(c);
                 std::vector<LState> ls;
+                double worst = 0.0;
+                for (int q = 0; q < nrhs; ++q)
+                    if (active[q]) worst = std::max(worst, rel[q]);
+                const double eta = std::min(1e-1, std::max(1e-7, 0.3 * tol / worst));
                 rc = bicgstab_l<float, float>(c, c->b32, c->x32, nullptr, vec.data(), c->bicgstab_l, nrhs, eta, maxit,
                                               apply32, ls, rel.data());
                 if (rc) return rc;
@@ -1291,11 +1409,15 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                     inf[q].matvecs += ls[q].matvecs;
                 }
             } else {
-                rc = bicgstab<float, float>(c, c->b32, c->x32, nullptr, c->r32, c->rhat32, c->p32, c->v32, c->s32,
-                                            c->t32, nrhs, eta, maxit, apply32, iters, rel.data(), nullptr, !transposed);
+                auto apply32 = [&](const RhsSet& set, const z64* in, z64* out) {
+                    return op_apply<float>(c, set, in, out, transposed);
+                };
+                rc = bicgstab<float, float>(c, inner, c->b32, c->x32, nullptr, c->r32, c->rhat32, c->p32, c->v32,
+                                            c->s32, c->t32, tol2v, maxit, apply32, iters, rel.data(), nullptr,
+                                            !transposed);
                 if (rc) return rc;
-                for (int q = 0; q < nrhs; ++q) {
-                    if (!active[q]) continue;
+                for (int i = 0; i < inner.n; ++i) {
+                    const int q = inner.slot[i];
                     const double* sq = &c->red_host[(size_t)q * kStateLen];
                     const bool half = sq[S_DONE] == 1.0 && sq[S_SNORM2] == sq[S_RNORM2];
                     inf[q].iters += iters[q];
@@ -1303,7 +1425,8 @@ int solve_systems(Ctx* c, int i_omega, const z128* b, int nrhs, double tol, int 
                 }
             }
             LS_HIP(hipMemcpyAsync(dscale, inv.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, c->stream));
-            hipLaunchKernelGGL(k_add32, vgrid(nrhs), dim3(kThreads), 0, c->stream, u_out, c->x32, m, dscale);
+            hipLaunchKernelGGL(k_add32, dim3(kRedBlocks, inner.n), dim3(kThreads), 0, c->stream, u_out, c->x32, m,
+                               dscale, slot_map(inner));
             LS_HIP(hipGetLastError());
             LS_HIP(hipStreamSynchronize(c->stream));
             for (int q = 0; q < nrhs; ++q)

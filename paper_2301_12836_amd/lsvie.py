@@ -5,7 +5,7 @@ torch tensors to device pointers and checks shapes.  If the shared library has n
 loading fails loudly (there is no CPU fallback).
 
 The module-level functions carry the C names (``ls_setup``, ``ls_apply``, ``ls_apply_noalloc``, ``ls_apply_c64``,
-``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_moment``, ``ls_solve_force``,
+``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_multi``, ``ls_solve_moment``, ``ls_solve_force``,
 ``ls_solve_batch``, ``ls_strain``, ``ls_apply_T``, ``ls_convolve``, ``ls_solve_T``,
 ``ls_grad_contrast``, ``ls_grad``, ``ls_sample``, ``ls_synthesize``, ``ls_residual_history``, ``ls_profile``,
 ``ls_profile_read``, ``ls_device_bytes``, ``ls_kernel_variants``, ``ls_destroy``); ``Context`` wraps
@@ -42,7 +42,7 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
                LS_ERR_NONFINITE: "LS_ERR_NONFINITE", LS_ERR_STATE: "LS_ERR_STATE"}
 
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_noalloc", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
-            "ls_solve_moment", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve",
+            "ls_solve_moment", "ls_solve_multi", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve",
             "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch", "ls_sample", "ls_synthesize", "ls_residual_history",
             "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_last_error")
 
@@ -106,6 +106,7 @@ def load():
         "ls_rhs_moment": (I, [P, I, dp, ip, D, P]),
         "ls_rhs_force": (I, [P, I, dp, ip, P]),
         "ls_solve": (I, [P, I, P, I, D, I, I, P, P, ctypes.POINTER(Info)]),
+        "ls_solve_multi": (I, [P, ip, P, I, D, I, I, P, P, ctypes.POINTER(Info)]),
         "ls_solve_moment": (I, [P, I, dp, ip, D, D, I, I, P, P, ctypes.POINTER(Info)]),
         "ls_strain": (I, [P, P, P, I]),
         "ls_apply_T": (I, [P, I, P, P, I]),
@@ -119,7 +120,7 @@ def load():
         "ls_synthesize": (I, [P, P, ip, I, I, I, D, D, D, P]),
         "ls_solve_force": (I, [P, I, dp, ip, D, I, I, P, ctypes.POINTER(Info)]),
         "ls_profile": (I, [P, I]),
-        "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, I]),
+        "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, ctypes.POINTER(ctypes.c_longlong), I]),
         "ls_device_bytes": (ctypes.c_longlong, [P]),
         "ls_kernel_variants": (I, [P, ip]),
         "ls_last_error": (ctypes.c_char_p, []),
@@ -236,6 +237,17 @@ def ls_solve(ctx, i_omega, b, n_rhs, tol, maxit, precision, x0, u_out, raise_on_
     return code, [i.as_dict() for i in infos]
 
 
+def ls_solve_multi(ctx, i_omega, b, n_rhs, tol, maxit, precision, x0, u_out, raise_on_error=True):
+    """i_omega: one frequency index per system (sequence of n_rhs ints)."""
+    iw = np.ascontiguousarray(np.asarray(i_omega, dtype=np.int32).reshape(int(n_rhs)))
+    infos = (Info * int(n_rhs))()
+    code = load().ls_solve_multi(ctx, iw.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(b), int(n_rhs),
+                                 float(tol), int(maxit), int(precision), _ptr(x0), _ptr(u_out), infos)
+    if raise_on_error:
+        _check(code)
+    return code, [i.as_dict() for i in infos]
+
+
 def ls_solve_moment(ctx, i_omega, M, src, t0, tol, maxit, precision, x0, u_out, raise_on_error=True):
     m, mp = _dbl(M, 6)
     s, sp = _int3(src)
@@ -345,16 +357,19 @@ def ls_profile(ctx, enable):
 
 
 def ls_profile_read(ctx, n_max=64):
+    """{family: {"count", "ms", "rhs", "tables"}}: launches, summed event time, summed right-hand sides and
+    summed distinct Green's tables over the recorded launches of each kernel family."""
     names = ctypes.create_string_buffer(64 * n_max)
     counts = (ctypes.c_int * n_max)()
     ms = (ctypes.c_double * n_max)()
-    nf = load().ls_profile_read(ctx, names, counts, ms, n_max)
+    units = (ctypes.c_longlong * (2 * n_max))()
+    nf = load().ls_profile_read(ctx, names, counts, ms, units, n_max)
     if nf < 0:
         _check(nf)
     out = {}
     for k in range(min(nf, n_max)):
         name = names.raw[64 * k:64 * k + 64].split(b"\0", 1)[0].decode()
-        out[name] = {"count": counts[k], "ms": ms[k]}
+        out[name] = {"count": counts[k], "ms": ms[k], "rhs": units[2 * k], "tables": units[2 * k + 1]}
     return out
 
 
@@ -477,12 +492,17 @@ class Context:
         return out
 
     def solve(self, b, i_omega=0, tol=1e-8, maxit=2000, precision=None, x0=None, out=None, raise_on_error=True):
+        """Solve A u = b for the fields b; i_omega is one frequency index for all of them, or a sequence with
+        one per field (then every system runs at its own frequency in the same launches)."""
         b, nrhs = self._field(b, self.torch.complex128)
         if x0 is not None:
             x0, _ = self._field(x0, self.torch.complex128)
         out = self._out(out, b)
         prec = LS_PREC_MIXED if (precision or ("mixed" if self.mixed else "c128")) == "mixed" else LS_PREC_C128
-        code, infos = ls_solve(self.handle, i_omega, b, nrhs, tol, maxit, prec, x0, out, raise_on_error)
+        if np.ndim(i_omega) == 0:
+            code, infos = ls_solve(self.handle, i_omega, b, nrhs, tol, maxit, prec, x0, out, raise_on_error)
+        else:
+            code, infos = ls_solve_multi(self.handle, i_omega, b, nrhs, tol, maxit, prec, x0, out, raise_on_error)
         return out, infos
 
     def solve_moment(self, M, src, i_omega=0, t0=0.0, tol=1e-8, maxit=2000, precision=None, x0=None, out=None,
@@ -605,21 +625,24 @@ class Context:
         return ls_device_bytes(self.handle)
 
 
-def solve_batch(contexts, jobs, tol=1e-8, maxit=2000, precision="c128", raise_on_error=True):
+def solve_batch(contexts, jobs, tol=1e-8, maxit=2000, precision="c128", raise_on_error=True, outs=None):
     """Solve moment-tensor jobs over several contexts (grids may differ) in one library call.
 
     jobs: sequence of (context index, frequency index, M[6], (i, j, k), t0).  Returns (fields, infos):
-    one new complex128 [3, N3, N2, N1] tensor per job on its context's device, and the per-job info."""
-    outs, arr = [], []
-    for ci, iw, M, src, t0 in jobs:
+    one complex128 [3, N3, N2, N1] tensor per job on its context's device (new ones, or the caller's outs,
+    one per job, each checked), and the per-job info."""
+    if outs is not None and len(outs) != len(jobs):
+        raise ValueError("outs must hold one field per job")
+    new_outs, arr = [], []
+    for k, (ci, iw, M, src, t0) in enumerate(jobs):
         ctx = contexts[ci]
-        out = ctx.empty()
-        outs.append(out)
+        out = ctx.empty() if outs is None else ctx._check(outs[k], ctx.field_shape, ctx.torch.complex128)
+        new_outs.append(out)
         arr.append(Job(int(ci), int(iw), (ctypes.c_double * 6)(*np.asarray(M, dtype=np.float64).reshape(6)),
                        (ctypes.c_int * 3)(*[int(v) for v in src]), float(t0), out.data_ptr()))
     prec = LS_PREC_MIXED if precision == "mixed" else LS_PREC_C128
     code, infos = ls_solve_batch([c.handle for c in contexts], arr, tol, maxit, prec, raise_on_error)
-    return outs, infos
+    return new_outs, infos
 
 
 def context_from_model(model, precision="c128", max_rhs=1, green_mode="exact", device="cuda:0", omegas=None,
