@@ -109,7 +109,11 @@ typedef struct {
  *   LS_FLAG_NO_GRAPH  run every BiCGSTAB iteration as separate launches instead of replaying one
  *                     captured hipGraph per iteration (the default when the stream can be captured).
  *   LS_FLAG_AUTOTUNE  at set-up, time the available kernel variants of every FFT pass (register
- *                     four-step and LDS Stockham) at the context's sizes and keep the fastest. */
+ *                     four-step and LDS Stockham) at the context's sizes and keep the fastest.  The
+ *                     choice is cached, keyed by device, grid, FFT lengths, max_rhs, buffer layout,
+ *                     table kind and precision, in the text file that the environment variable
+ *                     LS_AUTOTUNE_CACHE names (default $HOME/.cache/lsvie/autotune.txt); a context
+ *                     whose key is cached takes the cached choice without timing. */
 enum { LS_FLAG_NO_GRAPH = 1, LS_FLAG_AUTOTUNE = 2 };
 
 typedef struct {

@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
+#include <sys/stat.h>
 #include <map>
 #include <mutex>
 #include <new>
@@ -241,6 +243,74 @@ int check_solve_buffers(const ls_ctx* c, const void* b, const void* x0, const vo
         if ((rc = check_disjoint(c, x0, u_out, n_rhs, sizeof(z128), "solve (x0, u_out)"))) return rc;
     }
     return LS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// autotuner cache: one line per tuned configuration, "key v0 .. v9" (the FFT variant of every pass and
+// precision), in the file LS_AUTOTUNE_CACHE names, else $HOME/.cache/lsvie/autotune.txt.  A missing or
+// unreadable cache only means tuning again; a later line for the same key wins.
+
+std::string autotune_path() {
+    if (const char* e = std::getenv("LS_AUTOTUNE_CACHE")) return e;
+    const char* home = std::getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/lsvie/autotune.txt";
+}
+
+// everything the timings depend on: device, grid, FFT lengths, batch width, layout, table kind, precision
+std::string autotune_key(const Ctx* c) {
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+    (void)hipGetLastError();
+    for (char& ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    return "v1:" + arch + ":cu" + std::to_string(c->num_cu) + ":n" + std::to_string(c->n1) + "x" + std::to_string(c->n2) +
+           "x" + std::to_string(c->n3) + ":L" + std::to_string(c->L1) + "x" + std::to_string(c->L2) + "x" +
+           std::to_string(c->L3) + ":r" + std::to_string(c->max_rhs) + ":z" + std::to_string(c->zbs) + ":h" +
+           std::to_string((int)c->green_half) + ":m" + std::to_string(c->mixed);
+}
+
+bool autotune_lookup(const std::string& key, Ctx* c) {
+    FILE* f = std::fopen(autotune_path().c_str(), "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    int v[10];
+    while (std::fgets(line, sizeof line, f)) {
+        char k[400];
+        int w[10];
+        if (std::sscanf(line, "%399s %d %d %d %d %d %d %d %d %d %d", k, &w[0], &w[1], &w[2], &w[3], &w[4], &w[5], &w[6],
+                        &w[7], &w[8], &w[9]) != 11 ||
+            key != k)
+            continue;
+        bool ok = true;
+        for (int q = 0; q < 10; ++q) ok = ok && (w[q] == 0 || w[q] == 1);
+        if (ok) {
+            std::copy(w, w + 10, v);
+            found = true;
+        }
+    }
+    std::fclose(f);
+    if (found)
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 5; ++q) c->variant[p][q] = v[5 * p + q];
+    return found;
+}
+
+void autotune_store(const std::string& key, const Ctx* c) {
+    const std::string path = autotune_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {   // create the directory chain (best effort)
+        for (size_t i = 1; i <= slash; ++i)
+            if (path[i] == '/' || i == slash) (void)mkdir(path.substr(0, i == slash ? slash : i).c_str(), 0755);
+    }
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s", key.c_str());
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 5; ++q) std::fprintf(f, " %d", c->variant[p][q]);
+    std::fprintf(f, "\n");
+    std::fclose(f);
 }
 
 bool is_isotropic(const double* C) {
@@ -532,11 +602,15 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     if (rc == LS_OK) rc = fold_background(c, dC, drho, fold21);
     if (rc == LS_OK) rc = build_green_tables(c);
     if (rc == LS_OK && (c->flags & LS_FLAG_AUTOTUNE)) {
-        if (hipMemsetAsync(c->work, 0, (size_t)c->max_rhs * 3 * c->n3 * c->L2 * c->L1 * sizeof(z128), c->stream) !=
-            hipSuccess)
-            rc = fail(LS_ERR_HIP, "autotune buffer clear failed");
-        if (rc == LS_OK) rc = autotune_passes<double>(c);
-        if (rc == LS_OK && c->mixed) rc = autotune_passes<float>(c);
+        const std::string key = autotune_key(c);
+        if (!autotune_lookup(key, c)) {
+            if (hipMemsetAsync(c->work, 0, (size_t)c->max_rhs * 3 * c->n3 * c->L2 * c->L1 * sizeof(z128), c->stream) !=
+                hipSuccess)
+                rc = fail(LS_ERR_HIP, "autotune buffer clear failed");
+            if (rc == LS_OK) rc = autotune_passes<double>(c);
+            if (rc == LS_OK && c->mixed) rc = autotune_passes<float>(c);
+            if (rc == LS_OK) autotune_store(key, c);
+        }
     }
     if (rc == LS_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = fail(LS_ERR_HIP, "setup synchronisation failed");
     if (rc) {

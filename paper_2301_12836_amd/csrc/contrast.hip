@@ -310,7 +310,7 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     // the mask bit I is set
     // tau on plane q at this thread's cell, from u planes q-1, q, q+1: rows I of dC eps for which the
     // mask bit I is set; the owned cell also returns its z components (Voigt 33, 23, 13) in zc
-    auto tau_cell = [&](int q, auto rows, cpx<T>* zc) __attribute__((always_inline)) {
+    auto tau_cell = [&](int q, auto rows, cpx<T>* zc, const T* C) __attribute__((always_inline)) {
         constexpr int mask = decltype(rows)::value;
         const cpx<T>* um = us + ((q - 1) & 3) * 3 * UP;
         const cpx<T>* u0 = us + (q & 3) * 3 * UP;
@@ -348,14 +348,14 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
             }
         }
     };
-    auto tau_plane = [&](int q, cpx<T>* zc) __attribute__((always_inline)) {
+    auto tau_plane = [&](int q, cpx<T>* zc, const T* C) __attribute__((always_inline)) {
         if (q < 0 || q >= N3 || !cell) return;  // never read with a nonzero weight
         if (role == 0)
-            tau_cell(q, std::integral_constant<int, 0x3f>{}, zc);
+            tau_cell(q, std::integral_constant<int, 0x3f>{}, zc, C);
         else if (role == 1)
-            tau_cell(q, std::integral_constant<int, (1 << 1) | (1 << 3) | (1 << 5)>{}, zc);
+            tau_cell(q, std::integral_constant<int, (1 << 1) | (1 << 3) | (1 << 5)>{}, zc, C);
         else
-            tau_cell(q, std::integral_constant<int, (1 << 0) | (1 << 4) | (1 << 5)>{}, zc);
+            tau_cell(q, std::integral_constant<int, (1 << 0) | (1 << 4) | (1 << 5)>{}, zc, C);
     };
 
     // prologue: zero tau planes; u planes z0-2 .. z0+2; tau planes z0-1 and z0 (the owned cell's z
@@ -368,9 +368,9 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     __syncthreads();
     cpx<T> tprev[3] = {}, tcur[3] = {}, tnext[3] = {};
     load_C(C, z0 - 1);
-    tau_plane(z0 - 1, tprev);
+    tau_plane(z0 - 1, tprev, C);
     load_C(C, z0);
-    tau_plane(z0, tcur);
+    tau_plane(z0, tcur, C);
     __syncthreads();  // tau(z0-1) has read u(z0-2), whose ring slot u(z0+2) takes
     load_plane(z0 + 2);
     store_plane(z0 + 2);
@@ -383,16 +383,19 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     // One barrier per step: step k computes tau(k+1) into one tau plane and f(k) from the other, and
     // stores u(k+3) into the ring slot of u(k-1), which nothing reads in this step.  The dC and drho of
     // the next step are requested at the top of the step and the next u plane right after the store,
-    // so each load has about a whole step to land.
-    for (int k = z0; k < zend; ++k) {
+    // so each load has about a whole step to land.  The loop is unrolled by two with the dC and drho of
+    // alternate steps in alternate registers (C, Cn and dro, dron): no loaded value is copied, so the first
+    // wait for a load comes in the step that uses it, not at the end of the step that issued it (the wait
+    // counter retires loads in order, so such a wait also waits for every load issued before it).
+    auto step = [&](int k, T* Cu, T* Cx, T& du, T& dx) __attribute__((always_inline)) {
         const bool more = k + 1 < zend;
         if (more) {
-            if constexpr (DB) load_C(Cn, k + 2);
-            dron = (drho + (long long)(k + 1) * plane)[cell_xy];
+            if constexpr (DB) load_C(Cx, k + 2);
+            dx = (drho + (long long)(k + 1) * plane)[cell_xy];
         }
-        tau_plane(k + 1, tnext);
+        tau_plane(k + 1, tnext, Cu);
         if constexpr (!DB) {
-            if (more) load_C(C, k + 2);
+            if (more) load_C(Cu, k + 2);
         }
         if (own) {
             const cpx<T>* s0 = ts + (k & 1) * 6 * SP + po;
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
             const cpx<T> f2 = tdx(4) + tdy(3) + w3(tz, tprev[0], tcur[0], tnext[0]);
             const long long p = (long long)k * plane + cell_xy;
             const cpx<T>* uk = us + (k & 3) * 3 * UP + (ly + 2) * UX + (lx + 2);
-            const T wr = w2 * dro;
+            const T wr = w2 * du;
             const cpx<T> g0 = wr * uk[0] - f0, g1 = wr * uk[UP] - f1, g2 = wr * uk[2 * UP] - f2;
             if constexpr (OUT == 0) {
                 const long long cpitch = (long long)N3 * L2 * L1;
@@ -437,14 +440,16 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
             tprev[c] = tcur[c];
             tcur[c] = tnext[c];
         }
-        dro = dron;
-        if constexpr (DB) {
-            if (more) {
-#pragma unroll
-                for (int qq = 0; qq < 21; ++qq) C[qq] = Cn[qq];
-            }
-        }
         __syncthreads();
+    };
+    for (int k = z0; k < zend; k += 2) {
+        if constexpr (DB) {
+            step(k, C, Cn, dro, dron);
+            if (k + 1 < zend) step(k + 1, Cn, C, dron, dro);
+        } else {
+            step(k, C, C, dro, dron);
+            if (k + 1 < zend) step(k + 1, C, C, dron, dro);
+        }
     }
 }
 

@@ -39,7 +39,8 @@ def test_graph_iterations_equal_eager_launches(precision):
     graph.close()
 
 
-def test_autotuned_variants_keep_parity():
+def test_autotuned_variants_keep_parity(tmp_path, monkeypatch):
+    monkeypatch.setenv("LS_AUTOTUNE_CACHE", str(tmp_path / "autotune.txt"))
     m = models.random_medium((24, 20, 18), seed=9, rel=0.1, aniso_background=True)
     ctx = lsvie.context_from_model(m, omegas=[W], precision="mixed", max_rhs=2, autotune=True)
     v = ctx.kernel_variants
@@ -93,3 +94,27 @@ def test_solve_batch_over_uneven_grids():
     assert e.value.code == lsvie.LS_ERR_ARG
     A.close()
     B.close()
+
+
+def test_autotune_cache_is_written_and_used(tmp_path, monkeypatch):
+    """The first tuned context writes its choice under its key; a context of the same configuration takes
+    the cached choice without timing, here an edited line selecting the LDS Stockham kernels everywhere,
+    and keeps parity with the oracle."""
+    cache = tmp_path / "autotune.txt"
+    monkeypatch.setenv("LS_AUTOTUNE_CACHE", str(cache))
+    m = models.random_medium((16, 12, 10), seed=19, rel=0.1, aniso_background=True)
+    ctx = lsvie.context_from_model(m, omegas=[W], precision="mixed", max_rhs=2, autotune=True)
+    ctx.close()
+    lines = cache.read_text().split("\n")
+    key, *vals = lines[0].split()
+    assert len(vals) == 10 and set(vals) <= {"0", "1"} and key.startswith("v1:")
+    cache.write_text(lines[0] + "\n" + key + " 1 1 1 1 1 1 1 1 1 1\n")
+    ctx = lsvie.context_from_model(m, omegas=[W], precision="mixed", max_rhs=2, autotune=True)
+    v = ctx.kernel_variants
+    assert all(x == "stockham" for p in v.values() for x in p.values()), v
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, W)
+    u = models.random_field(m.shape, 3)
+    assert rel(ctx.apply(torch.from_numpy(u)).cpu().numpy(), P.apply_fft(u)) < 1e-10
+    assert rel(ctx.apply(torch.from_numpy(u).to(torch.complex64)).cpu().numpy(), P.apply_fft(u)) < 1e-5
+    ctx.close()
+    assert len(cache.read_text().strip().split("\n")) == 2   # the cached key was not tuned again
