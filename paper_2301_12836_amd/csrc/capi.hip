@@ -104,7 +104,8 @@ static void release(Ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
                     c->xd, c->bd, c->gs, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
-                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes, c->gpart, c->xbest, c->dparts};
+                    c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes, c->gpart, c->xbest, c->dparts,
+                    c->gloc, c->ph, c->sh, c->ph32, c->sh32};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto q : c->ghat) (void)hipFree(q);
@@ -112,6 +113,8 @@ static void release(Ctx* c) {
     for (auto q : c->kry128) (void)hipFree(q);
     for (auto q : c->kry64) (void)hipFree(q);
     for (auto q : c->ghat32) (void)hipFree(q);
+    for (auto q : c->minv) (void)hipFree(q);
+    for (auto q : c->minv32) (void)hipFree(q);
     for (auto q : c->tw128) (void)hipFree(q);
     for (auto q : c->tw64) (void)hipFree(q);
     if (c->red_host) (void)hipHostFree(c->red_host);
@@ -411,7 +414,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
         for (int J = 0; J < I; ++J)
             if (std::fabs(C0[I * 6 + J] - C0[J * 6 + I]) > 1e-12 * cmax)
                 return fail(LS_ERR_ARG, "background stiffness must be symmetric");
-    ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, 0, 0, 1, {0, 0}};
+    ls_options o = {LS_PREC_C128, LS_GREEN_EXACT, 1, 0, 0, 1, LS_PRECOND_NONE, {0}};
     if (opt) o = *opt;
     if (o.bicgstab_l == 0) o.bicgstab_l = 1;
     if (o.bicgstab_l < 1 || o.bicgstab_l > 4) return fail(LS_ERR_ARG, "bicgstab_l must be in [1, 4] (0 means 1)");
@@ -430,6 +433,9 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
         if (e && std::strcmp(e, "half") == 0) half = true;
     }
     if (o.max_rhs < 1 || o.max_rhs > 64) return fail(LS_ERR_ARG, "max_rhs must be in [1, 64]");
+    if (o.precond != LS_PRECOND_NONE && o.precond != LS_PRECOND_BLOCK_JACOBI) return fail(LS_ERR_ARG, "bad precond");
+    if (o.precond != LS_PRECOND_NONE && o.bicgstab_l > 1)
+        return fail(LS_ERR_ARG, "the block-Jacobi preconditioner works with Bi-CGSTAB (bicgstab_l = 1)");
     if (o.taper < 0 || 2 * o.taper > std::min(grid->n[0], std::min(grid->n[1], grid->n[2])))
         return fail(LS_ERR_ARG, "taper must be in [0, min(N)/2]");
 
@@ -494,6 +500,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     c->flags = o.flags;
     c->taper = o.taper;
     c->bicgstab_l = o.bicgstab_l;
+    c->precond = o.precond;
     {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess) {
@@ -564,6 +571,21 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     // per-slot squared tolerances, kRedBlocks doubles each
     A((void**)&c->red, 5 * kRedBlocks * sizeof(double));
     A(&c->stage, 8192);
+    if (c->precond == LS_PRECOND_BLOCK_JACOBI) {
+        c->minv.assign(n_omega, nullptr);
+        c->minv32.assign(n_omega, nullptr);
+        for (int i = 0; i < n_omega; ++i) {
+            A((void**)&c->minv[i], 9 * n * sizeof(z128));
+            if (c->mixed) A((void**)&c->minv32[i], 9 * n * sizeof(z64));
+        }
+        A((void**)&c->gloc, 125 * 6 * sizeof(z128));
+        A((void**)&c->ph, fe * sizeof(z128));
+        A((void**)&c->sh, fe * sizeof(z128));
+        if (c->mixed) {
+            A((void**)&c->ph32, fe * sizeof(z64));
+            A((void**)&c->sh32, fe * sizeof(z64));
+        }
+    }
     if (rc == LS_OK && c->bicgstab_l > 1) rc = krylov_setup(c);
     if (rc == LS_OK) {
         const size_t hb = std::max<size_t>(4 * kRedBlocks, (size_t)c->max_rhs * kStateLen) * sizeof(double);
@@ -601,6 +623,7 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     std::copy(fold21, fold21 + 21, c->fold21);
     if (rc == LS_OK) rc = fold_background(c, dC, drho, fold21);
     if (rc == LS_OK) rc = build_green_tables(c);
+    if (rc == LS_OK) rc = build_block_jacobi(c);
     if (rc == LS_OK && (c->flags & LS_FLAG_AUTOTUNE)) {
         const std::string key = autotune_key(c);
         if (!autotune_lookup(key, c)) {
@@ -629,7 +652,18 @@ int ls_set_contrast(ls_ctx* c, const double* dC, const double* drho) {
     int rc;
     if ((rc = check_ctx(c))) return rc;
     if (!dC || !drho) return fail(LS_ERR_ARG, "null argument");
-    return fold_background(c, dC, drho, c->fold21);
+    if ((rc = fold_background(c, dC, drho, c->fold21))) return rc;
+    return build_block_jacobi(c);
+}
+
+int ls_precond_blocks(ls_ctx* c, int i_omega, void* minv) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = check_omega(c, i_omega))) return rc;
+    if (!minv) return fail(LS_ERR_ARG, "null argument");
+    if (c->precond != LS_PRECOND_BLOCK_JACOBI) return fail(LS_ERR_STATE, "the context has no block-Jacobi preconditioner");
+    LS_HIP(hipMemcpyAsync(minv, c->minv[i_omega], 9 * (size_t)c->ncell * sizeof(z128), hipMemcpyDeviceToDevice,
+                          c->stream));
+    return LS_OK;
 }
 
 int ls_apply(ls_ctx* c, int i_omega, const void* u, void* Au, int n_rhs) {

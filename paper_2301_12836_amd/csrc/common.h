@@ -90,6 +90,13 @@ struct RhsSet {
 struct SlotMap {
     int slot[kMaxRhs];
 };
+// per-position inverse diagonal blocks of the block-Jacobi preconditioner ([9][ncell] of the position's
+// frequency; trans: apply the transposed blocks, for the transposed operator)
+template <typename T>
+struct PreTabs {
+    const cpx<T>* m[kMaxRhs];
+    int trans;
+};
 template <typename T>
 struct SlotW2 {      // field slot and w^2 of each position (contrast kernels)
     int slot[kMaxRhs];
@@ -170,6 +177,7 @@ struct Ctx {
     int device = 0;    // the HIP device the context was set up on
     int taper = 0;     // absorbing-layer thickness in cells (0: off)
     int launch_rhs = 0;  // most systems one operator launch of a solve covers (0: all of them)
+    int precond = 0;     // LS_PRECOND_*: preconditioner of the Bi-CGSTAB solves
     // FFT kernel variant per pass and precision: 0 register four-step, 1 LDS Stockham
     // passes: 0 x forward, 1 y forward, 2 z with Green multiply, 3 y inverse, 4 x inverse
     int variant[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
@@ -188,6 +196,12 @@ struct Ctx {
                                   // (half-space: [2 N3 - 1][2 N2 - 1][N1][6])
     std::vector<z64*> ghat32;
     double* gl_nodes = nullptr;   // LS_GREEN_ANISO: Gauss-Legendre nodes and weights on [0, 1] (device)
+    // block-Jacobi preconditioner (LS_PRECOND_BLOCK_JACOBI): inverse diagonal 3x3 blocks per frequency,
+    // entry (a, b) of cell p at [(3 a + b) ncell + p], FP64 and (mixed) FP32; h^3 G at the offsets [-2, 2]^3
+    // while they are built ([125][6])
+    std::vector<z128*> minv;
+    std::vector<z64*> minv32;
+    z128* gloc = nullptr;
 
     // twiddle tables e^{-2 pi i m / L}, m < L, per distinct length
     std::vector<int> tw_len;
@@ -200,11 +214,13 @@ struct Ctx {
     // Krylov vectors, c128 [max_rhs][3][ncell] each
     z128 *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr, *t = nullptr;
     z128 *xd = nullptr, *bd = nullptr;           // FP64 iterate / rhs copies for refinement
+    z128 *ph = nullptr, *sh = nullptr;           // preconditioned directions M^-1 p, M^-1 s (block Jacobi only)
     z128* xbest = nullptr;       // best iterate of the FP64 solves [max_rhs][3][ncell]
     void* gs = nullptr;          // Gconv y scratch of the transposed operator [max_rhs][3][ncell] (c128 size)
     // c64 Krylov vectors for the inner solve of the mixed path
     z64 *r32 = nullptr, *rhat32 = nullptr, *p32 = nullptr, *v32 = nullptr, *s32 = nullptr, *t32 = nullptr,
         *x32 = nullptr, *b32 = nullptr;
+    z64 *ph32 = nullptr, *sh32 = nullptr;
     double* partials = nullptr;  // reduction partials [max_rhs][kRedSlots][kRedBlocks]
     double* state = nullptr;     // BiCGSTAB scalars per right-hand side [max_rhs][kStateLen]
     void* stage = nullptr;       // small host/device staging area (8 KB)
@@ -275,6 +291,10 @@ int strain_launch(Ctx* c, const z128* u, z128* eps, int nrhs);
 int build_green_tables(Ctx* c);
 int rhs_points_launch(Ctx* c, int i_omega, const int* cells, const double* forces, int npts, double t0,
                       z128* b);
+int local_green_table(Ctx* c, int i_omega, z128* out);  // h^3 G at the offsets [-2, 2]^3, [125][6]
+
+// block-Jacobi preconditioner; see precond.hip
+int build_block_jacobi(Ctx* c);
 
 // the LS matvec Au = u - Gconv B u, its transpose A^T y = y - B Gconv y, and Gconv f, for the systems of a
 // set (fields indexed by slot); see capi.hip

@@ -706,6 +706,50 @@ int build_green_tables(Ctx* c) {
     return LS_OK;
 }
 
+namespace {
+
+// h^3 G at the offsets m in [-2, 2]^3, entry ((mz + 2) 5 + my + 2) 5 + mx + 2, six components (11, 22, 33, 23,
+// 13, 12): the closed form with the self term at m = 0, or the sampled LS_GREEN_ANISO table (octant with
+// mirror signs, or half-space read at -m for m_x < 0).  Offsets that do not fit in the grid are left zero.
+__global__ void k_local_table(z128* __restrict__ out, int N1, int N2, int N3, double h, GreenParams P, z128 self,
+                              const z128* __restrict__ greal, int half) {
+    const int t = threadIdx.x;
+    if (t >= 125) return;
+    const int mx = t % 5 - 2, my = (t / 5) % 5 - 2, mz = t / 25 - 2;
+    z128 g[6] = {};
+    if (abs(mx) < N1 && abs(my) < N2 && abs(mz) < N3) {
+        if (greal && half) {
+            const int s = mx < 0 ? -1 : 1;
+            const z128* e = greal + (((long long)(s * mz + N3 - 1) * (2 * N2 - 1) + (s * my + N2 - 1)) * N1 + s * mx) * 6;
+            for (int q = 0; q < 6; ++q) g[q] = e[q];
+        } else if (greal) {
+            const z128* e = greal + (((long long)abs(mz) * N2 + abs(my)) * N1 + abs(mx)) * 6;
+            const double sg[6] = {1.0, 1.0, 1.0, ((my < 0) != (mz < 0)) ? -1.0 : 1.0,
+                                  ((mx < 0) != (mz < 0)) ? -1.0 : 1.0, ((mx < 0) != (my < 0)) ? -1.0 : 1.0};
+            for (int q = 0; q < 6; ++q) g[q] = sg[q] * e[q];
+        } else if (mx == 0 && my == 0 && mz == 0) {
+            g[0] = g[1] = g[2] = self;
+        } else {
+            green6(mx * h, my * h, mz * h, P, g);
+            const double h3 = h * h * h;
+            for (int q = 0; q < 6; ++q) g[q] = h3 * g[q];
+        }
+    }
+    for (int q = 0; q < 6; ++q) out[t * 6 + q] = g[q];
+}
+
+}  // namespace
+
+int local_green_table(Ctx* c, int i_omega, z128* out) {
+    const GreenParams P = params_of(c, i_omega);
+    const bool aniso = c->green_mode == LS_GREEN_ANISO;
+    const z128 self = aniso ? z128{0.0, 0.0} : self_term(c->h, P);
+    hipLaunchKernelGGL(k_local_table, dim3(1), dim3(128), 0, c->stream, out, c->n1, c->n2, c->n3, c->h, P, self,
+                       aniso ? (const z128*)c->greal[i_omega] : nullptr, c->green_half ? 1 : 0);
+    LS_HIP(hipGetLastError());
+    return LS_OK;
+}
+
 // cells: host int[3 npts], forces: host double[3 npts] (already h^3 times the force density)
 int rhs_points_launch(Ctx* c, int i_omega, const int* cells, const double* forces, int npts, double t0, z128* b) {
     if (npts > 16) return fail(LS_ERR_ARG, "too many source points");

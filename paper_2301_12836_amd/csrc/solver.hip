@@ -155,6 +155,80 @@ __global__ __launch_bounds__(kThreads) void k_update_s(const cpx<T>* __restrict_
     write_partials(partials, rr, 0, ss, 0.0, sh);
 }
 
+// Right preconditioning by the block-Jacobi matrix M (or M^T for the transposed operator): the operator
+// is applied to M^-1 p and M^-1 s, which the updates of p and s form cell by cell (the three components of a
+// cell sit n apart) while they write p and s; x takes its steps along M^-1 p and M^-1 s.
+#define LS_FOR_CELLS(n) for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < (n); e += (long long)kRedBlocks * kThreads)
+
+template <typename T>
+__device__ __forceinline__ void minv_apply(const cpx<T>* __restrict__ M, long long n, long long e, int trans,
+                                           const cpx<T> v[3], cpx<T> y[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cpx<T> acc = {T(0), T(0)};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc = acc + M[(trans ? 3 * b + a : 3 * a + b) * n + e] * v[b];
+        y[a] = acc;
+    }
+}
+
+// p = r + beta (p - omega v);  ph = M^-1 p
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update_p_pre(const cpx<T>* __restrict__ r, cpx<T>* __restrict__ p,
+                                                           const cpx<T>* __restrict__ v, cpx<T>* __restrict__ ph,
+                                                           long long n, const double* __restrict__ state,
+                                                           SlotMap sm, PreTabs<T> pt) {
+    const int rr = sm.slot[blockIdx.y];
+    const double* st = state + rr * kStateLen;
+    if (st[S_ACTIVE] == 0.0) return;
+    const cpx<T> beta = {(T)st[S_BETA], (T)st[S_BETA + 1]};
+    const cpx<T> om = {(T)st[S_OMEGA], (T)st[S_OMEGA + 1]};
+    const cpx<T>* M = pt.m[blockIdx.y];
+    const long long off = (long long)rr * 3 * n;
+    LS_FOR_CELLS(n) {
+        cpx<T> pn[3], y[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const long long q = off + a * n + e;
+            pn[a] = load_nt(&r[q]) + beta * (load_nt(&p[q]) - om * load_nt(&v[q]));
+            store_nt(&p[q], pn[a]);
+        }
+        minv_apply(M, n, e, pt.trans, pn, y);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) store_nt(&ph[off + a * n + e], y[a]);
+    }
+}
+
+// s = r - alpha v;  sh = M^-1 s;  partials ||s||^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update_s_pre(const cpx<T>* __restrict__ r, const cpx<T>* __restrict__ v,
+                                                           cpx<T>* __restrict__ s, cpx<T>* __restrict__ sh,
+                                                           long long n, const double* __restrict__ state,
+                                                           double* partials, SlotMap sm, PreTabs<T> pt) {
+    __shared__ double shm[2 * kThreads];
+    const int rr = sm.slot[blockIdx.y];
+    const double* st = state + rr * kStateLen;
+    if (st[S_ACTIVE] == 0.0) return;
+    const cpx<T> al = {(T)st[S_ALPHA], (T)st[S_ALPHA + 1]};
+    const cpx<T>* M = pt.m[blockIdx.y];
+    const long long off = (long long)rr * 3 * n;
+    double ss = 0;
+    LS_FOR_CELLS(n) {
+        cpx<T> sv[3], y[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const long long q = off + a * n + e;
+            sv[a] = load_nt(&r[q]) - al * load_nt(&v[q]);
+            store_nt(&s[q], sv[a]);
+            ss += (double)sv[a].x * sv[a].x + (double)sv[a].y * sv[a].y;
+        }
+        minv_apply(M, n, e, pt.trans, sv, y);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) store_nt(&sh[off + a * n + e], y[a]);
+    }
+    write_partials(partials, rr, 0, ss, 0.0, shm);
+}
+
 // x += alpha p for the systems that converged at the half step
 template <typename T, typename X>
 __global__ __launch_bounds__(kThreads) void k_update_x_half(cpx<X>* __restrict__ x, const cpx<T>* __restrict__ p,
@@ -192,12 +266,14 @@ __global__ __launch_bounds__(kThreads) void k_dot_ts(const cpx<T>* __restrict__ 
 }
 
 // x += alpha p + omega s; r = s - omega t; partials ||r||^2, r^H r (complex)
-template <typename T, typename X>
+// PRE: the x step takes xs (M^-1 s) instead of s
+template <typename T, typename X, bool PRE>
 __global__ __launch_bounds__(kThreads) void k_update_xr(cpx<X>* __restrict__ x, const cpx<T>* __restrict__ p,
-                                                        const cpx<T>* __restrict__ s, const cpx<T>* __restrict__ t,
-                                                        cpx<T>* __restrict__ r, const cpx<T>* __restrict__ rhat,
-                                                        long long m, const double* __restrict__ state,
-                                                        double* partials, SlotMap sm) {
+                                                        const cpx<T>* __restrict__ s, const cpx<T>* __restrict__ xs,
+                                                        const cpx<T>* __restrict__ t, cpx<T>* __restrict__ r,
+                                                        const cpx<T>* __restrict__ rhat, long long m,
+                                                        const double* __restrict__ state, double* partials,
+                                                        SlotMap sm) {
     __shared__ double sh[2 * kThreads];
     const int rr = sm.slot[blockIdx.y];
     const double* st = state + rr * kStateLen;
@@ -209,8 +285,9 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(cpx<X>* __restrict__ x, 
     double nr = 0, re = 0, im = 0;
     LS_FOR_ELEMS(m) {
         const cpx<T> pv = load_nt(&p[off + e]), sv = load_nt(&s[off + e]);
+        const cpx<T> xsv = PRE ? load_nt(&xs[off + e]) : sv;
         const cpx<X> xv = load_nt(&x[off + e]);
-        store_nt(&x[off + e], xv + alx * cpx<X>{(X)pv.x, (X)pv.y} + omx * cpx<X>{(X)sv.x, (X)sv.y});
+        store_nt(&x[off + e], xv + alx * cpx<X>{(X)pv.x, (X)pv.y} + omx * cpx<X>{(X)xsv.x, (X)xsv.y});
         const cpx<T> rv = sv - om * load_nt(&t[off + e]);
         store_nt(&r[off + e], rv);
         const cpx<double> rw = wide(rv);
@@ -486,13 +563,15 @@ inline int stall_window(double r2, double b2) { return r2 < 1e-8 * b2 ? 30 : 300
 template <typename T, typename X, typename ApplyFn>
 int bicgstab(Ctx* c, const RhsSet& all, const cpx<T>* b, cpx<X>* x, const cpx<T>* ax0, cpx<T>* r, cpx<T>* rhat,
              cpx<T>* p, cpx<T>* v, cpx<T>* s, cpx<T>* t, const double* tol2v, int maxit, ApplyFn apply,
-             std::vector<int>& iters, const double* hscale = nullptr, BestIterate* keep = nullptr, bool fuse = false) {
+             std::vector<int>& iters, const double* hscale = nullptr, BestIterate* keep = nullptr, bool fuse = false,
+             cpx<T>* ph = nullptr, cpx<T>* sh = nullptr, int pre = 0) {
     const long long m = (long long)c->field_elems();
     int ns = 0;   // slots spanned by the set (state entries read back)
     for (int q = 0; q < all.n; ++q) ns = std::max(ns, all.slot[q] + 1);
     // r^H v and (t^H s, t^H t) come from the x-inverse epilogue of the operator call that writes v and t,
     // when it can compute them (forward operator, register four-step x pass)
-    const int fblocks = fuse ? fused_dot_blocks<T>(c) : 0;
+    // (not with a preconditioner: t^H s needs s, while the operator is applied to M^-1 s)
+    const int fblocks = fuse && !pre ? fused_dot_blocks<T>(c) : 0;
     const long long flines = 3LL * c->n3 * c->n2;
     hipLaunchKernelGGL((k_init<T>), dim3(kRedBlocks, all.n), dim3(kThreads), 0, c->stream, b, ax0, r, rhat, p, v, m,
                        c->partials, slot_map(all));
@@ -522,11 +601,21 @@ int bicgstab(Ctx* c, const RhsSet& all, const cpx<T>* b, cpx<X>* x, const cpx<T>
         int brc;
         const dim3 g(kRedBlocks, cur.n);
         const SlotMap sm = slot_map(cur);
+        PreTabs<T> pt{};
+        if (pre) {
+            for (int q = 0; q < cur.n; ++q)
+                pt.m[q] = sizeof(T) == 8 ? (const cpx<T>*)c->minv[cur.freq[q]] : (const cpx<T>*)c->minv32[cur.freq[q]];
+            pt.trans = pre == 2 ? 1 : 0;
+        }
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"), cur.n);
-        hipLaunchKernelGGL((k_update_p<T>), g, dim3(kThreads), 0, c->stream, r, p, v, m, c->state, sm);
+        if (pre)
+            hipLaunchKernelGGL((k_update_p_pre<T>), g, dim3(kThreads), 0, c->stream, r, p, v, ph, m / 3, c->state, sm,
+                               pt);
+        else
+            hipLaunchKernelGGL((k_update_p<T>), g, dim3(kThreads), 0, c->stream, r, p, v, m, c->state, sm);
         c->prof.end(c->stream);
         if (fblocks) c->dot = {1, rhat, c->dparts, flines, fblocks};
-        brc = apply(cur, p, v);
+        brc = apply(cur, pre ? ph : p, v);
         c->dot = {};
         if (brc) return brc;
         if (fblocks) {
@@ -538,13 +627,18 @@ int bicgstab(Ctx* c, const RhsSet& all, const cpx<T>* b, cpx<X>* x, const cpx<T>
             if ((brc = finalize(c, cur, PH_ALPHA, 2))) return brc;
         }
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"), cur.n);
-        hipLaunchKernelGGL((k_update_s<T>), g, dim3(kThreads), 0, c->stream, r, v, s, m, c->state, c->partials, sm);
+        if (pre)
+            hipLaunchKernelGGL((k_update_s_pre<T>), g, dim3(kThreads), 0, c->stream, r, v, s, sh, m / 3, c->state,
+                               c->partials, sm, pt);
+        else
+            hipLaunchKernelGGL((k_update_s<T>), g, dim3(kThreads), 0, c->stream, r, v, s, m, c->state, c->partials,
+                               sm);
         c->prof.end(c->stream);
         if ((brc = finalize(c, cur, PH_S, 1))) return brc;
-        hipLaunchKernelGGL((k_update_x_half<T, X>), g, dim3(kThreads), 0, c->stream, x, p, m, c->state, sm);
+        hipLaunchKernelGGL((k_update_x_half<T, X>), g, dim3(kThreads), 0, c->stream, x, pre ? ph : p, m, c->state, sm);
         hipLaunchKernelGGL(k_clear_half, dim3(1), dim3(kMaxRhs), 0, c->stream, c->state, cur.n, sm);
         if (fblocks) c->dot = {2, nullptr, c->dparts, flines, fblocks};
-        brc = apply(cur, s, t);
+        brc = apply(cur, pre ? sh : s, t);
         c->dot = {};
         if (brc) return brc;
         if (fblocks) {
@@ -556,8 +650,12 @@ int bicgstab(Ctx* c, const RhsSet& all, const cpx<T>* b, cpx<X>* x, const cpx<T>
             if ((brc = finalize(c, cur, PH_OMEGA, 3))) return brc;
         }
         c->prof.begin(c->stream, LS_PNAME(T, "blas1"), cur.n);
-        hipLaunchKernelGGL((k_update_xr<T, X>), g, dim3(kThreads), 0, c->stream, x, p, s, t, r, rhat, m, c->state,
-                           c->partials, sm);
+        if (pre)
+            hipLaunchKernelGGL((k_update_xr<T, X, true>), g, dim3(kThreads), 0, c->stream, x, ph, s, sh, t, r, rhat, m,
+                               c->state, c->partials, sm);
+        else
+            hipLaunchKernelGGL((k_update_xr<T, X, false>), g, dim3(kThreads), 0, c->stream, x, p, s, s, t, r, rhat, m,
+                               c->state, c->partials, sm);
         c->prof.end(c->stream);
         if ((brc = finalize(c, cur, PH_RHO, 4))) return brc;
         LS_HIP(hipGetLastError());
@@ -1217,6 +1315,8 @@ int solve_systems(Ctx* c, const int* freq, const z128* b, int nrhs, double tol, 
     std::vector<double> rel(nrhs, 0.0), nrm(nrhs, 0.0);
     std::vector<int> iters;
     int rc = LS_OK;
+    // block-Jacobi right preconditioning: M^-1 (1), or M^-T for the transposed operator (2)
+    const int pre = c->precond == LS_PRECOND_BLOCK_JACOBI ? (transposed ? 2 : 1) : 0;
     if (precision == LS_PREC_C128 && c->bicgstab_l > 1) {
         auto apply = [&](const z128* in, z128* out) { return op_apply<double>(c, all, in, out, transposed); };
         const std::vector<z128*> vec = krylov_vectors<double>(c);
@@ -1267,7 +1367,7 @@ int solve_systems(Ctx* c, const int* freq, const z128* b, int nrhs, double tol, 
                 for (int i = 0; i < todo.n; ++i) extra[todo.slot[i]] += 1;
             }
             rc = bicgstab<double, double>(c, todo, b, u_out, ax0, c->r, c->rhat, c->p, c->v, c->s, c->t, tol2v, maxit,
-                                          apply, iters, nullptr, &best, !transposed);
+                                          apply, iters, nullptr, &best, !transposed, c->ph, c->sh, pre);
             if (rc) return rc;
             RhsSet broken;
             for (int i = 0; i < todo.n; ++i) {
@@ -1414,7 +1514,7 @@ int solve_systems(Ctx* c, const int* freq, const z128* b, int nrhs, double tol, 
                 };
                 rc = bicgstab<float, float>(c, inner, c->b32, c->x32, nullptr, c->r32, c->rhat32, c->p32, c->v32,
                                             c->s32, c->t32, tol2v, maxit, apply32, iters, rel.data(), nullptr,
-                                            !transposed);
+                                            !transposed, c->ph32, c->sh32, pre);
                 if (rc) return rc;
                 for (int i = 0; i < inner.n; ++i) {
                     const int q = inner.slot[i];

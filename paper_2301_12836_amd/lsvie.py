@@ -35,6 +35,9 @@ LS_GREEN_ANISO = 2
 GREEN_MODES = {"exact": LS_GREEN_EXACT, "paper_sum": LS_GREEN_PAPER_SUM, "aniso": LS_GREEN_ANISO}
 LS_FLAG_NO_GRAPH = 1
 LS_FLAG_AUTOTUNE = 2
+LS_PRECOND_NONE = 0
+LS_PRECOND_BLOCK_JACOBI = 1
+PRECONDS = {None: LS_PRECOND_NONE, "none": LS_PRECOND_NONE, "block_jacobi": LS_PRECOND_BLOCK_JACOBI}
 PASS_NAMES = ("x_fwd", "y_fwd", "z_green", "y_inv", "x_inv")
 
 ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "LS_ERR_HIP",
@@ -42,7 +45,7 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
                LS_ERR_NONFINITE: "LS_ERR_NONFINITE", LS_ERR_STATE: "LS_ERR_STATE"}
 
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_noalloc", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
-            "ls_solve_moment", "ls_solve_multi", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_apply_T", "ls_convolve",
+            "ls_solve_moment", "ls_solve_multi", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_precond_blocks", "ls_apply_T", "ls_convolve",
             "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch", "ls_sample", "ls_synthesize", "ls_residual_history",
             "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_last_error")
 
@@ -60,7 +63,7 @@ class Grid(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("green_mode", ctypes.c_int), ("max_rhs", ctypes.c_int),
                 ("flags", ctypes.c_int), ("taper", ctypes.c_int), ("bicgstab_l", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("precond", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
 
 
 class Info(ctypes.Structure):
@@ -100,6 +103,7 @@ def load():
                          ctypes.POINTER(P)]),
         "ls_destroy": (None, [P]),
         "ls_set_contrast": (I, [P, P, P]),
+        "ls_precond_blocks": (I, [P, I, P]),
         "ls_apply": (I, [P, I, P, P, I]),
         "ls_apply_noalloc": (I, [P, I, P, P, I]),
         "ls_apply_c64": (I, [P, I, P, P, I]),
@@ -182,12 +186,12 @@ def check_buffer(t, shape, dtype, device, name="out"):
 # C-named entry points (torch tensors in, plain pointers to the library)
 
 def ls_setup(shape, h, C0, rho0, dC, drho, omegas, precision=LS_PREC_C128, green_mode=LS_GREEN_EXACT,
-             max_rhs=1, stream=None, flags=0, taper=0, bicgstab_l=1):
+             max_rhs=1, stream=None, flags=0, taper=0, bicgstab_l=1, precond=LS_PRECOND_NONE):
     """dC, drho: contiguous float64 CUDA tensors [21, N3, N2, N1] and [N3, N2, N1]; returns a handle."""
     lib = load()
     g = Grid((ctypes.c_int * 3)(*[int(v) for v in shape]), float(h))
     opt = Options(int(precision), int(green_mode), int(max_rhs), int(flags), int(taper), int(bicgstab_l),
-                  (ctypes.c_int * 2)())
+                  int(precond), (ctypes.c_int * 1)())
     c0, c0p = _dbl(C0, 36)
     om, omp = _dbl(omegas, len(np.atleast_1d(omegas)))
     out = ctypes.c_void_p()
@@ -202,6 +206,11 @@ def ls_destroy(ctx):
 
 def ls_set_contrast(ctx, dC, drho):
     return _check(load().ls_set_contrast(ctx, _ptr(dC), _ptr(drho)))
+
+
+def ls_precond_blocks(ctx, i_omega, minv):
+    """minv: contiguous complex128 CUDA tensor [9, N3, N2, N1] (inverse block entry (a, b) at [3 a + b])."""
+    return _check(load().ls_precond_blocks(ctx, int(i_omega), _ptr(minv)))
 
 
 def ls_apply(ctx, i_omega, u, Au, n_rhs):
@@ -392,7 +401,8 @@ class Context:
     """One grid + medium + frequency set on one GPU (owns the library context)."""
 
     def __init__(self, shape, h, C0, rho0, dc21, drho, omegas, precision="c128", green_mode="exact", max_rhs=1,
-                 device="cuda:0", graphs=True, autotune=False, taper=0, bicgstab_l=1):
+                 device="cuda:0", graphs=True, autotune=False, taper=0, bicgstab_l=1, precond=None):
+        """precond: None or "block_jacobi" (right point-block Jacobi preconditioning of every Bi-CGSTAB solve)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the LS library runs only on the GPU")
@@ -413,7 +423,7 @@ class Context:
                                GREEN_MODES[green_mode], max_rhs,
                                self.stream.cuda_stream,
                                (0 if graphs else LS_FLAG_NO_GRAPH) | (LS_FLAG_AUTOTUNE if autotune else 0),
-                               int(taper), int(bicgstab_l))
+                               int(taper), int(bicgstab_l), PRECONDS[precond])
         del dc, dr
 
     def close(self):
@@ -434,6 +444,13 @@ class Context:
         dc = torch.as_tensor(dc21, dtype=torch.float64).reshape(21, n3, n2, n1).to(self.device).contiguous()
         dr = torch.as_tensor(drho, dtype=torch.float64).reshape(n3, n2, n1).to(self.device).contiguous()
         ls_set_contrast(self.handle, dc, dr)
+
+    def precond_blocks(self, i_omega=0):
+        """Inverse diagonal blocks of the block-Jacobi preconditioner: complex128 [N3, N2, N1, 3, 3]."""
+        torch = self.torch
+        out = torch.empty((9,) + self.field_shape[1:], dtype=torch.complex128, device=self.device)
+        ls_precond_blocks(self.handle, i_omega, out)
+        return out.permute(1, 2, 3, 0).reshape(self.field_shape[1:] + (3, 3))
 
     # helpers
     def _field(self, t, dtype=None):
@@ -646,8 +663,8 @@ def solve_batch(contexts, jobs, tol=1e-8, maxit=2000, precision="c128", raise_on
 
 
 def context_from_model(model, precision="c128", max_rhs=1, green_mode="exact", device="cuda:0", omegas=None,
-                       graphs=True, autotune=False, taper=0, bicgstab_l=1):
+                       graphs=True, autotune=False, taper=0, bicgstab_l=1, precond=None):
     return Context(model.shape, model.h, model.C0, model.rho0, model.dc21, model.drho,
                    model.omegas if omegas is None else omegas, precision=precision, green_mode=green_mode,
                    max_rhs=max_rhs, device=device, graphs=graphs, autotune=autotune, taper=taper,
-                   bicgstab_l=bicgstab_l)
+                   bicgstab_l=bicgstab_l, precond=precond)
