@@ -105,7 +105,7 @@ static void release(Ctx* c) {
     void* ptrs[] = {c->dc, c->drho, c->dc32, c->drho32, c->work, c->tau, c->r, c->rhat, c->p, c->v, c->s, c->t,
                     c->xd, c->bd, c->gs, c->r32, c->rhat32, c->p32, c->v32, c->s32, c->t32, c->x32, c->b32, c->partials,
                     c->state, c->stage, c->red, c->batch_b, c->batch_x, c->ints, c->gl_nodes, c->gpart, c->xbest, c->dparts,
-                    c->gloc, c->ph, c->sh, c->ph32, c->sh32};
+                    c->gloc, c->ph, c->sh, c->ph32, c->sh32, c->dcp, c->dcp32};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto q : c->ghat) (void)hipFree(q);
@@ -537,9 +537,11 @@ int ls_setup(const ls_grid* grid, const double C0[36], double rho0, const double
     };
     A((void**)&c->dc, 21 * n * sizeof(double));
     A((void**)&c->drho, n * sizeof(double));
+    A((void**)&c->dcp, contrast_packed_elems(c, false) * sizeof(double));
     if (c->mixed) {
         A((void**)&c->dc32, 21 * n * sizeof(float));
         A((void**)&c->drho32, n * sizeof(float));
+        A((void**)&c->dcp32, contrast_packed_elems(c, true) * sizeof(float));
     }
     c->ghat.assign(n_omega, nullptr);
     c->ghat32.assign(n_omega, nullptr);

@@ -187,6 +187,10 @@ struct Ctx {
     double* drho = nullptr;   // [ncell]
     float* dc32 = nullptr;
     float* drho32 = nullptr;
+    // the same contrast packed tile by tile for the fused contrast kernel (contrast_packed_elems): the 21
+    // values of the cells of one xy tile on one z plane are contiguous, so a block reads one run per plane
+    double* dcp = nullptr;
+    float* dcp32 = nullptr;
 
     // k-space Green's tables per frequency: octant [L3/2+1][L2/2+1][L1/2+1][6] (half-space
     // [L3][L2][L1/2+1][6] when green_half), already scaled by 1/(L1 L2 L3) so the inverse FFT needs no
@@ -278,6 +282,7 @@ template <typename T>
 int to_work(Ctx* c, const RhsSet& set, const cpx<T>* f, cpx<T>* work);
 int grad_contrast_launch(Ctx* c, int i_omega, const z128* u, const z128* mu, int nrhs, double* g21, double* grho);
 int fold_background(Ctx* c, const double* dc_in, const double* drho_in, const double fold21[21]);
+size_t contrast_packed_elems(const Ctx* c, bool fp32);   // elements of dcp (fp32 false) or dcp32
 bool use_fused_contrast();  // false under LS_CONTRAST=split (the two-kernel contrast, which needs tau)
 int conj_launch(Ctx* c, z128* a, long long m);
 int sample_launch(Ctx* c, const z128* u, int nrhs, const int* rec_host, int nrec, z128* out);
