@@ -547,6 +547,110 @@ __global__ __launch_bounds__((TX * ZSplit<T, L, HALF>::N1), (sizeof(T) == 4 ? (z
         }
 }
 
+// Fused z pass for the lengths with a factor 3 (L = A x 16, A = 3, 6, 12: 48, 96, 192) with the octant table:
+// an asymmetric four-step over 16 threads per column.  With n = n1 + A n2 and k = k2 + 16 k1 (n1, k1 < A;
+// n2, k2 < 16),
+//   X[k2 + 16 k1] = sum_{n1} W_A^{n1 k1} W_L^{n1 k2} sum_{n2} W_16^{n2 k2} x[n1 + A n2].
+// Threads q < A run the length-16 DFT of the column's elements q + A n2 (n2 < 8: the data occupy z < L/2, so
+// the upper half is zero) and the twiddles W_L^{q k2}; one LDS transpose gives thread q = k2 the A values of
+// its length-A DFT (reg_dft3), whose outputs X[q + 16 k1] sit in slot k1 when the Green's table multiplies
+// them.  The inverse runs the same steps backwards and threads q < A store their first 8 outputs.  The same
+// register footprint (16 values of each component) and block (TX columns x 16 threads) as length 256.
+template <typename T, int L, int TX, int ZBS>
+__global__ __launch_bounds__(TX * 16, (sizeof(T) == 4 ? 3 : 1)) void k_fs_zgreen3(
+    cpx<T>* __restrict__ data, int nrhs, int L1, int L2, long long CS, long long RS, int n3, GreenTabs<T> gt,
+    const cpx<T>* __restrict__ tw, long long nb_real) {
+    constexpr int B = 16, A = L / B;
+    static_assert(A * B == L && (A == 3 || A == 6 || A == 12), "lengths 48, 96, 192");
+    __shared__ cpx<T> lds[L * TX];
+    __shared__ cpx<T> tws[L];
+    const long long lb = xcd_logical_block(blockIdx.x, nb_real);
+    if (lb < 0) return;
+    const int tid = threadIdx.x, t = tid % TX, q = tid / TX;
+    stage_twiddles<T, L>(tws, tw, tid, TX * B);
+    const int ntx = L1 / TX;
+    const int rhs = (int)(lb % nrhs);
+    const cpx<T>* __restrict__ ghat = gt.g[rhs];   // this position's frequency
+    const int xt = paired_row((int)((lb / nrhs) % ntx), ntx);
+    const int y = paired_row((int)(lb / ((long long)nrhs * ntx)), L2);
+    const int kx0 = xt * TX + t;
+    cpx<T>* const col = data + (long long)rhs * RS + zrow_offset(y, ZBS, L1) + kx0;
+    const bool s1 = q < A;   // a first-stage thread: element n1 = q of the line
+    const int qa = s1 ? q : A - 1;
+    cpx<T> v[3][B];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int e = q + A * j;
+            v[c][j] = (s1 && j < B / 2 && e < n3) ? load_nt(&col[c * CS + zplane_offset(e, ZBS, L2, L1)])
+                                                   : cpx<T>{T(0), T(0)};
+        }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        // every thread transforms (threads q >= A hold zeros and write nothing): no divergent merge
+        reg_dft<-1, B, T, true>(v[c]);
+#pragma unroll
+        for (int k2 = 1; k2 < B; ++k2) v[c][k2] = v[c][k2] * tw_at<-1>(tws, qa * k2);
+        if (s1) {
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) lds[(k2 * A + q) * TX + t] = v[c][k2];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) v[c][n1] = lds[(q * A + n1) * TX + t];
+#pragma unroll
+        for (int n1 = A; n1 < B; ++n1) v[c][n1] = cpx<T>{T(0), T(0)};   // unused slots: no live registers
+        __syncthreads();
+        reg_dft3<-1, A, T>(v[c]);
+    }
+
+    const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1;
+    int kx, ky;
+    bool fx, fy;
+    fold_index(kx0, L1, kx, fx);
+    fold_index(y, L2, ky, fy);
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+        int kz;
+        bool fz;
+        fold_index(q + B * i, L, kz, fz);
+        cpx<T> g[6];
+        load_g6(ghat, ((long long)kz * O2 + ky) * O1 + kx, g);
+        if (fy != fz) g[3] = T(-1) * g[3];
+        if (fx != fz) g[4] = T(-1) * g[4];
+        if (fx != fy) g[5] = T(-1) * g[5];
+        const cpx<T> g11 = g[0], g22 = g[1], g33 = g[2], g23 = g[3], g13 = g[4], g12 = g[5];
+        const cpx<T> f1 = v[0][i], f2 = v[1][i], f3 = v[2][i];
+        v[0][i] = g11 * f1 + g12 * f2 + g13 * f3;
+        v[1][i] = g12 * f1 + g22 * f2 + g23 * f3;
+        v[2][i] = g13 * f1 + g23 * f2 + g33 * f3;
+    }
+
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        reg_dft3<+1, A, T>(v[c]);
+#pragma unroll
+        for (int n1 = 1; n1 < A; ++n1) v[c][n1] = v[c][n1] * tw_at<+1>(tws, n1 * q);
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) lds[(n1 * B + q) * TX + t] = v[c][n1];
+        __syncthreads();
+        // threads q >= A read and transform row A - 1 again and store nothing
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) v[c][k2] = lds[(qa * B + k2) * TX + t];
+        __syncthreads();
+        reg_dft<+1, B, T>(v[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < B / 2; ++j) {
+            const int e = q + A * j;
+            if (s1 && e < n3) store_nt(&col[c * CS + zplane_offset(e, ZBS, L2, L1)], v[c][j]);
+        }
+}
+
 // z pass in registers where three components of N2 values fit (both precisions up to 512, paired at 512)
 template <typename T, int L, bool HALF>
 constexpr bool fs_z_ok() {
@@ -653,6 +757,25 @@ constexpr int z_threads() {
 template <typename T, int LL, bool HALF>
 int try_fs_z(Ctx* c, bool fs, cpx<T>* data, int nrhs, long long CS, long long RS, long long ES, const GreenTabs<T>& ghat,
              const cpx<T>* tw) {
+    if constexpr (!HALF && (LL == 192 || (sizeof(T) == 4 && (LL == 48 || LL == 96)))) {
+        // the asymmetric four-step (k_fs_zgreen3); the half-space table keeps the LDS kernel, and so does FP64
+        // at 48 and 96, where it measured faster (6-RHS launches: 0.027 against 0.035 ms at 48, 0.129
+        // against 0.131 ms at 96; at 192 the register kernel takes 0.80 ms against 1.24)
+        if (fs) {
+            constexpr int TX = seg_cols<T>();
+            if (c->L1 % TX) return -1;
+            const long long nb = (long long)nrhs * (c->L1 / TX) * c->L2;
+            const unsigned nbl = (unsigned)((nb + 7) / 8 * 8);
+            if (c->zbs)
+                hipLaunchKernelGGL((k_fs_zgreen3<T, LL, TX, 3>), dim3(nbl), dim3(TX * 16), 0, c->stream, data, nrhs,
+                                   c->L1, c->L2, CS, RS, c->n3, ghat, tw, nb);
+            else
+                hipLaunchKernelGGL((k_fs_zgreen3<T, LL, TX, 0>), dim3(nbl), dim3(TX * 16), 0, c->stream, data, nrhs,
+                                   c->L1, c->L2, CS, RS, c->n3, ghat, tw, nb);
+            return 1;
+        }
+        return 0;
+    }
     if constexpr (fs_z_ok<T, LL, HALF>()) {
         // the register kernel needs 2^zbs to divide the threads per line
         if (fs && (z_threads<T, LL, HALF>() / seg_cols<T>()) % (1 << c->zbs) == 0) {

@@ -83,6 +83,66 @@ __device__ __forceinline__ void reg_dft(cpx<T>* v) {
     }
 }
 
+// cos(2 pi m / 24) for m = 0..6 (first quadrant); with unit_root24 the roots of unity of orders 3, 6, 12, 24
+constexpr double kCos24[7] = {1.0,
+                              0.96592582628906828674974319972890,
+                              0.86602540378443864676372317075294,
+                              0.70710678118654752440084436210485,
+                              0.5,
+                              0.25881904510252076234889883762405,
+                              0.0};
+
+// e^{SIGN 2 pi i m / N} for N dividing 24, as a compile-time constant
+template <int SIGN, int N, typename T>
+__device__ __forceinline__ constexpr cpx<T> unit_root24(int m) {
+    const int q = ((m % N) + N) % N * (24 / N);   // index on the 24-point circle
+    double c = 0.0, s = 0.0;
+    if (q <= 6) {
+        c = kCos24[q];
+        s = kCos24[6 - q];
+    } else if (q <= 12) {
+        c = -kCos24[12 - q];
+        s = kCos24[q - 6];
+    } else if (q <= 18) {
+        c = -kCos24[q - 12];
+        s = -kCos24[18 - q];
+    } else {
+        c = kCos24[24 - q];
+        s = -kCos24[q - 18];
+    }
+    return {T(c), T(SIGN * s)};
+}
+
+// In-register DFT of length N = 3, 6 or 12 with sign SIGN, natural order in and out: with n = a + 3 b and
+// k = k2 + B k1 (B = N / 3), a length-B DFT of each residue a, the twiddles W_N^{a k2}, then length-3 DFTs.
+template <int SIGN, int N, typename T>
+__device__ __forceinline__ void reg_dft3(cpx<T>* v) {
+    if constexpr (N == 3) {
+        SmallDft<SIGN, 3, T>::run(v);
+    } else {
+        constexpr int B = N / 3;
+        static_assert(B == 2 || B == 4, "lengths 3, 6, 12");
+        cpx<T> tmp[N];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cpx<T> w[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) w[b] = v[a + 3 * b];
+            SmallDft<SIGN, B, T>::run(w);
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2)
+                tmp[a * B + k2] = (a * k2 == 0) ? w[k2] : w[k2] * unit_root24<SIGN, N, T>(a * k2);
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) {
+            cpx<T> w[3] = {tmp[k2], tmp[B + k2], tmp[2 * B + k2]};
+            SmallDft<SIGN, 3, T>::run(w);
+#pragma unroll
+            for (int k1 = 0; k1 < 3; ++k1) v[k2 + B * k1] = w[k1];
+        }
+    }
+}
+
 template <int L>
 struct FourStep {
     static constexpr int N1 = (L == 16) ? 4 : (L == 32) ? 4 : (L == 64) ? 8 : (L == 128) ? 8 : 16;
