@@ -651,6 +651,126 @@ __global__ __launch_bounds__(TX * 16, (sizeof(T) == 4 ? 3 : 1)) void k_fs_zgreen
         }
 }
 
+// Fused z pass at length 384 = 24 x 16 with the octant table: the asymmetric four-step of k_fs_zgreen3 with the
+// second stage split over thread pairs.  Threads q < 24 run the length-16 DFTs of elements q + 24 n2 (n2 < 8)
+// and the twiddles W_384^{q k2}; after the LDS transpose thread p = 2 k2 + h holds the 12 values n1 = 2 m + h
+// of line k2, runs a length-12 DFT, and the radix-2 step that joins the even (h = 0) and odd (h = 1) halves
+// of the length-24 DFT exchanges values with the partner thread p ^ 1, TX lanes away in the same wavefront:
+// thread p ends with X[k2 + 16 (i + 12 h)] in slot i.  The inverse runs the same steps backwards.  32 threads
+// per column, 16 values of each component per thread.
+template <typename T, int TX, int ZBS>
+__global__ __launch_bounds__(TX * 32, (sizeof(T) == 4 ? 2 : 1)) void k_fs_zgreen3p(
+    cpx<T>* __restrict__ data, int nrhs, int L1, int L2, long long CS, long long RS, int n3, GreenTabs<T> gt,
+    const cpx<T>* __restrict__ tw, long long nb_real) {
+    constexpr int L = 384, B = 16, A = 24, H = 12;
+    static_assert(2 * TX <= 64, "partner lanes share a wavefront");
+    __shared__ cpx<T> lds[L * TX];
+    __shared__ cpx<T> tws[L];
+    const long long lb = xcd_logical_block(blockIdx.x, nb_real);
+    if (lb < 0) return;
+    const int tid = threadIdx.x, t = tid % TX, q = tid / TX;
+    stage_twiddles<T, L>(tws, tw, tid, TX * 32);
+    const int ntx = L1 / TX;
+    const int rhs = (int)(lb % nrhs);
+    const cpx<T>* __restrict__ ghat = gt.g[rhs];
+    const int xt = paired_row((int)((lb / nrhs) % ntx), ntx);
+    const int y = paired_row((int)(lb / ((long long)nrhs * ntx)), L2);
+    const int kx0 = xt * TX + t;
+    cpx<T>* const col = data + (long long)rhs * RS + zrow_offset(y, ZBS, L1) + kx0;
+    const bool s1 = q < A;       // a first-stage thread (element n1 = q)
+    const int qa = s1 ? q : A - 1;
+    const int k2 = q >> 1;       // second stage: line k2, half h
+    const bool h = q & 1;
+    cpx<T> v[3][B];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int e = q + A * j;
+            v[c][j] = (s1 && j < B / 2 && e < n3) ? load_nt(&col[c * CS + zplane_offset(e, ZBS, L2, L1)])
+                                                   : cpx<T>{T(0), T(0)};
+        }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        // every thread transforms (threads q >= 24 hold zeros and write nothing): no divergent merge
+        reg_dft<-1, B, T, true>(v[c]);
+#pragma unroll
+        for (int kk = 1; kk < B; ++kk) v[c][kk] = v[c][kk] * tw_at<-1>(tws, qa * kk);
+        if (s1) {
+#pragma unroll
+            for (int kk = 0; kk < B; ++kk) lds[(kk * A + q) * TX + t] = v[c][kk];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < H; ++m) v[c][m] = lds[(k2 * A + 2 * m + (int)h) * TX + t];
+#pragma unroll
+        for (int m = H; m < B; ++m) v[c][m] = cpx<T>{T(0), T(0)};
+        __syncthreads();
+        reg_dft3<-1, H, T>(v[c]);
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            cpx<T> mine = v[c][i];
+            if (i > 0) mine = sel(h, mine * tw_at<-1>(tws, i * B), mine);
+            const cpx<T> other = lane_xor(mine, TX);
+            v[c][i] = sel(h, other - mine, mine + other);
+        }
+    }
+
+    const int O1 = L1 / 2 + 1, O2 = L2 / 2 + 1;
+    int kx, ky;
+    bool fx, fy;
+    fold_index(kx0, L1, kx, fx);
+    fold_index(y, L2, ky, fy);
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        int kz;
+        bool fz;
+        fold_index(k2 + B * (i + H * (int)h), L, kz, fz);
+        cpx<T> g[6];
+        load_g6(ghat, ((long long)kz * O2 + ky) * O1 + kx, g);
+        if (fy != fz) g[3] = T(-1) * g[3];
+        if (fx != fz) g[4] = T(-1) * g[4];
+        if (fx != fy) g[5] = T(-1) * g[5];
+        const cpx<T> g11 = g[0], g22 = g[1], g33 = g[2], g23 = g[3], g13 = g[4], g12 = g[5];
+        const cpx<T> f1 = v[0][i], f2 = v[1][i], f3 = v[2][i];
+        v[0][i] = g11 * f1 + g12 * f2 + g13 * f3;
+        v[1][i] = g12 * f1 + g22 * f2 + g23 * f3;
+        v[2][i] = g13 * f1 + g23 * f2 + g33 * f3;
+    }
+
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const cpx<T> mine = v[c][i];
+            const cpx<T> other = lane_xor(mine, TX);
+            const cpx<T> d = other - mine;
+            const cpx<T> dw = (i > 0) ? d * tw_at<+1>(tws, i * B) : d;
+            v[c][i] = sel(h, dw, mine + other);
+        }
+        reg_dft3<+1, H, T>(v[c]);
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const int n1 = 2 * m + (int)h;
+            lds[(n1 * B + k2) * TX + t] = v[c][m] * tw_at<+1>(tws, n1 * k2);
+        }
+        __syncthreads();
+        // threads q >= 24 read and transform row 23 again and store nothing
+#pragma unroll
+        for (int kk = 0; kk < B; ++kk) v[c][kk] = lds[(qa * B + kk) * TX + t];
+        __syncthreads();
+        reg_dft<+1, B, T>(v[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < B / 2; ++j) {
+            const int e = q + A * j;
+            if (s1 && e < n3) store_nt(&col[c * CS + zplane_offset(e, ZBS, L2, L1)], v[c][j]);
+        }
+}
+
 // z pass in registers where three components of N2 values fit (both precisions up to 512, paired at 512)
 template <typename T, int L, bool HALF>
 constexpr bool fs_z_ok() {
@@ -771,6 +891,23 @@ int try_fs_z(Ctx* c, bool fs, cpx<T>* data, int nrhs, long long CS, long long RS
                                    c->L1, c->L2, CS, RS, c->n3, ghat, tw, nb);
             else
                 hipLaunchKernelGGL((k_fs_zgreen3<T, LL, TX, 0>), dim3(nbl), dim3(TX * 16), 0, c->stream, data, nrhs,
+                                   c->L1, c->L2, CS, RS, c->n3, ghat, tw, nb);
+            return 1;
+        }
+        return 0;
+    }
+    if constexpr (!HALF && LL == 384) {
+        // the paired asymmetric four-step (k_fs_zgreen3p); the half-space table keeps the LDS kernel
+        if (fs) {
+            constexpr int TX = seg_cols<T>();
+            if (c->L1 % TX) return -1;
+            const long long nb = (long long)nrhs * (c->L1 / TX) * c->L2;
+            const unsigned nbl = (unsigned)((nb + 7) / 8 * 8);
+            if (c->zbs)
+                hipLaunchKernelGGL((k_fs_zgreen3p<T, TX, 3>), dim3(nbl), dim3(TX * 32), 0, c->stream, data, nrhs,
+                                   c->L1, c->L2, CS, RS, c->n3, ghat, tw, nb);
+            else
+                hipLaunchKernelGGL((k_fs_zgreen3p<T, TX, 0>), dim3(nbl), dim3(TX * 32), 0, c->stream, data, nrhs,
                                    c->L1, c->L2, CS, RS, c->n3, ghat, tw, nb);
             return 1;
         }
