@@ -304,6 +304,203 @@ __global__ __launch_bounds__(TX * FourStep<L>::N1) void k_fs_strided(cpx<T>* __r
     }
 }
 
+// Strided pass at the lengths with a factor 3: the asymmetric four-step of k_fs_zgreen3 (L = A x 16, A = 3, 6,
+// 12, 16 threads per column) for one component, without the Green multiply.  Forward: natural input (threads
+// q < A hold elements q + A j), outputs X[q + 16 k1] in slot k1; inverse: the reverse, natural outputs.
+// Threads q >= A transform zeros or a copy of row A - 1 and write nothing (no divergent merge).
+template <typename T, int L, int TX, int SIGN, bool PRUNE>
+__global__ __launch_bounds__(TX * 16) void k_fs_strided3(cpx<T>* __restrict__ data, long long S1, long long S2,
+                                                          long long ES, int n_in, int n_out,
+                                                          const cpx<T>* __restrict__ tw) {
+    constexpr int B = 16, A = L / B;
+    static_assert(A * B == L && (A == 3 || A == 6 || A == 12), "lengths 48, 96, 192");
+    __shared__ cpx<T> lds[L * TX];
+    __shared__ cpx<T> tws[L];
+    const int tid = threadIdx.x, t = tid % TX, q = tid / TX;
+    stage_twiddles<T, L>(tws, tw, tid, TX * B);
+    cpx<T>* base = data + (long long)blockIdx.z * S1 + (long long)blockIdx.y * S2 + (long long)blockIdx.x * TX + t;
+    const bool s1 = q < A;
+    const int qa = s1 ? q : A - 1;
+    cpx<T> v[B];
+    if constexpr (SIGN < 0) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int e = q + A * j;
+            v[j] = (s1 && !(PRUNE && j >= B / 2) && e < n_in) ? load_nt(&base[e * ES]) : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        reg_dft<SIGN, B, T, PRUNE>(v);
+#pragma unroll
+        for (int k2 = 1; k2 < B; ++k2) v[k2] = v[k2] * tw_at<SIGN>(tws, qa * k2);
+        if (s1) {
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) lds[(k2 * A + q) * TX + t] = v[k2];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) v[n1] = lds[(q * A + n1) * TX + t];
+        reg_dft3<SIGN, A, T>(v);
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            const int k = q + B * k1;
+            if (k < n_out) store_nt(&base[k * ES], v[k1]);
+        }
+    } else {
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            const int k = q + B * k1;
+            v[k1] = k < n_in ? load_nt(&base[k * ES]) : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        reg_dft3<SIGN, A, T>(v);
+#pragma unroll
+        for (int n1 = 1; n1 < A; ++n1) v[n1] = v[n1] * tw_at<SIGN>(tws, n1 * q);
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) lds[(n1 * B + q) * TX + t] = v[n1];
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) v[k2] = lds[(qa * B + k2) * TX + t];
+        reg_dft<SIGN, B, T>(v);
+        if (s1) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                const int e = q + A * j;
+                if (!(PRUNE && j >= B / 2) && e < n_out) base[e * ES] = v[j];
+            }
+        }
+    }
+}
+
+// Strided pass at length 384 = 24 x 16: the paired asymmetric four-step of k_fs_zgreen3p for one component.
+// Forward: thread p = 2 k2 + h ends with X[k2 + 16 (i + 12 h)] in slot i; inverse: the reverse.
+template <typename T, int TX, int SIGN, bool PRUNE>
+__global__ __launch_bounds__(TX * 32) void k_fs_strided3p(cpx<T>* __restrict__ data, long long S1, long long S2,
+                                                           long long ES, int n_in, int n_out,
+                                                           const cpx<T>* __restrict__ tw) {
+    constexpr int L = 384, B = 16, A = 24, H = 12;
+    static_assert(2 * TX <= 64, "partner lanes share a wavefront");
+    __shared__ cpx<T> lds[L * TX];
+    __shared__ cpx<T> tws[L];
+    const int tid = threadIdx.x, t = tid % TX, q = tid / TX;
+    stage_twiddles<T, L>(tws, tw, tid, TX * 32);
+    cpx<T>* base = data + (long long)blockIdx.z * S1 + (long long)blockIdx.y * S2 + (long long)blockIdx.x * TX + t;
+    const bool s1 = q < A;
+    const int qa = s1 ? q : A - 1;
+    const int k2 = q >> 1;
+    const bool h = q & 1;
+    cpx<T> v[B];
+    if constexpr (SIGN < 0) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int e = q + A * j;
+            v[j] = (s1 && !(PRUNE && j >= B / 2) && e < n_in) ? load_nt(&base[e * ES]) : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        reg_dft<SIGN, B, T, PRUNE>(v);
+#pragma unroll
+        for (int kk = 1; kk < B; ++kk) v[kk] = v[kk] * tw_at<SIGN>(tws, qa * kk);
+        if (s1) {
+#pragma unroll
+            for (int kk = 0; kk < B; ++kk) lds[(kk * A + q) * TX + t] = v[kk];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < H; ++m) v[m] = lds[(k2 * A + 2 * m + (int)h) * TX + t];
+        reg_dft3<SIGN, H, T>(v);
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            cpx<T> mine = v[i];
+            if (i > 0) mine = sel(h, mine * tw_at<SIGN>(tws, i * B), mine);
+            const cpx<T> other = lane_xor(mine, TX);
+            const cpx<T> x = sel(h, other - mine, mine + other);
+            const int k = k2 + B * (i + H * (int)h);
+            if (k < n_out) store_nt(&base[k * ES], x);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const int k = k2 + B * (i + H * (int)h);
+            v[i] = k < n_in ? load_nt(&base[k * ES]) : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const cpx<T> mine = v[i];
+            const cpx<T> other = lane_xor(mine, TX);
+            const cpx<T> d = other - mine;
+            const cpx<T> dw = (i > 0) ? d * tw_at<SIGN>(tws, i * B) : d;
+            v[i] = sel(h, dw, mine + other);
+        }
+        reg_dft3<SIGN, H, T>(v);
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const int n1 = 2 * m + (int)h;
+            lds[(n1 * B + k2) * TX + t] = v[m] * tw_at<SIGN>(tws, n1 * k2);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < B; ++kk) v[kk] = lds[(qa * B + kk) * TX + t];
+        reg_dft<SIGN, B, T>(v);
+        if (s1) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                const int e = q + A * j;
+                if (!(PRUNE && j >= B / 2) && e < n_out) base[e * ES] = v[j];
+            }
+        }
+    }
+}
+
+// x-inverse epilogue of one output element qq: MODE 1 out = u - v, with the inner products of DOT accumulated
+// (1: a^H out; 2: out^H u and |out|^2); MODE 2 out = v
+template <typename T, int MODE, int DOT>
+__device__ __forceinline__ void contig_out(cpx<T> v, long long qq, const cpx<T>* __restrict__ u,
+                                           cpx<T>* __restrict__ out, const cpx<T>* __restrict__ dot_a,
+                                           double acc[3]) {
+    if constexpr (MODE == 1) {
+        const cpx<T> uu = load_nt(&u[qq]);
+        const cpx<T> o = uu - v;
+        store_nt(&out[qq], o);
+        if constexpr (DOT == 1) {   // a^H o
+            const cpx<T> a = load_nt(&dot_a[qq]);
+            acc[0] += (double)a.x * o.x + (double)a.y * o.y;
+            acc[1] += (double)a.x * o.y - (double)a.y * o.x;
+        } else if constexpr (DOT == 2) {   // o^H u, |o|^2
+            acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
+            acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
+            acc[2] += (double)o.x * o.x + (double)o.y * o.y;
+        }
+    } else {
+        store_nt(&out[qq], v);
+    }
+}
+
+// Fixed-order block sum of the fused inner products of an x-inverse block of NT threads holding TY lines:
+// wavefront shuffles, then the wavefronts in order, into dot_parts[(rhs kRedSlots + slot) nparts + block of
+// the right-hand side].
+template <int NT, int TY, int DOT>
+__device__ __forceinline__ void contig_dot_parts(const double acc[3], int tid, double* __restrict__ dot_parts,
+                                                 long long dot_lines, int dot_nparts, const SlotMap& sm) {
+    constexpr int NW = (NT + 63) / 64;   // whole wavefronts only (checked by fused_dot_blocks)
+    constexpr int NS = DOT == 1 ? 2 : 3;
+    __shared__ double red[NW][NS];
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double x = acc[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+        if (lane == 0) red[wave][k] = x;
+    }
+    __syncthreads();
+    if (tid < NS) {
+        double x = 0.0;
+        for (int w = 0; w < NW; ++w) x += red[w][tid];
+        const long long l0 = (long long)blockIdx.x * TY;
+        const long long rr = l0 / dot_lines, blk = (l0 - rr * dot_lines) / TY;
+        dot_parts[((long long)sm.slot[rr] * kRedSlots + tid) * dot_nparts + blk] = x;
+    }
+}
+
 // Contiguous (x) pass over TY lines per block.  MODE 0: forward in place; MODE 1: inverse with
 // out = u - v (compact); MODE 2: inverse with out = v (compact).
 // DOT (MODE 1 only): inner products of the written field, fused for the Bi-CGSTAB iteration that
@@ -362,48 +559,179 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
 #pragma unroll
             for (int j = 0; j < F::N2; ++j) {
                 const int e = q + F::N1 * j;
-                if (!half_slot<L, PRUNE>(j) && e < n_out) {
-                    const long long qq = orow * n_out + e;
-                    if constexpr (MODE == 1) {
-                        const cpx<T> uu = load_nt(&u[qq]);
-                        const cpx<T> o = uu - v[j];
-                        store_nt(&out[qq], o);
-                        if constexpr (DOT == 1) {   // a^H o
-                            const cpx<T> a = load_nt(&dot_a[qq]);
-                            acc[0] += (double)a.x * o.x + (double)a.y * o.y;
-                            acc[1] += (double)a.x * o.y - (double)a.y * o.x;
-                        } else if constexpr (DOT == 2) {   // o^H u, |o|^2
-                            acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
-                            acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
-                            acc[2] += (double)o.x * o.x + (double)o.y * o.y;
-                        }
-                    } else {
-                        store_nt(&out[qq], v[j]);
-                    }
-                }
+                if (!half_slot<L, PRUNE>(j) && e < n_out)
+                    contig_out<T, MODE, DOT>(v[j], orow * n_out + e, u, out, dot_a, acc);
             }
         }
-        if constexpr (MODE == 1 && DOT != 0) {
-            // fixed-order block sum: wavefront shuffles, then the wavefronts in order
-            constexpr int NW = (TY * F::N1 + 63) / 64;   // whole wavefronts only (checked by fused_dot_blocks)
-            constexpr int NS = DOT == 1 ? 2 : 3;
-            __shared__ double red[NW][NS];
-            const int lane = tid & 63, wave = tid >> 6;
+        if constexpr (MODE == 1 && DOT != 0)
+            contig_dot_parts<TY * F::N1, TY, DOT>(acc, tid, dot_parts, dot_lines, dot_nparts, sm);
+    }
+}
+
+// Contiguous (x) pass at the lengths with a factor 3 (L = A x 16, A = 3, 6, 12): the asymmetric four-step of
+// k_fs_strided3 along lines, 16 threads per line (thread q = tid mod 16) and TY lines per block; MODE and DOT
+// as in k_fs_contig.  Threads q >= A transform zeros or a copy of element row A - 1 and write nothing.
+template <typename T, int L, int TY, int SIGN, int MODE, bool PRUNE, int DOT = 0>
+__global__ __launch_bounds__(TY * 16) void k_fs_contig3(cpx<T>* __restrict__ data, long long nlines, int D2,
+                                                         long long S1, long long S2, int n_in, int n_out,
+                                                         const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ u,
+                                                         cpx<T>* __restrict__ out, const cpx<T>* __restrict__ dot_a,
+                                                         double* __restrict__ dot_parts, long long dot_lines,
+                                                         int dot_nparts, int zbs, SlotMap sm, long long lpr) {
+    constexpr int B = 16, A = L / B;
+    static_assert(A * B == L && (A == 3 || A == 6 || A == 12), "lengths 48, 96, 192");
+    constexpr int LDP = TY + 1;
+    __shared__ cpx<T> lds[L * LDP];
+    __shared__ cpx<T> tws[L];
+    const int tid = threadIdx.x, q = tid % B, ln = tid / B;
+    stage_twiddles<T, L>(tws, tw, tid, TY * B);
+    const long long line = (long long)blockIdx.x * TY + ln;
+    const bool valid = line < nlines;
+    const long long orow = (MODE == 0 || !valid) ? 0 : slot_row(line, lpr, line_position<TY>(line, lpr), sm, D2, zbs);
+    const long long o1 = line / D2, o2 = line - o1 * D2;
+    cpx<T>* base = data + o1 * S1 + o2 * S2;
+    const bool s1 = q < A;
+    const int qa = s1 ? q : A - 1;
+    cpx<T> v[B];
+    if constexpr (MODE == 0) {
 #pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                double x = acc[k];
-                for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-                if (lane == 0) red[wave][k] = x;
-            }
-            __syncthreads();
-            if (tid < NS) {
-                double x = 0.0;
-                for (int w = 0; w < NW; ++w) x += red[w][tid];
-                const long long l0 = (long long)blockIdx.x * TY;
-                const long long rr = l0 / dot_lines, blk = (l0 - rr * dot_lines) / TY;
-                dot_parts[((long long)sm.slot[rr] * kRedSlots + tid) * dot_nparts + blk] = x;
+        for (int j = 0; j < B; ++j) {
+            const int e = q + A * j;
+            v[j] = (s1 && !(PRUNE && j >= B / 2) && valid && e < n_in) ? base[e] : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        reg_dft<SIGN, B, T, PRUNE>(v);
+#pragma unroll
+        for (int k2 = 1; k2 < B; ++k2) v[k2] = v[k2] * tw_at<SIGN>(tws, qa * k2);
+        if (s1) {
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) lds[(k2 * A + q) * LDP + ln] = v[k2];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) v[n1] = lds[(q * A + n1) * LDP + ln];
+        reg_dft3<SIGN, A, T>(v);
+        if (valid) {
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) {
+                const int k = q + B * k1;
+                if (k < n_out) base[k] = v[k1];
             }
         }
+    } else {
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            const int k = q + B * k1;
+            v[k1] = (valid && k < n_in) ? load_nt(&base[k]) : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        reg_dft3<SIGN, A, T>(v);
+#pragma unroll
+        for (int n1 = 1; n1 < A; ++n1) v[n1] = v[n1] * tw_at<SIGN>(tws, n1 * q);
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) lds[(n1 * B + q) * LDP + ln] = v[n1];
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) v[k2] = lds[(qa * B + k2) * LDP + ln];
+        reg_dft<SIGN, B, T>(v);
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (valid && s1) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                const int e = q + A * j;
+                if (!(PRUNE && j >= B / 2) && e < n_out) contig_out<T, MODE, DOT>(v[j], orow * n_out + e, u, out, dot_a, acc);
+            }
+        }
+        if constexpr (MODE == 1 && DOT != 0) contig_dot_parts<TY * B, TY, DOT>(acc, tid, dot_parts, dot_lines, dot_nparts, sm);
+    }
+}
+
+// Contiguous (x) pass at length 384 = 24 x 16: the paired asymmetric four-step of k_fs_strided3p along lines,
+// 32 threads per line (thread p = tid mod 32, partner p ^ 1 one lane away); MODE and DOT as in k_fs_contig.
+template <typename T, int TY, int SIGN, int MODE, bool PRUNE, int DOT = 0>
+__global__ __launch_bounds__(TY * 32) void k_fs_contig3p(cpx<T>* __restrict__ data, long long nlines, int D2,
+                                                          long long S1, long long S2, int n_in, int n_out,
+                                                          const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ u,
+                                                          cpx<T>* __restrict__ out, const cpx<T>* __restrict__ dot_a,
+                                                          double* __restrict__ dot_parts, long long dot_lines,
+                                                          int dot_nparts, int zbs, SlotMap sm, long long lpr) {
+    constexpr int L = 384, B = 16, A = 24, H = 12, NL = 32;
+    constexpr int LDP = TY + 1;
+    __shared__ cpx<T> lds[L * LDP];
+    __shared__ cpx<T> tws[L];
+    const int tid = threadIdx.x, q = tid % NL, ln = tid / NL;
+    stage_twiddles<T, L>(tws, tw, tid, TY * NL);
+    const long long line = (long long)blockIdx.x * TY + ln;
+    const bool valid = line < nlines;
+    const long long orow = (MODE == 0 || !valid) ? 0 : slot_row(line, lpr, line_position<TY>(line, lpr), sm, D2, zbs);
+    const long long o1 = line / D2, o2 = line - o1 * D2;
+    cpx<T>* base = data + o1 * S1 + o2 * S2;
+    const bool s1 = q < A;
+    const int qa = s1 ? q : A - 1;
+    const int k2 = q >> 1;
+    const bool h = q & 1;
+    cpx<T> v[B];
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const int e = q + A * j;
+            v[j] = (s1 && !(PRUNE && j >= B / 2) && valid && e < n_in) ? base[e] : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        reg_dft<SIGN, B, T, PRUNE>(v);
+#pragma unroll
+        for (int kk = 1; kk < B; ++kk) v[kk] = v[kk] * tw_at<SIGN>(tws, qa * kk);
+        if (s1) {
+#pragma unroll
+            for (int kk = 0; kk < B; ++kk) lds[(kk * A + q) * LDP + ln] = v[kk];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < H; ++m) v[m] = lds[(k2 * A + 2 * m + (int)h) * LDP + ln];
+        reg_dft3<SIGN, H, T>(v);
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            cpx<T> mine = v[i];
+            if (i > 0) mine = sel(h, mine * tw_at<SIGN>(tws, i * B), mine);
+            const cpx<T> other = lane_xor(mine, 1);
+            const cpx<T> x = sel(h, other - mine, mine + other);
+            const int k = k2 + B * (i + H * (int)h);
+            if (valid && k < n_out) base[k] = x;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const int k = k2 + B * (i + H * (int)h);
+            v[i] = (valid && k < n_in) ? load_nt(&base[k]) : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const cpx<T> mine = v[i];
+            const cpx<T> other = lane_xor(mine, 1);
+            const cpx<T> d = other - mine;
+            const cpx<T> dw = (i > 0) ? d * tw_at<SIGN>(tws, i * B) : d;
+            v[i] = sel(h, dw, mine + other);
+        }
+        reg_dft3<SIGN, H, T>(v);
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            const int n1 = 2 * m + (int)h;
+            lds[(n1 * B + k2) * LDP + ln] = v[m] * tw_at<SIGN>(tws, n1 * k2);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < B; ++kk) v[kk] = lds[(qa * B + kk) * LDP + ln];
+        reg_dft<SIGN, B, T>(v);
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (valid && s1) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                const int e = q + A * j;
+                if (!(PRUNE && j >= B / 2) && e < n_out) contig_out<T, MODE, DOT>(v[j], orow * n_out + e, u, out, dot_a, acc);
+            }
+        }
+        if constexpr (MODE == 1 && DOT != 0) contig_dot_parts<TY * NL, TY, DOT>(acc, tid, dot_parts, dot_lines, dot_nparts, sm);
     }
 }
 
@@ -806,6 +1134,23 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
     switch (L) {
 #define CASE(LL)                                                                                             \
     case LL: {                                                                                               \
+        if constexpr (LL == 48 || LL == 96 || LL == 192 || LL == 384) {                                      \
+            if (fs) {                                                                                        \
+                constexpr int TY = seg_cols<T>();                                                            \
+                const long long nb = (nlines + TY - 1) / TY;                                                 \
+                if constexpr (LL == 384)                                                                     \
+                    hipLaunchKernelGGL((k_fs_contig3p<T, TY, SIGN, MODE, PRUNE, DOT>), dim3((unsigned)nb),   \
+                                       dim3(TY * 32), 0, c->stream, data, nlines, D2, S1, S2, n_in, n_out,   \
+                                       tw, u, out, (const cpx<T>*)c->dot.a, c->dot.parts, c->dot.lines,      \
+                                       c->dot.nparts, zbs, sm, lpr);                                         \
+                else                                                                                         \
+                    hipLaunchKernelGGL((k_fs_contig3<T, LL, TY, SIGN, MODE, PRUNE, DOT>), dim3((unsigned)nb), \
+                                       dim3(TY * 16), 0, c->stream, data, nlines, D2, S1, S2, n_in, n_out,   \
+                                       tw, u, out, (const cpx<T>*)c->dot.a, c->dot.parts, c->dot.lines,      \
+                                       c->dot.nparts, zbs, sm, lpr);                                         \
+                break;                                                                                       \
+            }                                                                                                \
+        }                                                                                                    \
         if constexpr (fs_ok<T, LL>()) {                                                                      \
             if (fs) {                                                                                        \
                 constexpr int TY = seg_cols<T>();                                                            \
@@ -817,7 +1162,7 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
                 break;                                                                                       \
             }                                                                                                \
         }                                                                                                    \
-        if constexpr (DOT != 0) return fail(LS_ERR_STATE, "fused inner products need a power-of-two x length"); \
+        if constexpr (DOT != 0) return fail(LS_ERR_STATE, "fused inner products need a register x pass");     \
         constexpr int TY = contig_lines<T, LL>();                                                            \
         const long long nb = (nlines + TY - 1) / TY;                                                         \
         hipLaunchKernelGGL((k_fft_contig<T, LL, TY, SIGN, MODE>), dim3((unsigned)nb), dim3(kThreads), 0,     \
@@ -845,6 +1190,20 @@ int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long lon
     switch (L) {
 #define CASE(LL)                                                                                             \
     case LL: {                                                                                               \
+        if constexpr (LL == 48 || LL == 96 || LL == 192) {                                                   \
+            if (fs) {                                                                                        \
+                hipLaunchKernelGGL((k_fs_strided3<T, LL, TX, SIGN, PRUNE>), dim3(NX / TX, D2, D1),           \
+                                   dim3(TX * 16), 0, c->stream, data, S1, S2, ES, n_in, n_out, tw);          \
+                break;                                                                                       \
+            }                                                                                                \
+        }                                                                                                    \
+        if constexpr (LL == 384) {                                                                           \
+            if (fs) {                                                                                        \
+                hipLaunchKernelGGL((k_fs_strided3p<T, TX, SIGN, PRUNE>), dim3(NX / TX, D2, D1),              \
+                                   dim3(TX * 32), 0, c->stream, data, S1, S2, ES, n_in, n_out, tw);          \
+                break;                                                                                       \
+            }                                                                                                \
+        }                                                                                                    \
         if constexpr (fs_ok<T, LL>()) {                                                                      \
             if (fs) {                                                                                        \
                 hipLaunchKernelGGL((k_fs_strided<T, LL, TX, SIGN, PRUNE>), dim3(NX / TX, D2, D1),                    \
@@ -1140,7 +1499,10 @@ int fused_dot_blocks(const Ctx* c) {
     switch (c->L1) {
 #define CASE(LL)                                                         \
     case LL:                                                             \
-        if constexpr (fs_ok<T, LL>()) ok = fs_threads<T, LL>() % 64 == 0; \
+        if constexpr (LL == 48 || LL == 96 || LL == 192 || LL == 384)   \
+            ok = true;  /* 16 or 32 threads x 128-byte tiles */           \
+        else if constexpr (fs_ok<T, LL>())                                \
+            ok = fs_threads<T, LL>() % 64 == 0;                           \
         break;
         LS_FOR_LENGTHS(CASE)
 #undef CASE
