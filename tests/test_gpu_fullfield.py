@@ -80,3 +80,23 @@ def test_config3_full_field_six_rhs():
         e, e32 = rel(got[r], want), rel(got32[r], want)
         print("config3 128^3 rhs", r, "c128", e, "c64", e32, flush=True)
         assert e < 1e-10 and e32 < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(48, 24, 96), (192, 8, 8), (8, 8, 192)])
+@pytest.mark.parametrize("precision,tol,bar", [("c128", 1e-10, 2e-10), ("mixed", 1e-6, 1.1e-6)])
+def test_factor3_solves_certified_by_oracle(shape, precision, tol, bar):
+    """Solves on grids whose FFT lengths have a factor 3 (96, 48, 192; 384 along x, then along z), where the
+    Bi-CGSTAB inner products are summed in the x-inverse epilogue of the factor-3 register kernels: the
+    residual of each solution under the oracle's own operator (Eq 21, 22) meets the tolerance."""
+    m = models.random_medium(shape, seed=sum(shape) + 7, rel=0.1, aniso_background=True)
+    w = 2 * np.pi * 10.0
+    ctx = lsvie.context_from_model(m, omegas=[w], precision="mixed", max_rhs=2)
+    b = np.stack([models.random_field(shape, seed=s) for s in (11, 12)])
+    x, infos = ctx.solve(torch.from_numpy(b), tol=tol, maxit=2000, precision=precision)
+    x = x.cpu().numpy()
+    ctx.close()
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, w)
+    for r in range(2):
+        res = rel(P.apply_fft(x[r]), b[r])   # ||A x - b|| / ||b||
+        print(shape, precision, "rhs", r, "iters", infos[r]["iters"], "oracle residual", res, flush=True)
+        assert infos[r]["status"] == 0 and res < bar
