@@ -233,8 +233,9 @@ constexpr int seg_cols() {
     return 128 / (int)sizeof(cpx<T>);
 }
 
-// usable for powers of two whose transpose buffer stays within 64 KB (all but c128 at 512); lengths
-// with a factor 3 run the LDS Stockham kernels
+// usable for powers of two whose transpose buffer stays within 64 KB (all but c128 at 512); the lengths
+// with a factor 3 have register kernels of their own (k_fs_strided3, k_fs_contig3, k_fs_zgreen3 and the
+// paired forms at 384)
 template <typename T, int L>
 constexpr bool fs_ok() {
     return (L & (L - 1)) == 0 && L * seg_cols<T>() * (int)sizeof(cpx<T>) <= 65536;
