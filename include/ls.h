@@ -352,6 +352,13 @@ long long ls_device_bytes(const ls_ctx* ctx);
  * multiply, 3 y inverse, 4 x inverse).  Chosen by timing when built with LS_FLAG_AUTOTUNE. */
 int ls_kernel_variants(const ls_ctx* ctx, int* variants);
 
+/* Values per cell of the contrast the fused contrast kernel reads (Eq 8, 11-12): 9 when every cell's total
+ * contrast (input plus background fold, tapered) vanishes off the orthotropic pattern 11, 12, 13, 22, 23,
+ * 33, 44, 55, 66 (isotropic, VTI and orthorhombic media in the grid axes), 21 otherwise; decided at
+ * ls_setup and again by ls_set_contrast (LS_CONTRAST_K=21 in the environment keeps 21).  Returns 9 or 21,
+ * or LS_ERR_ARG for a null context. */
+int ls_contrast_format(const ls_ctx* ctx);
+
 /* Message of the last error on this host thread ("" if none). */
 const char* ls_last_error(void);
 

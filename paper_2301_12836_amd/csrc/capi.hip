@@ -1047,6 +1047,11 @@ int ls_profile_read(ls_ctx* c, char* names, int* counts, double* ms, long long* 
 
 long long ls_device_bytes(const ls_ctx* c) { return c ? c->bytes : 0; }
 
+int ls_contrast_format(const ls_ctx* c) {
+    if (!c) return fail(LS_ERR_ARG, "null context");
+    return c->contrast_k;
+}
+
 int ls_kernel_variants(const ls_ctx* c, int* variants) {
     if (!c || !variants) return fail(LS_ERR_ARG, "null argument");
     for (int p = 0; p < 2; ++p)

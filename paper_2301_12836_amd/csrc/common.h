@@ -191,6 +191,10 @@ struct Ctx {
     // values of the cells of one xy tile on one z plane are contiguous, so a block reads one run per plane
     double* dcp = nullptr;
     float* dcp32 = nullptr;
+    // values per cell in the packed copy: 9 when every cell's contrast has the orthotropic pattern (nonzero
+    // only at 11, 12, 13, 22, 23, 33, 44, 55, 66: isotropic, VTI and orthorhombic media in the grid axes),
+    // else 21
+    int contrast_k = 21;
 
     // k-space Green's tables per frequency: octant [L3/2+1][L2/2+1][L1/2+1][6] (half-space
     // [L3][L2][L1/2+1][6] when green_half), already scaled by 1/(L1 L2 L3) so the inverse FFT needs no

@@ -23,6 +23,11 @@ __host__ __device__ constexpr int packed(int I, int J) {
     return I <= J ? I * 6 - I * (I - 1) / 2 + (J - I) : J * 6 - J * (J - 1) / 2 + (I - J);
 }
 
+// packed indices of the nine entries of an orthotropic stiffness (11, 12, 13, 22, 23, 33, 44, 55, 66) and of the
+// twelve others, which vanish for isotropic, VTI and orthorhombic media in the grid axes
+constexpr int kOrtho9[9] = {0, 1, 2, 6, 7, 11, 15, 18, 20};
+constexpr int kOffOrtho[12] = {3, 4, 5, 8, 9, 10, 12, 13, 14, 16, 17, 19};
+
 // d/dx_a at index i of an axis with n cells (Eq 18): central inside, one-sided at the ends
 template <typename T>
 __device__ __forceinline__ cpx<T> deriv(const cpx<T>* __restrict__ f, long long p, long long stride, int i, int n,
@@ -208,7 +213,7 @@ __device__ __forceinline__ cpx<T> w3(const W3<T>& w, cpx<T> fm, cpx<T> f0, cpx<T
 // OUT 0: f into the padded work buffer; OUT 1: out = y - f (the transposed operator's epilogue).
 // Launch position rhs works on field slot sw.slot[rhs] of u (and y, out for OUT 1) at w^2 = sw.w2[rhs]; OUT 0
 // writes position rhs of the work buffer.
-template <typename T, int BX, int BY, int NT, int MINB, bool DB, int OUT>
+template <typename T, int BX, int BY, int NT, int MINB, bool DB, int OUT, int K>
 __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     const cpx<T>* __restrict__ u, const T* __restrict__ dcp, const T* __restrict__ drho, cpx<T>* __restrict__ out,
     const cpx<T>* __restrict__ y, SlotW2<T> sw, int nrhs, int N1, int N2, int N3, int L1, int L2, T inv_h, int tx,
@@ -257,12 +262,13 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     const W3<T> dxw = d_weights(gx, N1, inv_h), dyw = d_weights(gy, N2, inv_h);
     const W3<T> txw = dt_weights(gx, N1, inv_h), tyw = dt_weights(gy, N2, inv_h);
     const unsigned cell_xy = cell ? (unsigned)(gy * N1 + gx) : 0u;  // clamped: never used when !cell
-    // the cell's place in the tile-packed contrast (k_pack_contrast): its tile's run of 21 x BX x BY values
+    // the cell's place in the tile-packed contrast (k_pack_contrast): its tile's run of K x BX x BY values
     // on a z plane, then its position in the tile
+    static_assert(K == 21 || K == 9, "general or orthotropic contrast");
     constexpr int TILE = BX * BY;
     const int pgx = cell ? gx : 0, pgy = cell ? gy : 0;
-    const long long pplane = (long long)tx * ty * 21 * TILE;
-    const unsigned pxy = (unsigned)(((pgy / BY) * tx + pgx / BX) * 21 * TILE + (pgy % BY) * BX + pgx % BX);
+    const long long pplane = (long long)tx * ty * K * TILE;
+    const unsigned pxy = (unsigned)(((pgy / BY) * tx + pgx / BX) * K * TILE + (pgy % BY) * BX + pgx % BX);
 
     // plane loads: element e = t + m NT of the [3][UY][UX] box; its offset in plane 0 and validity
     unsigned ldoff[NLOAD];
@@ -308,10 +314,19 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     // this step; with DB, Cn is loaded for the next one at the top of the step, else C is reloaded
     // right after its tau plane (fewer registers)
     T C[21], Cn[DB ? 21 : 1];
+    // K = 9: the twelve entries off the orthotropic pattern are compile-time zeros, so their loads and products
+    // drop out (adding the exact zeros they would contribute leaves every sum bitwise unchanged)
     auto load_C = [&](T* dst, int q) __attribute__((always_inline)) {
         const T* base = dcp + (long long)min(max(q, 0), N3 - 1) * pplane + pxy;
+        if constexpr (K == 21) {
 #pragma unroll
-        for (int qq = 0; qq < 21; ++qq) dst[qq] = base[qq * TILE];
+            for (int qq = 0; qq < 21; ++qq) dst[qq] = base[qq * TILE];
+        } else {
+#pragma unroll
+            for (int qq = 0; qq < 12; ++qq) dst[kOffOrtho[qq]] = T(0);
+#pragma unroll
+            for (int qq = 0; qq < 9; ++qq) dst[kOrtho9[qq]] = base[qq * TILE];
+        }
     };
     // tau on plane q at this thread's cell, from u planes q-1, q, q+1: rows I of dC eps for which
     // the mask bit I is set
@@ -460,10 +475,11 @@ __global__ __launch_bounds__(NT, MINB) void k_contrast_zmarch(
     }
 }
 
-// Tile-packed contrast for k_contrast_zmarch with BX x BY tiles: value q of cell (x, y, z) goes to
-// ((z TY + y / BY) TX + x / BX) 21 BX BY + q BX BY + (y mod BY) BX + x mod BX (TX x TY tiles per plane; the
-// entries of cells outside the grid in edge tiles stay zero).
-template <typename T, int BX, int BY>
+// Tile-packed contrast for k_contrast_zmarch with BX x BY tiles: stored value q of cell (x, y, z) goes to
+// ((z TY + y / BY) TX + x / BX) K BX BY + q BX BY + (y mod BY) BX + x mod BX (TX x TY tiles per plane; the
+// entries of cells outside the grid in edge tiles stay zero).  K = 21 stores every packed entry, K = 9 the
+// orthotropic ones (kOrtho9).
+template <typename T, int BX, int BY, int K>
 __global__ void k_pack_contrast(const double* __restrict__ dc, T* __restrict__ dcp, int N1, int N2, int N3) {
     const long long n = (long long)N1 * N2 * N3;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -471,8 +487,19 @@ __global__ void k_pack_contrast(const double* __restrict__ dc, T* __restrict__ d
     const int x = (int)(p % N1), y = (int)((p / N1) % N2), z = (int)(p / ((long long)N1 * N2));
     const int TX = (N1 + BX - 1) / BX, TY = (N2 + BY - 1) / BY;
     constexpr int TILE = BX * BY;
-    const long long o = (((long long)z * TY + y / BY) * TX + x / BX) * 21 * TILE + (y % BY) * BX + x % BX;
-    for (int q = 0; q < 21; ++q) dcp[o + q * TILE] = (T)dc[q * n + p];
+    const long long o = (((long long)z * TY + y / BY) * TX + x / BX) * K * TILE + (y % BY) * BX + x % BX;
+    for (int q = 0; q < K; ++q) dcp[o + q * TILE] = (T)dc[(K == 21 ? q : kOrtho9[q]) * n + p];
+}
+
+// flag = 1 if any cell's contrast has a nonzero entry off the orthotropic pattern
+__global__ void k_off_ortho(const double* __restrict__ dc, long long n, int* __restrict__ flag) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    for (int q = 0; q < 12; ++q)
+        if (dc[kOffOrtho[q] * n + p] != 0.0) {
+            atomicOr(flag, 1);
+            return;
+        }
 }
 
 // compact field f[slot][c][n] -> zero-padded work buffer at position r (layout of zplane_offset; data cells only)
@@ -691,9 +718,33 @@ int pack_contrast(Ctx* c, T* dst) {
     using S = FusedShape<T>;
     LS_HIP(hipMemsetAsync(dst, 0, packed_elems<T>(c) * sizeof(T), c->stream));
     const long long n = c->ncell;
-    hipLaunchKernelGGL((k_pack_contrast<T, S::BX, S::BY>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
-                       c->dc, dst, c->n1, c->n2, c->n3);
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (c->contrast_k == 9)
+        hipLaunchKernelGGL((k_pack_contrast<T, S::BX, S::BY, 9>), g, dim3(256), 0, c->stream, c->dc, dst, c->n1, c->n2, c->n3);
+    else
+        hipLaunchKernelGGL((k_pack_contrast<T, S::BX, S::BY, 21>), g, dim3(256), 0, c->stream, c->dc, dst, c->n1, c->n2,
+                           c->n3);
     LS_HIP(hipGetLastError());
+    return LS_OK;
+}
+
+// values per cell of the packed contrast: 9 if the folded contrast has the orthotropic pattern at every cell,
+// else 21; LS_CONTRAST_K=21 in the environment keeps the general form (both are kept under test)
+int choose_contrast_k(Ctx* c) {
+    const char* e = std::getenv("LS_CONTRAST_K");
+    if (e && std::strcmp(e, "21") == 0) {
+        c->contrast_k = 21;
+        return LS_OK;
+    }
+    int* flag = (int*)c->stage;   // staging area of the context, free at set-up
+    LS_HIP(hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+    hipLaunchKernelGGL(k_off_ortho, dim3((unsigned)((c->ncell + 255) / 256)), dim3(256), 0, c->stream, c->dc, c->ncell,
+                       flag);
+    LS_HIP(hipGetLastError());
+    int h = 0;
+    LS_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    LS_HIP(hipStreamSynchronize(c->stream));
+    c->contrast_k = h ? 21 : 9;
     return LS_OK;
 }
 
@@ -718,9 +769,14 @@ int launch_fused(Ctx* c, const RhsSet& set, const cpx<T>* u, cpx<T>* out, const 
     const long long nb = cols * ((c->n3 + nzc - 1) / nzc);
     const unsigned nbl = (unsigned)((nb + 7) / 8 * 8);
     c->prof.begin(c->stream, OUT == 0 ? LS_PNAME(T, "contrast_fused") : LS_PNAME(T, "contrast_fused_T"), nrhs);
-    hipLaunchKernelGGL((k_contrast_zmarch<T, S::BX, S::BY, S::NT, S::PER_CU, S::DB, OUT>), dim3(nbl), dim3(S::NT), 0,
-                       c->stream, u, contrast_packed_of<T>(c), density_of<T>(c), out, y, slot_w2<T>(c, set), nrhs, c->n1,
-                       c->n2, c->n3, c->L1, c->L2, T(1.0 / c->h), tx, ty, nzc, nb, c->zbs);
+    if (c->contrast_k == 9)
+        hipLaunchKernelGGL((k_contrast_zmarch<T, S::BX, S::BY, S::NT, S::PER_CU, S::DB, OUT, 9>), dim3(nbl), dim3(S::NT), 0,
+                           c->stream, u, contrast_packed_of<T>(c), density_of<T>(c), out, y, slot_w2<T>(c, set), nrhs, c->n1,
+                           c->n2, c->n3, c->L1, c->L2, T(1.0 / c->h), tx, ty, nzc, nb, c->zbs);
+    else
+        hipLaunchKernelGGL((k_contrast_zmarch<T, S::BX, S::BY, S::NT, S::PER_CU, S::DB, OUT, 21>), dim3(nbl), dim3(S::NT), 0,
+                           c->stream, u, contrast_packed_of<T>(c), density_of<T>(c), out, y, slot_w2<T>(c, set), nrhs, c->n1,
+                           c->n2, c->n3, c->L1, c->L2, T(1.0 / c->h), tx, ty, nzc, nb, c->zbs);
     c->prof.end(c->stream);
     LS_HIP(hipGetLastError());
     return LS_OK;
@@ -846,7 +902,8 @@ int fold_background(Ctx* c, const double* dc_in, const double* drho_in, const do
     hipLaunchKernelGGL(k_fold, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, dc_in, drho_in, c->dc, c->drho,
                        c->dc32, c->drho32, c->n1, c->n2, c->n3, c->taper, dfold);
     LS_HIP(hipGetLastError());
-    int rc = pack_contrast<double>(c, c->dcp);
+    int rc = choose_contrast_k(c);
+    if (rc == LS_OK) rc = pack_contrast<double>(c, c->dcp);
     if (rc == LS_OK && c->dcp32) rc = pack_contrast<float>(c, c->dcp32);
     LS_HIP(hipStreamSynchronize(c->stream));
     LS_HIP(hipFreeAsync(dfold, c->stream));

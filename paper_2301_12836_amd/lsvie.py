@@ -47,7 +47,7 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_noalloc", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
             "ls_solve_moment", "ls_solve_multi", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_precond_blocks", "ls_apply_T", "ls_convolve",
             "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch", "ls_sample", "ls_synthesize", "ls_residual_history",
-            "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_last_error")
+            "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_contrast_format", "ls_last_error")
 
 
 class LsError(RuntimeError):
@@ -127,6 +127,7 @@ def load():
         "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, ctypes.POINTER(ctypes.c_longlong), I]),
         "ls_device_bytes": (ctypes.c_longlong, [P]),
         "ls_kernel_variants": (I, [P, ip]),
+        "ls_contrast_format": (I, [P]),
         "ls_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -382,6 +383,13 @@ def ls_profile_read(ctx, n_max=64):
     return out
 
 
+def ls_contrast_format(ctx):
+    k = load().ls_contrast_format(ctx)
+    if k < 0:
+        _check(k)
+    return k
+
+
 def ls_kernel_variants(ctx):
     v = (ctypes.c_int * 10)()
     _check(load().ls_kernel_variants(ctx, v))
@@ -632,6 +640,11 @@ class Context:
 
     def profile_read(self):
         return ls_profile_read(self.handle)
+
+    @property
+    def contrast_format(self):
+        """Values per cell of the packed contrast the fused kernel reads: 9 (orthotropic pattern) or 21."""
+        return ls_contrast_format(self.handle)
 
     @property
     def kernel_variants(self):
