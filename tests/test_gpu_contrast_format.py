@@ -60,3 +60,25 @@ def test_general_medium_keeps_21_values(monkeypatch):
     ctx = context(m, 2 * np.pi * 15.0, False, monkeypatch)
     assert ctx.contrast_format == 21
     ctx.close()
+
+
+def test_set_contrast_switches_format(monkeypatch):
+    """A context built on an isotropic medium (9 values per cell) given a general contrast by ls_set_contrast
+    switches to 21 and applies exactly the operator of a context built on that contrast; and back."""
+    m = models.config1(n=12)
+    w = m.omegas[0]
+    g = models.random_medium(m.shape, seed=8, rel=0.1)
+    ctx = context(m, w, False, monkeypatch)
+    assert ctx.contrast_format == 9
+    ctx.set_contrast(g.dc21, g.drho)
+    assert ctx.contrast_format == 21
+    fresh = lsvie.Context(m.shape, m.h, m.C0, m.rho0, g.dc21, g.drho, [w], precision="mixed", max_rhs=2)
+    u = torch.from_numpy(np.stack([models.random_field(m.shape, seed=s) for s in (1, 2)]))
+    for dt in (torch.complex128, torch.complex64):
+        assert torch.equal(ctx.apply(u.to(dt)), fresh.apply(u.to(dt)))
+    ctx.set_contrast(m.dc21, m.drho)
+    assert ctx.contrast_format == 9
+    back = context(m, w, False, monkeypatch)
+    assert torch.equal(ctx.apply(u), back.apply(u))
+    for c in (ctx, fresh, back):
+        c.close()
