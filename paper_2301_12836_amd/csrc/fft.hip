@@ -412,7 +412,7 @@ __global__ __launch_bounds__(TX * 32) void k_fs_strided3p(cpx<T>* __restrict__ d
         for (int i = 0; i < H; ++i) {
             cpx<T> mine = v[i];
             if (i > 0) mine = sel(h, mine * tw_at<SIGN>(tws, i * B), mine);
-            const cpx<T> other = lane_xor(mine, TX);
+            const cpx<T> other = lane_xor<TX>(mine);
             const cpx<T> x = sel(h, other - mine, mine + other);
             const int k = k2 + B * (i + H * (int)h);
             if (k < n_out) store_nt(&base[k * ES], x);
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(TX * 32) void k_fs_strided3p(cpx<T>* __restrict__ d
 #pragma unroll
         for (int i = 0; i < H; ++i) {
             const cpx<T> mine = v[i];
-            const cpx<T> other = lane_xor(mine, TX);
+            const cpx<T> other = lane_xor<TX>(mine);
             const cpx<T> d = other - mine;
             const cpx<T> dw = (i > 0) ? d * tw_at<SIGN>(tws, i * B) : d;
             v[i] = sel(h, dw, mine + other);
@@ -712,7 +712,7 @@ __global__ __launch_bounds__(TY * 32) void k_fs_contig3p(cpx<T>* __restrict__ da
         for (int i = 0; i < H; ++i) {
             cpx<T> mine = v[i];
             if (i > 0) mine = sel(h, mine * tw_at<SIGN>(tws, i * B), mine);
-            const cpx<T> other = lane_xor(mine, 1);
+            const cpx<T> other = lane_xor<1>(mine);
             const cpx<T> x = sel(h, other - mine, mine + other);
             const int k = k2 + B * (i + H * (int)h);
             if (valid && k < n_out) base[k] = x;
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(TY * 32) void k_fs_contig3p(cpx<T>* __restrict__ da
 #pragma unroll
         for (int i = 0; i < H; ++i) {
             const cpx<T> mine = v[i];
-            const cpx<T> other = lane_xor(mine, 1);
+            const cpx<T> other = lane_xor<1>(mine);
             const cpx<T> d = other - mine;
             const cpx<T> dw = (i > 0) ? d * tw_at<SIGN>(tws, i * B) : d;
             v[i] = sel(h, dw, mine + other);
@@ -1069,7 +1069,7 @@ __global__ __launch_bounds__(TX * 32, (sizeof(T) == 4 ? 2 : 1)) void k_fs_zgreen
         for (int i = 0; i < H; ++i) {
             cpx<T> mine = v[c][i];
             if (i > 0) mine = sel(h, mine * tw_at<-1>(tws, i * B), mine);
-            const cpx<T> other = lane_xor(mine, TX);
+            const cpx<T> other = lane_xor<TX>(mine);
             v[c][i] = sel(h, other - mine, mine + other);
         }
     }
@@ -1101,7 +1101,7 @@ __global__ __launch_bounds__(TX * 32, (sizeof(T) == 4 ? 2 : 1)) void k_fs_zgreen
 #pragma unroll
         for (int i = 0; i < H; ++i) {
             const cpx<T> mine = v[c][i];
-            const cpx<T> other = lane_xor(mine, TX);
+            const cpx<T> other = lane_xor<TX>(mine);
             const cpx<T> d = other - mine;
             const cpx<T> dw = (i > 0) ? d * tw_at<+1>(tws, i * B) : d;
             v[c][i] = sel(h, dw, mine + other);

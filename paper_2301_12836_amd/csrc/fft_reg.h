@@ -224,8 +224,42 @@ struct FourStepPair {
 };
 template <typename T>
 __device__ __forceinline__ cpx<T> sel(bool h, cpx<T> a, cpx<T> b) { return {h ? a.x : b.x, h ? a.y : b.y}; }
-template <typename T>
-__device__ __forceinline__ cpx<T> lane_xor(cpx<T> a, int mask) { return {__shfl_xor(a.x, mask), __shfl_xor(a.y, mask)}; }
+// The 32-bit value of lane (this lane XOR M) of the wavefront.  M = 1 and M = 8 stay inside a 16-lane row and
+// are a DPP modifier on a VALU move (quad_perm [1, 0, 3, 2]; row_ror:8, a rotation by half a row), instead of a
+// shuffle through the LDS crossbar (ds_bpermute): FP64 z pass 11.0 -> 8.8 ms at 384 and 21.2 -> 20.2 ms at 512
+// (6 right-hand sides).  Other M take the crossbar: for M = 16, gfx950's v_permlane16_swap with a select per
+// word measured slower in the FP32 z pass at 512 (9.9 -> 10.5 ms).  Lane layouts checked on the device.
+template <int M>
+__device__ __forceinline__ unsigned xor_lane_u32(unsigned x) {
+    if constexpr (M == 1)
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+    else if constexpr (M == 8)
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);
+    else
+        return (unsigned)__shfl_xor((int)x, M);
+}
+template <int M>
+__device__ __forceinline__ float xor_lane(float x) {
+    return __uint_as_float(xor_lane_u32<M>(__float_as_uint(x)));
+}
+template <int M>
+__device__ __forceinline__ double xor_lane(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = xor_lane_u32<M>((unsigned)b), hi = xor_lane_u32<M>((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// the value of lane (this lane XOR M); every lane of the wavefront must take part
+template <int M, typename T>
+__device__ __forceinline__ cpx<T> lane_xor(cpx<T> a) { return {xor_lane<M>(a.x), xor_lane<M>(a.y)}; }
+// the partner's value in the paired split of length L: the DPP exchange from length 384 up; at length 128
+// (FP64 at 64^3) the crossbar measured faster (0.216 against 0.225-0.232 ms)
+template <int M, int L, typename T>
+__device__ __forceinline__ cpx<T> pair_partner(cpx<T> a) {
+    if constexpr (L >= 384)
+        return lane_xor<M>(a);
+    else
+        return {__shfl_xor(a.x, M), __shfl_xor(a.y, M)};
+}
 template <typename T, int L, int TX, int SIGN, bool HALF = false>
 __device__ __forceinline__ void fsp_forward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int p) {
     using F = FourStepPair<L>;
@@ -246,7 +280,7 @@ __device__ __forceinline__ void fsp_forward(cpx<T>* v, cpx<T>* lds, const cpx<T>
     for (int i = 0; i < F::N2; ++i) {
         cpx<T> mine = v[i];
         if (i > 0) mine = sel(h, mine * tw_at<SIGN>(tw, i * F::N2), mine);
-        const cpx<T> other = lane_xor(mine, TX);
+        const cpx<T> other = pair_partner<TX, L>(mine);
         v[i] = sel(h, other - mine, mine + other);
     }
 }
@@ -258,7 +292,7 @@ __device__ __forceinline__ void fsp_backward(cpx<T>* v, cpx<T>* lds, const cpx<T
 #pragma unroll
     for (int i = 0; i < F::N2; ++i) {
         const cpx<T> mine = v[i];
-        const cpx<T> other = lane_xor(mine, TX);
+        const cpx<T> other = pair_partner<TX, L>(mine);
         const cpx<T> d = other - mine;
         const cpx<T> dw = (i > 0) ? d * tw_at<SIGN>(tw, i * F::N2) : d;
         v[i] = sel(h, dw, mine + other);
