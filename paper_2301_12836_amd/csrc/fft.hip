@@ -552,17 +552,29 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
             const int k = spectral_index<L>(q, i);
             v[i] = (valid && k < n_in) ? load_nt(&base[k]) : cpx<T>{T(0), T(0)};
         }
-        // the epilogue's u (and r^ for DOT 1) requested before the transform
+        // the epilogue's u requested before the transform; r^ for DOT 1 as well in FP64, after it in FP32
+        // (there the late loads took the 6-RHS launch at 128^3 from 0.313 to 0.296 ms, and in FP64 the early
+        // ones measured 0.462 against 0.469 ms)
+        constexpr bool late_a = sizeof(T) == 4;
         cpx<T> up[F::N2], ap[F::N2];
+        auto load_a = [&]() __attribute__((always_inline)) {
+#pragma unroll
+            for (int j = 0; j < F::N2; ++j) {
+                const int e = q + F::N1 * j;
+                const bool ok = MODE == 1 && DOT == 1 && valid && !half_slot<L, PRUNE>(j) && e < n_out;
+                ap[j] = ok ? load_nt(&dot_a[orow * n_out + e]) : cpx<T>{T(0), T(0)};
+            }
+        };
 #pragma unroll
         for (int j = 0; j < F::N2; ++j) {
             const int e = q + F::N1 * j;
             const bool ok = MODE == 1 && valid && !half_slot<L, PRUNE>(j) && e < n_out;
             up[j] = ok ? load_nt(&u[orow * n_out + e]) : cpx<T>{T(0), T(0)};
-            ap[j] = (ok && DOT == 1) ? load_nt(&dot_a[orow * n_out + e]) : cpx<T>{T(0), T(0)};
         }
+        if constexpr (!late_a) load_a();
         __syncthreads();
         fs_backward<T, L, LDP, SIGN>(v, lds, tws, ln, q);
+        if constexpr (late_a) load_a();
         double acc[3] = {0.0, 0.0, 0.0};
         if (valid) {
 #pragma unroll
