@@ -2,7 +2,8 @@
 384 (config 5's 192^3 grid) on each axis in turn, and 256 with six right-hand sides in one launch (the
 benchmark's 128^3 configuration).  Every output value of the HIP path is compared with the oracle's
 zero-padded FFT apply (Eq 21) of the same seeded inputs: relative L2 1e-10 for the FP64 operator, 1e-5
-for the FP32 one."""
+for the FP32 one.  The transposed operator and the Green's convolution alone get the same full-field check
+at 192, 384 and 256, and solves at the factor-3 lengths are certified by the oracle's residual."""
 
 import numpy as np
 import pytest
@@ -100,3 +101,33 @@ def test_factor3_solves_certified_by_oracle(shape, precision, tol, bar):
         res = rel(P.apply_fft(x[r]), b[r])   # ||A x - b|| / ||b||
         print(shape, precision, "rhs", r, "iters", infos[r]["iters"], "oracle residual", res, flush=True)
         assert infos[r]["status"] == 0 and res < bar
+
+
+@pytest.mark.parametrize("which", ["config4_96", "z384", "config3_128"])
+def test_transposed_and_convolution_full_field(which):
+    """The transposed operator A^T y = y - B (G * y) that the adjoint solves iterate on (Eq 21 transposed),
+    and the Green's convolution G * y alone, over every cell: at FFT length 192 (config 4's 96^3 grid, its
+    highest frequency), 384 along z, and 256 with two right-hand sides per launch (the benchmark's 128^3
+    model at 40 Hz).  Relative L2 1e-10 against the oracle's zero-padded FFT forms."""
+    from oracle import adjoint as oadj
+    if which == "config4_96":
+        m = models.config4()
+    elif which == "z384":
+        m = models.random_medium((8, 8, 192), seed=201, rel=0.1, aniso_background=True)
+    else:
+        m = models.config3()
+    w = m.omegas[-1] if which != "z384" else 2 * np.pi * 20.0
+    ctx = lsvie.context_from_model(m, omegas=[w], precision="mixed", max_rhs=2)
+    y = np.stack([models.random_field(m.shape, seed=s) for s in (31, 32)])
+    yt = torch.from_numpy(y)
+    got_T = ctx.apply_T(yt).cpu().numpy()
+    got_c = ctx.convolve(yt).cpu().numpy()
+    ctx.close()
+    print(which, "device done; oracle", flush=True)
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, w)
+    tab = P.table()
+    for r in range(2):
+        eT = rel(got_T[r], oadj.apply_T(P, y[r]))
+        ec = rel(got_c[r], op.convolve_fft(y[r], tab))
+        print(which, "rhs", r, "A^T", eT, "G*y", ec, flush=True)
+        assert eT < 1e-10 and ec < 1e-10
