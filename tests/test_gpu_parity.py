@@ -231,6 +231,12 @@ def test_error_paths_on_gpu():
     with pytest.raises(ValueError):
         ctx.rhs_moment(models.EXPLOSION, (3, 3, 3), out=torch.empty((1, 1), dtype=torch.complex128,
                                                                     device=ctx.device))
+    # an empty batch and one beyond max_rhs (1 here) are refused by the library: n_rhs outside [1, max_rhs]
+    for nr in (0, 2):
+        for call in (ctx.apply, ctx.solve):
+            with pytest.raises(lsvie.LsError) as e:
+                call(torch.zeros((nr,) + tuple(b.shape), dtype=torch.complex128, device=ctx.device))
+            assert e.value.code == lsvie.LS_ERR_ARG
     # zero right-hand side: immediate u = 0
     x, infos = ctx.solve(torch.zeros_like(b), tol=1e-8)
     assert float(torch.abs(x).max()) == 0.0 and infos[0]["iters"] == 0
