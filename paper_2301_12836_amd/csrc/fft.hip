@@ -501,6 +501,12 @@ __device__ __forceinline__ void contig_dot_parts(const double acc[3], int tid, d
     }
 }
 
+// The x passes' transposes take the bank-swizzled LDS slots (fs_slot) in FP32: 6-RHS launches at 128^3 x
+// forward 0.184 -> 0.143 ms, x inverse 0.213 -> 0.205 ms; in FP64 they measured no faster (0.353 against 0.356
+// ms at 128^3), so FP64 keeps the padded layout.
+template <typename T, int L, int LDP>
+constexpr bool kSwzX = sizeof(T) == 4 && (L == 128 || L == 256 || L == 512) && (LDP - 1) * FourStep<L>::N1 <= L;
+
 // Contiguous (x) pass over TY lines per block.  MODE 0: forward in place; MODE 1: inverse with
 // out = u - v (compact); MODE 2: inverse with out = v (compact).
 // DOT (MODE 1 only): inner products of the written field, fused for the Bi-CGSTAB iteration that
@@ -538,7 +544,7 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
             v[j] = (!half_slot<L, PRUNE>(j) && valid && e < n_in) ? base[e] : cpx<T>{T(0), T(0)};
         }
         __syncthreads();
-        fs_forward<T, L, LDP, SIGN>(v, lds, tws, ln, q);
+        fs_forward<T, L, LDP, SIGN, false, kSwzX<T, L, LDP>>(v, lds, tws, ln, q);
         if (valid) {
 #pragma unroll
             for (int i = 0; i < F::N2; ++i) {
@@ -573,7 +579,7 @@ __global__ __launch_bounds__(TY * FourStep<L>::N1) void k_fs_contig(cpx<T>* __re
         }
         if constexpr (!late_a) load_a();
         __syncthreads();
-        fs_backward<T, L, LDP, SIGN>(v, lds, tws, ln, q);
+        fs_backward<T, L, LDP, SIGN, kSwzX<T, L, LDP>>(v, lds, tws, ln, q);
         if constexpr (late_a) load_a();
         double acc[3] = {0.0, 0.0, 0.0};
         if (valid) {

@@ -159,28 +159,47 @@ __device__ __forceinline__ cpx<T> tw_at(const cpx<T>* __restrict__ tw, int m) {
     return w;
 }
 
+// LDS slot of row r (the four-step index) of line or column t.  Plain: r TX + t, for kernels whose lanes run
+// over t (columns).  SWZ, for kernels whose lanes run over the N1 threads q of a line (64 / N1 lines per
+// wavefront): each line's L rows contiguous after a skew of N1 slots per line, with the low log2 N1 bits of the
+// row XORed with the next log2 N1, so that the rows one access touches (r = N1 k2 + q when the forward writes,
+// r = N1 (q + N1 s) + n1 when it reads, and the inverse's reverse steps) fall in distinct banks (at most two
+// to a bank in the inverse's read at lengths 128 and 512).  With the plain padded layout the x passes took 24
+// bank-conflict cycles per LDS instruction in FP32 and 10.5 in FP64 at length 256 (SQ_LDS_BANK_CONFLICT).  It
+// uses (TX - 1)(L + N1) slots for TX - 1 lines: within the L TX the kernels allocate when (TX - 1) N1 <= L.
+template <int L, int TX, bool SWZ>
+__device__ __forceinline__ int fs_slot(int r, int t) {
+    if constexpr (SWZ) {
+        constexpr int N1 = FourStep<L>::N1, S = N1 == 16 ? 4 : N1 == 8 ? 3 : 2;
+        static_assert((1 << S) == N1, "power-of-two split");
+        return t * (L + N1) + (r & ~(N1 - 1)) + ((r & (N1 - 1)) ^ ((r >> S) & (N1 - 1)));
+    } else {
+        return r * TX + t;
+    }
+}
+
 // natural -> spectral, one line per column.  lds: L * TX values, free on entry; free on exit.  HALF:
-// the upper half of the line (slots j >= N2/2 of every thread) is zero and is not read.
-template <typename T, int L, int TX, int SIGN, bool HALF = false>
+// the upper half of the line (slots j >= N2/2 of every thread) is zero and is not read.  SWZ: fs_slot.
+template <typename T, int L, int TX, int SIGN, bool HALF = false, bool SWZ = false>
 __device__ __forceinline__ void fs_forward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int q) {
     using F = FourStep<L>;
     reg_dft<SIGN, F::N2, T, HALF>(v);
 #pragma unroll
     for (int k2 = 1; k2 < F::N2; ++k2) v[k2] = v[k2] * tw_at<SIGN>(tw, q * k2);
 #pragma unroll
-    for (int k2 = 0; k2 < F::N2; ++k2) lds[(k2 * F::N1 + q) * TX + t] = v[k2];
+    for (int k2 = 0; k2 < F::N2; ++k2) lds[fs_slot<L, TX, SWZ>(k2 * F::N1 + q, t)] = v[k2];
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < F::M; ++s)
 #pragma unroll
-        for (int n1 = 0; n1 < F::N1; ++n1) v[s * F::N1 + n1] = lds[((q + F::N1 * s) * F::N1 + n1) * TX + t];
+        for (int n1 = 0; n1 < F::N1; ++n1) v[s * F::N1 + n1] = lds[fs_slot<L, TX, SWZ>((q + F::N1 * s) * F::N1 + n1, t)];
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < F::M; ++s) reg_dft<SIGN, F::N1, T>(v + s * F::N1);
 }
 
 // spectral -> natural (the reverse steps), same LDS contract.
-template <typename T, int L, int TX, int SIGN>
+template <typename T, int L, int TX, int SIGN, bool SWZ = false>
 __device__ __forceinline__ void fs_backward(cpx<T>* v, cpx<T>* lds, const cpx<T>* __restrict__ tw, int t, int q) {
     using F = FourStep<L>;
 #pragma unroll
@@ -193,10 +212,10 @@ __device__ __forceinline__ void fs_backward(cpx<T>* v, cpx<T>* lds, const cpx<T>
 #pragma unroll
     for (int s = 0; s < F::M; ++s)
 #pragma unroll
-        for (int n1 = 0; n1 < F::N1; ++n1) lds[(n1 * F::N2 + q + F::N1 * s) * TX + t] = v[s * F::N1 + n1];
+        for (int n1 = 0; n1 < F::N1; ++n1) lds[fs_slot<L, TX, SWZ>(n1 * F::N2 + q + F::N1 * s, t)] = v[s * F::N1 + n1];
     __syncthreads();
 #pragma unroll
-    for (int k2 = 0; k2 < F::N2; ++k2) v[k2] = lds[(q * F::N2 + k2) * TX + t];
+    for (int k2 = 0; k2 < F::N2; ++k2) v[k2] = lds[fs_slot<L, TX, SWZ>(q * F::N2 + k2, t)];
     __syncthreads();
     reg_dft<SIGN, F::N2, T>(v);
 }
