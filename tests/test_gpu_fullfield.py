@@ -61,13 +61,15 @@ def test_length_384_each_axis_full_field(shape):
     ctx.close()
 
 
-def test_config3_full_field_six_rhs():
-    """The benchmark's operator: 128^3 TTI random medium at 40 Hz, six right-hand sides per launch, every
-    cell of every right-hand side, FP64 and FP32."""
+@pytest.mark.parametrize("nrhs", [6, 5])
+def test_config3_full_field_six_rhs(nrhs):
+    """The benchmark's operator: 128^3 TTI random medium at 40 Hz, six right-hand sides per launch (and five,
+    where the x and y passes run in cache-sized chunks of 2, 2 and 1 right-hand sides in FP32), every cell of
+    every right-hand side, FP64 and FP32."""
     m = models.config3()
     w = m.omegas[-1]
     ctx = lsvie.context_from_model(m, omegas=[w], precision="mixed", max_rhs=6)
-    u = np.stack([models.random_field(m.shape, seed=40 + s) for s in range(6)])
+    u = np.stack([models.random_field(m.shape, seed=40 + s) for s in range(nrhs)])
     ut = torch.from_numpy(u)
     got = ctx.apply(ut).cpu().numpy()
     got32 = ctx.apply(ut.to(torch.complex64)).cpu().numpy()
@@ -76,10 +78,10 @@ def test_config3_full_field_six_rhs():
     print("config3: device applies done; oracle table", flush=True)
     P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, w)
     P.table()
-    for r in range(6):
+    for r in range(nrhs):
         want = P.apply_fft(u[r])
         e, e32 = rel(got[r], want), rel(got32[r], want)
-        print("config3 128^3 rhs", r, "c128", e, "c64", e32, flush=True)
+        print("config3 128^3 rhs", r, "of", nrhs, "c128", e, "c64", e32, flush=True)
         assert e < 1e-10 and e32 < 1e-5
 
 
@@ -131,3 +133,24 @@ def test_transposed_and_convolution_full_field(which):
         ec = rel(got_c[r], op.convolve_fft(y[r], tab))
         print(which, "rhs", r, "A^T", eT, "G*y", ec, flush=True)
         assert eT < 1e-10 and ec < 1e-10
+
+
+@pytest.mark.parametrize("precision,tol,bar", [("c128", 1e-8, 2e-8), ("mixed", 1e-6, 1.1e-6)])
+def test_config3_solve_in_cache_sized_chunks(precision, tol, bar):
+    """Solves of five systems on the benchmark's 128^3 model (10 Hz), where every operator call runs its x and
+    y passes in cache-sized chunks of right-hand sides and the Bi-CGSTAB inner products are summed in the
+    chunks' x-inverse epilogues: the residual of each solution under the oracle's own operator (Eq 21, 22)
+    meets the tolerance."""
+    m = models.config3()
+    w = m.omegas[1]
+    ctx = lsvie.context_from_model(m, omegas=[w], precision="mixed", max_rhs=5)
+    b = torch.stack([ctx.rhs_moment(M, src) for M, src in m.sources[:5]])
+    x, infos = ctx.solve(b, tol=tol, maxit=500, precision=precision)
+    x, b = x.cpu().numpy(), b.cpu().numpy()
+    ctx.close()
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, w)
+    P.table()
+    for r in range(5):
+        res = rel(P.apply_fft(x[r]), b[r])
+        print("config3 10 Hz", precision, "rhs", r, "iters", infos[r]["iters"], "oracle residual", res, flush=True)
+        assert infos[r]["status"] == 0 and res < bar
