@@ -1226,6 +1226,15 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
     return LS_OK;
 }
 
+// FP32 strided passes at the powers of two from 64 to 256 take 32-column tiles (256-byte segments, 512 threads,
+// the same 16 values per thread) where the x length allows: a plain copy with that access pattern moves 5.62
+// TB/s against 5.23 with 16 columns, and the y passes of 6-RHS applies measured 0.099 -> 0.097 ms (forward) and
+// 0.113 -> 0.108 ms (inverse) per chunk of 2 right-hand sides at 128^3, 0.047 -> 0.044 ms (inverse) at 64^3.
+template <typename T, int L>
+constexpr bool strided_wide() {
+    return sizeof(T) == 4 && L >= 64 && L <= 256 && (L & (L - 1)) == 0;
+}
+
 template <typename T, int SIGN, bool PRUNE>
 int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long long S1, long long S2, long long ES,
                    int n_in, int n_out, const cpx<T>* tw, const char* name, int variant = 0, int nrhs = 0) {
@@ -1248,6 +1257,14 @@ int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long lon
             if (fs) {                                                                                        \
                 hipLaunchKernelGGL((k_fs_strided3p<T, TX, SIGN, PRUNE>), dim3(NX / TX, D2, D1),              \
                                    dim3(TX * 32), 0, c->stream, data, S1, S2, ES, n_in, n_out, tw);          \
+                break;                                                                                       \
+            }                                                                                                \
+        }                                                                                                    \
+        if constexpr (strided_wide<T, LL>()) {                                                               \
+            if (fs && NX % (2 * TX) == 0) {                                                                  \
+                hipLaunchKernelGGL((k_fs_strided<T, LL, 2 * TX, SIGN, PRUNE>), dim3(NX / (2 * TX), D2, D1),        \
+                                   dim3(2 * fs_threads<T, LL>()), 0, c->stream, data, S1, S2, ES, n_in, n_out,   \
+                                   tw);                                                                      \
                 break;                                                                                       \
             }                                                                                                \
         }                                                                                                    \
