@@ -1226,18 +1226,20 @@ int launch_contig(Ctx* c, int L, cpx<T>* data, long long nlines, int D2, long lo
     return LS_OK;
 }
 
-// FP32 strided passes at the powers of two from 64 to 256 take 32-column tiles (256-byte segments, 512 threads,
-// the same 16 values per thread) where the x length allows: a plain copy with that access pattern moves 5.62
-// TB/s against 5.23 with 16 columns, and the y passes of 6-RHS applies measured 0.099 -> 0.097 ms (forward) and
-// 0.113 -> 0.108 ms (inverse) per chunk of 2 right-hand sides at 128^3, 0.047 -> 0.044 ms (inverse) at 64^3.
+// Strided passes at the powers of two from 64 to 256 and at 48, 96 and 192 take tiles of twice the columns (256-byte
+// segments, twice the threads, the same 16 values per thread) where the x length allows: a plain copy with that
+// access pattern moves 5.62 TB/s against 5.23 with 128-byte segments.  Measured on 6-RHS applies: FP32 y passes
+// per chunk of 2 right-hand sides at 128^3 0.099 -> 0.097 ms (forward) and 0.113 -> 0.108 ms (inverse), y
+// inverse at 64^3 0.047 -> 0.044 ms and at 96^3 0.128 -> 0.123 ms; FP64 per right-hand side at 128^3 0.111 ->
+// 0.102 and 0.111 -> 0.103 ms, y inverse at 64^3 0.086 -> 0.077 ms and at 96^3 0.141 -> 0.126 ms.
 template <typename T, int L>
 constexpr bool strided_wide() {
-    return sizeof(T) == 4 && L >= 64 && L <= 256 && (L & (L - 1)) == 0;
+    return L >= 64 && L <= 256 && (L & (L - 1)) == 0;
 }
-// the factor-3 kernel (k_fs_strided3) takes them at 48, 96 and 192: y inverse at 96^3 0.128 -> 0.123 ms
+// the factor-3 kernel (k_fs_strided3)
 template <typename T, int L>
 constexpr bool strided3_wide() {
-    return sizeof(T) == 4 && (L == 48 || L == 96 || L == 192);
+    return L == 48 || L == 96 || L == 192;
 }
 
 template <typename T, int SIGN, bool PRUNE>
