@@ -352,6 +352,13 @@ long long ls_device_bytes(const ls_ctx* ctx);
  * multiply, 3 y inverse, 4 x inverse).  Chosen by timing when built with LS_FLAG_AUTOTUNE. */
 int ls_kernel_variants(const ls_ctx* ctx, int* variants);
 
+/* The apply schedule: schedule[p] the right-hand sides per chunk of the x and y passes for precision p (0 c128,
+ * 1 c64) at max_rhs right-hand sides (the x and y passes of an operator call run chunk by chunk so that each
+ * pass's output is still in the memory-side cache when the next pass reads it), schedule[2 + p] 1 when the
+ * strided passes take 256-byte column tiles where the x length allows, 0 for 128-byte ones.  Chosen by timing
+ * when built with LS_FLAG_AUTOTUNE, else by the cache size.  schedule: host int [4]. */
+int ls_kernel_schedule(const ls_ctx* ctx, int* schedule);
+
 /* Values per cell of the contrast the fused contrast kernel reads (Eq 8, 11-12): 9 when every cell's total
  * contrast (input plus background fold, tapered) vanishes off the orthotropic pattern 11, 12, 13, 22, 23,
  * 33, 44, 55, 66 (isotropic, VTI and orthorhombic media in the grid axes), 21 otherwise; decided at

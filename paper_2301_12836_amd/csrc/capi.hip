@@ -249,9 +249,11 @@ int check_solve_buffers(const ls_ctx* c, const void* b, const void* x0, const vo
 }
 
 // ------------------------------------------------------------------------------------------
-// autotuner cache: one line per tuned configuration, "key v0 .. v9" (the FFT variant of every pass and
-// precision), in the file LS_AUTOTUNE_CACHE names, else $HOME/.cache/lsvie/autotune.txt.  A missing or
-// unreadable cache only means tuning again; a later line for the same key wins.
+// autotuner cache: one line per tuned configuration, "key v0 .. v9 c0 c1 w0 w1" (the FFT variant of every pass
+// and precision, then per precision the right-hand sides per chunk of the x and y passes and the strided
+// passes' tile choice), in the file LS_AUTOTUNE_CACHE names, else $HOME/.cache/lsvie/autotune.txt.  A missing
+// or unreadable cache only means tuning again; a later line for the same key wins; lines of other formats
+// (an older key version) are skipped.
 
 std::string autotune_path() {
     if (const char* e = std::getenv("LS_AUTOTUNE_CACHE")) return e;
@@ -267,7 +269,7 @@ std::string autotune_key(const Ctx* c) {
     (void)hipGetLastError();
     for (char& ch : arch)
         if (ch == ' ' || ch == ':') ch = '_';
-    return "v1:" + arch + ":cu" + std::to_string(c->num_cu) + ":n" + std::to_string(c->n1) + "x" + std::to_string(c->n2) +
+    return "v2:" + arch + ":cu" + std::to_string(c->num_cu) + ":n" + std::to_string(c->n1) + "x" + std::to_string(c->n2) +
            "x" + std::to_string(c->n3) + ":L" + std::to_string(c->L1) + "x" + std::to_string(c->L2) + "x" +
            std::to_string(c->L3) + ":r" + std::to_string(c->max_rhs) + ":z" + std::to_string(c->zbs) + ":h" +
            std::to_string((int)c->green_half) + ":m" + std::to_string(c->mixed);
@@ -278,25 +280,31 @@ bool autotune_lookup(const std::string& key, Ctx* c) {
     if (!f) return false;
     char line[512];
     bool found = false;
-    int v[10];
+    int v[14];
     while (std::fgets(line, sizeof line, f)) {
         char k[400];
-        int w[10];
-        if (std::sscanf(line, "%399s %d %d %d %d %d %d %d %d %d %d", k, &w[0], &w[1], &w[2], &w[3], &w[4], &w[5], &w[6],
-                        &w[7], &w[8], &w[9]) != 11 ||
+        int w[14];
+        if (std::sscanf(line, "%399s %d %d %d %d %d %d %d %d %d %d %d %d %d %d", k, &w[0], &w[1], &w[2], &w[3], &w[4],
+                        &w[5], &w[6], &w[7], &w[8], &w[9], &w[10], &w[11], &w[12], &w[13]) != 15 ||
             key != k)
             continue;
         bool ok = true;
         for (int q = 0; q < 10; ++q) ok = ok && (w[q] == 0 || w[q] == 1);
+        for (int q = 10; q < 12; ++q) ok = ok && w[q] >= 1 && w[q] <= c->max_rhs;
+        for (int q = 12; q < 14; ++q) ok = ok && (w[q] == 0 || w[q] == 1);
         if (ok) {
-            std::copy(w, w + 10, v);
+            std::copy(w, w + 14, v);
             found = true;
         }
     }
     std::fclose(f);
-    if (found)
-        for (int p = 0; p < 2; ++p)
+    if (found) {
+        for (int p = 0; p < 2; ++p) {
             for (int q = 0; q < 5; ++q) c->variant[p][q] = v[5 * p + q];
+            c->xy_chunk[p] = v[10 + p];
+            c->y_wide[p] = v[12 + p];
+        }
+    }
     return found;
 }
 
@@ -312,6 +320,11 @@ void autotune_store(const std::string& key, const Ctx* c) {
     std::fprintf(f, "%s", key.c_str());
     for (int p = 0; p < 2; ++p)
         for (int q = 0; q < 5; ++q) std::fprintf(f, " %d", c->variant[p][q]);
+    // a precision that was not tuned (c64 of an FP64-only context) stores the rule's choice of its chunk
+    for (int p = 0; p < 2; ++p)
+        std::fprintf(f, " %d", c->xy_chunk[p] > 0 ? c->xy_chunk[p]
+                                                  : (p == 0 ? xy_chunk_rule<double>(c, c->max_rhs) : xy_chunk_rule<float>(c, c->max_rhs)));
+    for (int p = 0; p < 2; ++p) std::fprintf(f, " %d", c->y_wide[p]);
     std::fprintf(f, "\n");
     std::fclose(f);
 }
@@ -1056,6 +1069,16 @@ int ls_kernel_variants(const ls_ctx* c, int* variants) {
     if (!c || !variants) return fail(LS_ERR_ARG, "null argument");
     for (int p = 0; p < 2; ++p)
         for (int q = 0; q < 5; ++q) variants[p * 5 + q] = c->variant[p][q];
+    return LS_OK;
+}
+
+int ls_kernel_schedule(const ls_ctx* c, int* schedule) {
+    if (!c || !schedule) return fail(LS_ERR_ARG, "null argument");
+    for (int p = 0; p < 2; ++p) {
+        schedule[p] = c->xy_chunk[p] > 0 ? std::min(c->xy_chunk[p], c->max_rhs)
+                                         : (p == 0 ? xy_chunk_rule<double>(c, c->max_rhs) : xy_chunk_rule<float>(c, c->max_rhs));
+        schedule[2 + p] = c->y_wide[p];
+    }
     return LS_OK;
 }
 

@@ -181,6 +181,10 @@ struct Ctx {
     // FFT kernel variant per pass and precision: 0 register four-step, 1 LDS Stockham
     // passes: 0 x forward, 1 y forward, 2 z with Green multiply, 3 y inverse, 4 x inverse
     int variant[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+    // per precision (0 c128, 1 c64): right-hand sides per chunk of the x and y passes (0: the cache-size rule),
+    // and whether the strided passes take 256-byte column tiles where the x length allows (1) or 128-byte ones
+    int xy_chunk[2] = {0, 0};
+    int y_wide[2] = {1, 1};
 
     // medium (folded contrast), FP64 and (mixed) FP32
     double* dc = nullptr;     // [21][ncell]
@@ -272,6 +276,9 @@ template <typename T>
 int fft_full_3d_forward(Ctx* c, cpx<T>* buf);
 template <typename T>
 int fused_dot_blocks(const Ctx* c);  // epilogue blocks per right-hand side if the dots can be fused, else 0
+// right-hand sides per chunk of the x and y passes by the memory-side cache size (used when Ctx::xy_chunk is 0)
+template <typename T>
+int xy_chunk_rule(const Ctx* c, int nrhs);
 template <typename T>
 int autotune_passes(Ctx* c);
 int supported_fft_length(int n);

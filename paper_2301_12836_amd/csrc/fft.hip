@@ -1250,11 +1250,12 @@ int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long lon
     if (NX % TX) return fail(LS_ERR_ARG, "x length not a multiple of the column tile");
     c->prof.begin(c->stream, name, nrhs);
     const bool fs = variant == 0 && use_fourstep();
+    const bool wide = c->y_wide[sizeof(T) == 8 ? 0 : 1] != 0;
     switch (L) {
 #define CASE(LL)                                                                                             \
     case LL: {                                                                                               \
         if constexpr (strided3_wide<T, LL>()) {                                                              \
-            if (fs && NX % (2 * TX) == 0) {                                                                  \
+            if (fs && wide && NX % (2 * TX) == 0) {                                                          \
                 hipLaunchKernelGGL((k_fs_strided3<T, LL, 2 * TX, SIGN, PRUNE>), dim3(NX / (2 * TX), D2, D1),       \
                                    dim3(2 * TX * 16), 0, c->stream, data, S1, S2, ES, n_in, n_out, tw);      \
                 break;                                                                                       \
@@ -1275,7 +1276,7 @@ int launch_strided(Ctx* c, int L, cpx<T>* data, int NX, int D2, int D1, long lon
             }                                                                                                \
         }                                                                                                    \
         if constexpr (strided_wide<T, LL>()) {                                                               \
-            if (fs && NX % (2 * TX) == 0) {                                                                  \
+            if (fs && wide && NX % (2 * TX) == 0) {                                                          \
                 hipLaunchKernelGGL((k_fs_strided<T, LL, 2 * TX, SIGN, PRUNE>), dim3(NX / (2 * TX), D2, D1),        \
                                    dim3(2 * fs_threads<T, LL>()), 0, c->stream, data, S1, S2, ES, n_in, n_out,   \
                                    tw);                                                                      \
@@ -1510,18 +1511,18 @@ int run_pass(Ctx* c, int pass, int variant, const RhsSet& set, cpx<T>* work, con
 // larger than the cache gains nothing, so such sizes keep one launch per pass.
 constexpr long long kMallBytes = 256ll << 20;
 template <typename T>
-int xy_chunk(const Ctx* c, int nrhs) {
+int xy_chunk_rule(const Ctx* c, int nrhs) {
     const long long per = 3LL * c->n3 * c->n2 * c->L1 * (long long)sizeof(cpx<T>);
     if (per > kMallBytes) return nrhs;
     return (int)std::max(1LL, std::min<long long>(nrhs, kMallBytes / per));
 }
 
 // Au = u - Gconv(f) (subtract_from_u) or Au = Gconv(f), where f already sits in work.  The x and y passes run
-// per chunk of right-hand-side positions (xy_chunk), the z pass over all of them.
+// per chunk of right-hand-side positions (Ctx::xy_chunk, else xy_chunk_rule), the z pass over all of them.
 template <typename T>
 int fft_apply_passes(Ctx* c, const RhsSet& set, cpx<T>* work, const cpx<T>* u, cpx<T>* Au, bool subtract_from_u) {
     const int prec = sizeof(T) == 8 ? 0 : 1;
-    const int ch = xy_chunk<T>(c, set.n);
+    const int ch = c->xy_chunk[prec] > 0 ? std::min(c->xy_chunk[prec], set.n) : xy_chunk_rule<T>(c, set.n);
     const long long pos = 3LL * c->n3 * c->L2 * c->L1;   // work elements per position
     auto chunk = [&](int a) {
         RhsSet s_;
@@ -1547,7 +1548,9 @@ int fft_apply_passes(Ctx* c, const RhsSet& set, cpx<T>* work, const cpx<T>* u, c
 }
 
 // Time both kernel variants of every pass at the context's sizes (max_rhs right-hand sides, first
-// frequency) and keep the faster; the work buffer contents are scratch.
+// frequency) and keep the faster; then, over the five passes together, the strided passes' column tiles (256
+// or 128 bytes) and the right-hand sides per chunk of the x and y passes (the cache-size rule, 1, 2, 3 or all).
+// The work buffer contents are scratch.
 template <typename T>
 int autotune_passes(Ctx* c) {
     const int prec = sizeof(T) == 8 ? 0 : 1;
@@ -1558,32 +1561,68 @@ int autotune_passes(Ctx* c) {
     LS_HIP(hipEventCreate(&a));
     LS_HIP(hipEventCreate(&b));
     int rc_ = LS_OK;
+    // milliseconds of three runs of fn after one warm-up run
+    auto timed = [&](auto fn, float& ms) -> int {
+        int r = fn();
+        if (r) return r;
+        if (hipEventRecord(a, c->stream) != hipSuccess) return fail(LS_ERR_HIP, "autotune event");
+        for (int k = 0; k < 3 && r == LS_OK; ++k) r = fn();
+        if (r) return r;
+        if (hipEventRecord(b, c->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess)
+            return fail(LS_ERR_HIP, "autotune timing");
+        return LS_OK;
+    };
+    // the kernel variant of every pass
     for (int pass = 0; pass < 5 && rc_ == LS_OK; ++pass) {
         float best = 0.f;
         for (int variant = 0; variant < 2 && rc_ == LS_OK; ++variant) {
-            rc_ = run_pass<T>(c, pass, variant, set, work, out, out, false);  // warm-up
-            if (rc_) break;
-            if (hipEventRecord(a, c->stream) != hipSuccess) rc_ = fail(LS_ERR_HIP, "autotune event");
-            for (int k = 0; k < 3 && rc_ == LS_OK; ++k)
-                rc_ = run_pass<T>(c, pass, variant, set, work, out, out, false);
-            if (rc_) break;
             float ms = 0.f;
-            if (hipEventRecord(b, c->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
-                hipEventElapsedTime(&ms, a, b) != hipSuccess) {
-                rc_ = fail(LS_ERR_HIP, "autotune timing");
-                break;
-            }
-            if (variant == 0 || ms < best) {
+            rc_ = timed([&] { return run_pass<T>(c, pass, variant, set, work, out, out, false); }, ms);
+            if (rc_ == LS_OK && (variant == 0 || ms < best)) {
                 best = ms;
                 c->variant[prec][pass] = variant;
             }
         }
+    }
+    // the strided passes' column tiles, then the chunk of the x and y passes, over all five passes
+    auto passes = [&] { return fft_apply_passes<T>(c, set, work, out, out, false); };
+    if (rc_ == LS_OK) {
+        float ms1 = 0.f, ms0 = 0.f;
+        c->y_wide[prec] = 1;
+        rc_ = timed(passes, ms1);
+        if (rc_ == LS_OK) {
+            c->y_wide[prec] = 0;
+            rc_ = timed(passes, ms0);
+            c->y_wide[prec] = (rc_ == LS_OK && ms0 < ms1) ? 0 : 1;
+        }
+    }
+    if (rc_ == LS_OK) {
+        const int cands[] = {xy_chunk_rule<T>(c, set.n), 1, 2, 3, set.n};
+        float best = 0.f;
+        int pick = 0;
+        for (int i = 0; i < 5 && rc_ == LS_OK; ++i) {
+            const int ch = std::min(cands[i], set.n);
+            bool seen = false;
+            for (int k = 0; k < i; ++k) seen = seen || std::min(cands[k], set.n) == ch;
+            if (seen) continue;
+            c->xy_chunk[prec] = ch;
+            float ms = 0.f;
+            rc_ = timed(passes, ms);
+            if (rc_ == LS_OK && (pick == 0 || ms < best)) {
+                best = ms;
+                pick = ch;
+            }
+        }
+        c->xy_chunk[prec] = pick;
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return rc_;
 }
 
+template int xy_chunk_rule<double>(const Ctx*, int);
+template int xy_chunk_rule<float>(const Ctx*, int);
 template int autotune_passes<double>(Ctx*);
 template int autotune_passes<float>(Ctx*);
 

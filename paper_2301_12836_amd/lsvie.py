@@ -8,7 +8,7 @@ The module-level functions carry the C names (``ls_setup``, ``ls_apply``, ``ls_a
 ``ls_rhs_moment``, ``ls_rhs_force``, ``ls_solve``, ``ls_solve_multi``, ``ls_solve_moment``, ``ls_solve_force``,
 ``ls_solve_batch``, ``ls_strain``, ``ls_apply_T``, ``ls_convolve``, ``ls_solve_T``,
 ``ls_grad_contrast``, ``ls_grad``, ``ls_sample``, ``ls_synthesize``, ``ls_residual_history``, ``ls_profile``,
-``ls_profile_read``, ``ls_device_bytes``, ``ls_kernel_variants``, ``ls_destroy``); ``Context`` wraps
+``ls_profile_read``, ``ls_device_bytes``, ``ls_kernel_variants``, ``ls_kernel_schedule``, ``ls_destroy``); ``Context`` wraps
 them for convenience, and ``solve_batch`` wraps ``ls_solve_batch`` over several contexts.
 """
 
@@ -47,7 +47,7 @@ ERROR_NAMES = {LS_ERR_ARG: "LS_ERR_ARG", LS_ERR_OOM: "LS_ERR_OOM", LS_ERR_HIP: "
 EXPORTED = ("ls_setup", "ls_destroy", "ls_apply", "ls_apply_noalloc", "ls_apply_c64", "ls_rhs_moment", "ls_rhs_force", "ls_solve",
             "ls_solve_moment", "ls_solve_multi", "ls_solve_force", "ls_strain", "ls_set_contrast", "ls_precond_blocks", "ls_apply_T", "ls_convolve",
             "ls_solve_T", "ls_grad_contrast", "ls_grad", "ls_solve_batch", "ls_sample", "ls_synthesize", "ls_residual_history",
-            "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_contrast_format", "ls_last_error")
+            "ls_profile", "ls_profile_read", "ls_device_bytes", "ls_kernel_variants", "ls_kernel_schedule", "ls_contrast_format", "ls_last_error")
 
 
 class LsError(RuntimeError):
@@ -127,6 +127,7 @@ def load():
         "ls_profile_read": (I, [P, ctypes.c_char_p, ip, dp, ctypes.POINTER(ctypes.c_longlong), I]),
         "ls_device_bytes": (ctypes.c_longlong, [P]),
         "ls_kernel_variants": (I, [P, ip]),
+        "ls_kernel_schedule": (I, [P, ip]),
         "ls_contrast_format": (I, [P]),
         "ls_last_error": (ctypes.c_char_p, []),
     }
@@ -397,6 +398,12 @@ def ls_kernel_variants(ctx):
             for p, prec in enumerate(("c128", "c64"))}
 
 
+def ls_kernel_schedule(ctx):
+    v = (ctypes.c_int * 4)()
+    _check(load().ls_kernel_schedule(ctx, v))
+    return {prec: {"xy_chunk": v[p], "wide_y_tiles": bool(v[2 + p])} for p, prec in enumerate(("c128", "c64"))}
+
+
 def ls_device_bytes(ctx):
     return int(load().ls_device_bytes(ctx))
 
@@ -649,6 +656,10 @@ class Context:
     @property
     def kernel_variants(self):
         return ls_kernel_variants(self.handle)
+
+    @property
+    def kernel_schedule(self):
+        return ls_kernel_schedule(self.handle)
 
     @property
     def device_bytes(self):

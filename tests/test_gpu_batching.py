@@ -44,8 +44,10 @@ def test_autotuned_variants_keep_parity(tmp_path, monkeypatch):
     m = models.random_medium((24, 20, 18), seed=9, rel=0.1, aniso_background=True)
     ctx = lsvie.context_from_model(m, omegas=[W], precision="mixed", max_rhs=2, autotune=True)
     v = ctx.kernel_variants
-    print("variants", v, flush=True)
+    sched = ctx.kernel_schedule
+    print("variants", v, "schedule", sched, flush=True)
     assert set(v) == {"c128", "c64"} and all(len(x) == 5 for x in v.values())
+    assert all(1 <= x["xy_chunk"] <= 2 for x in sched.values())
     P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, W)
     u = np.stack([models.random_field(m.shape, s) for s in range(2)])
     got = ctx.apply(torch.from_numpy(u)).cpu().numpy()
@@ -107,14 +109,34 @@ def test_autotune_cache_is_written_and_used(tmp_path, monkeypatch):
     ctx.close()
     lines = cache.read_text().split("\n")
     key, *vals = lines[0].split()
-    assert len(vals) == 10 and set(vals) <= {"0", "1"} and key.startswith("v1:")
-    cache.write_text(lines[0] + "\n" + key + " 1 1 1 1 1 1 1 1 1 1\n")
+    # ten kernel variants, then per precision the x/y chunk (1 .. max_rhs) and the strided tile choice
+    assert len(vals) == 14 and set(vals[:10]) <= {"0", "1"} and key.startswith("v2:")
+    assert all(1 <= int(x) <= 2 for x in vals[10:12]) and set(vals[12:]) <= {"0", "1"}
+    cache.write_text(lines[0] + "\n" + key + " 1 1 1 1 1 1 1 1 1 1 1 1 0 0\n")
     ctx = lsvie.context_from_model(m, omegas=[W], precision="mixed", max_rhs=2, autotune=True)
     v = ctx.kernel_variants
     assert all(x == "stockham" for p in v.values() for x in p.values()), v
+    assert ctx.kernel_schedule == {p: {"xy_chunk": 1, "wide_y_tiles": False} for p in ("c128", "c64")}
     P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, W)
     u = models.random_field(m.shape, 3)
     assert rel(ctx.apply(torch.from_numpy(u)).cpu().numpy(), P.apply_fft(u)) < 1e-10
     assert rel(ctx.apply(torch.from_numpy(u).to(torch.complex64)).cpu().numpy(), P.apply_fft(u)) < 1e-5
     ctx.close()
     assert len(cache.read_text().strip().split("\n")) == 2   # the cached key was not tuned again
+    # on a grid whose y pass (length 64) can take 256-byte tiles, a register-kernel schedule with one-system
+    # chunks and 128-byte tiles gives bitwise the same applies as the default schedule (two-system chunks, wide
+    # tiles): the chunks and tiles regroup the same per-line transforms
+    m2 = models.random_medium((16, 32, 10), seed=23, rel=0.1)
+    t = lsvie.context_from_model(m2, omegas=[W], precision="mixed", max_rhs=2, autotune=True)
+    t.close()
+    key2 = cache.read_text().strip().split("\n")[-1].split()[0]
+    cache.write_text(key2 + " 0 0 0 0 0 0 0 0 0 0 1 1 0 0\n")
+    ctx = lsvie.context_from_model(m2, omegas=[W], precision="mixed", max_rhs=2, autotune=True)
+    ref = lsvie.context_from_model(m2, omegas=[W], precision="mixed", max_rhs=2)
+    assert ctx.kernel_schedule == {p: {"xy_chunk": 1, "wide_y_tiles": False} for p in ("c128", "c64")}
+    assert ref.kernel_schedule == {p: {"xy_chunk": 2, "wide_y_tiles": True} for p in ("c128", "c64")}
+    u2 = torch.from_numpy(np.stack([models.random_field(m2.shape, s) for s in (4, 5)]))
+    for dt in (torch.complex128, torch.complex64):
+        assert torch.equal(ctx.apply(u2.to(dt)), ref.apply(u2.to(dt)))
+    ctx.close()
+    ref.close()
