@@ -140,3 +140,26 @@ def test_autotune_cache_is_written_and_used(tmp_path, monkeypatch):
         assert torch.equal(ctx.apply(u2.to(dt)), ref.apply(u2.to(dt)))
     ctx.close()
     ref.close()
+
+
+def test_autotuned_schedule_at_128_cubed_keeps_parity(tmp_path, monkeypatch):
+    """At the benchmark's 128^3 grid, where the x and y passes run in cache-sized chunks, the autotuner's choice
+    of kernel variants, y tiles and chunk (six right-hand sides) keeps the full-field parity with the oracle's
+    FFT apply in both precisions."""
+    monkeypatch.setenv("LS_AUTOTUNE_CACHE", str(tmp_path / "autotune.txt"))
+    m = models.config3()
+    w = m.omegas[-1]
+    ctx = lsvie.context_from_model(m, omegas=[w], precision="mixed", max_rhs=6, autotune=True)
+    sched = ctx.kernel_schedule
+    print("variants", ctx.kernel_variants, "schedule", sched, flush=True)
+    assert all(1 <= x["xy_chunk"] <= 6 for x in sched.values())
+    u = np.stack([models.random_field(m.shape, s) for s in (61, 62, 63)])
+    ut = torch.from_numpy(u)
+    got = ctx.apply(ut).cpu().numpy()
+    got32 = ctx.apply(ut.to(torch.complex64)).cpu().numpy()
+    ctx.close()
+    P = op.Problem(m.shape, m.h, m.C0, m.rho0, m.dc21, m.drho, w)
+    P.table()
+    for r in range(3):
+        want = P.apply_fft(u[r])
+        assert rel(got[r], want) < 1e-10 and rel(got32[r], want) < 1e-5
